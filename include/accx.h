@@ -1,0 +1,197 @@
+/*
+ * libaccx: the data-parallel hot path of an OpenACC offload region on one
+ * AMD Instinct MI355X (gfx950), behind a plain C ABI.
+ *
+ * Paper: A. Lashgar, A. Majidi, A. Baniasadi, "IPMACC: Open Source OpenACC
+ * to CUDA/OpenCL Translator", arXiv 1412.1127.  The calls follow the paper's
+ * statement of the problem:
+ *
+ *   - data directive with copy / copyin / copyout / create clauses over
+ *     [start:n] subarrays, and the host-accelerator pointer exchange
+ *     (section 1.2 "OpenACC Model", section 1.3 and Listing 1a, and the
+ *     data-clause step of section 2.3);
+ *   - the `kernels` + `loop independent` matrix-multiplication loop nest of
+ *     the worked example, i and j parallel, l sequential (Listing 1a/1b,
+ *     section 1.3), for float and int operands;
+ *   - the `reduction(+)` clause lowering: a reduction across the threads of
+ *     a block, then across blocks (section 2.3, "Replacing the dummy OpenACC
+ *     kernels region calls"; SRAD paragraph of section 4.2).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an acc_status; nothing throws across this ABI.
+ *     acc_last_error_string() gives a thread-local message for the last
+ *     failing call on the calling thread.
+ *   - Element counts are int64_t; element types are 4 bytes (float, int32).
+ *   - Matrices are square, row-major, LEN*LEN, element (i, j) at i*LEN + j.
+ *   - int32 arithmetic wraps: results are exact modulo 2^32, read as two's
+ *     complement.
+ *   - float results are computed in float32 arithmetic (or on bf16 matrix
+ *     cores with a three-term split, see ACC_PREC_*) and are not bitwise
+ *     reproducible across kernels; each kernel is bitwise deterministic
+ *     run to run.
+ *   - Without a usable GPU every compute or memory call returns
+ *     ACC_ERR_NO_DEVICE; there is no host fallback.
+ */
+#ifndef ACCX_H
+#define ACCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define ACCX_API __attribute__((visibility("default")))
+#else
+#define ACCX_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ACC_OK = 0,
+    ACC_ERR_INVALID_ARG = -1,     /* bad pointer, size, kind, dtype or flag */
+    ACC_ERR_NOT_PRESENT = -2,     /* operand not inside a mapped host range */
+    ACC_ERR_ALREADY_PRESENT = -3, /* clause overlaps a mapped host range */
+    ACC_ERR_OUT_OF_MEMORY = -4,   /* HBM budget exceeded or allocation failed */
+    ACC_ERR_DEVICE = -5,          /* HIP runtime or kernel launch error */
+    ACC_ERR_NO_DEVICE = -6,       /* no gfx950 device, or acc_init not called */
+} acc_status;
+
+/* Data clauses (section 1.3): copy = copy in at region entry and out at exit;
+ * copyin = in only; copyout = out only; create = device allocation only. */
+typedef enum { ACC_COPY = 0, ACC_COPYIN = 1, ACC_COPYOUT = 2, ACC_CREATE = 3 } acc_clause_kind;
+
+typedef enum { ACC_FLOAT32 = 0, ACC_INT32 = 1 } acc_dtype;
+
+/* One data clause: host[start : start+n) in elements of `dtype` ("[start:n]
+ * means n elements from element start", section 1.3).  `host` is the base of
+ * the host array, owned by the caller, alive until acc_data_end. */
+typedef struct {
+    int32_t kind;  /* acc_clause_kind */
+    int32_t dtype; /* acc_dtype */
+    void *host;
+    int64_t start;
+    int64_t n;
+} acc_clause;
+
+typedef struct acc_region_s *acc_region; /* opaque */
+
+/* ---- flags for acc_loopnest_matmul / accx_matmul_dev -------------------- */
+/* kernel choice (low 4 bits) */
+#define ACC_KERNEL_AUTO 0x0u            /* tiled matrix-core kernel */
+#define ACC_KERNEL_PLAIN 0x1u           /* one thread per (i,j), j on lanes */
+#define ACC_KERNEL_PLAIN_LISTING1B 0x2u /* Listing 1b's mapping: i on x, 16x16 */
+#define ACC_KERNEL_TILED 0x3u           /* LDS-tiled matrix-core kernel */
+#define ACC_KERNEL_MASK 0xFu
+/* float precision on the tiled kernel (bits 4..7); ignored for int32 and the
+ * plain kernels.  x = hi + mid + lo, three bf16 terms per operand. */
+#define ACC_PREC_AUTO 0x00u   /* cheap split + sampled float64 error probe;
+                                 adds the missing products if needed */
+#define ACC_PREC_FULL6 0x10u  /* 6 bf16 products: all pairs with p+q <= 2 */
+#define ACC_PREC_CHEAP3 0x20u /* 3 bf16 products: pairs with p+q <= 1 */
+#define ACC_PREC_MASK 0xF0u
+/* int32 on the tiled kernel: limb count (bits 8..11); 0 = probe max |x|. */
+#define ACC_LIMBS_SHIFT 8
+#define ACC_LIMBS_MASK 0xF00u
+/* asynchronous completion (acc_reduce_sum): *inout valid after acc_wait */
+#define ACC_ASYNC 0x1000u
+
+/* ---- flags for acc_reduce_sum / accx_reduce_sum_dev --------------------- */
+#define ACC_REDUCE_FAST 0x0u  /* single pass, last-block-done final stage */
+#define ACC_REDUCE_PLAIN 0x1u /* one element per thread + block tree, then a
+                                 second one-block launch over the partials */
+
+/* ---- library ------------------------------------------------------------ */
+
+/* Select `device` (HIP ordinal) and set the HBM budget for region data and
+ * library workspaces (0 = no budget beyond the device).  Must precede every
+ * other call but the string and version calls.  May be called again after
+ * acc_shutdown.  Errors: NO_DEVICE, INVALID_ARG (device < 0). */
+ACCX_API acc_status acc_init(int device, uint64_t hbm_budget_bytes);
+
+/* Free every region still open (no copyout) and all library memory. */
+ACCX_API acc_status acc_shutdown(void);
+
+/* Bytes currently charged against the budget (region arrays + workspaces). */
+ACCX_API acc_status acc_budget_used(uint64_t *bytes_out);
+
+/* ---- data regions (section 1.3, data-clause step of section 2.3) -------- */
+
+/* Open a data region: allocate a device copy of each clause's host range and,
+ * for copy and copyin, copy it host->device on the region's stream.
+ * `hip_stream` = NULL: the region creates its own stream; otherwise the
+ * caller's hipStream_t, which must outlive the region.  Clause ranges must
+ * not overlap one another or any mapped range (ALREADY_PRESENT).  n = 0 is
+ * allowed and maps nothing.  On any error nothing stays mapped.
+ * Errors: INVALID_ARG, ALREADY_PRESENT, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status acc_data_begin(const acc_clause *clauses, int nclauses, void *hip_stream,
+                          acc_region *region_out);
+
+/* Close a region: wait for its stream, copy device->host for copy and
+ * copyout, free its device memory and unmap its ranges.  Always frees, also
+ * after an error; returns the first error the region met. */
+ACCX_API acc_status acc_data_end(acc_region region);
+
+/* Block until all work enqueued on the region has finished. */
+ACCX_API acc_status acc_wait(acc_region region);
+
+/* Host-accelerator pointer exchange (section 2.3): the device address of the
+ * mapped host address `host`.  Errors: NOT_PRESENT. */
+ACCX_API acc_status acc_deviceptr(const void *host, void **device_out);
+
+/* ---- the loop nest (Listing 1a, section 1.3) ---------------------------- */
+
+/* c[i*len+j] = sum over l of a[i*len+l] * b[l*len+j], for 0 <= i, j < len:
+ * i and j parallel, l sequential.  a, b, c are HOST addresses, each of whose
+ * len*len elements must lie inside one mapped range of dtype `t` (the kernel
+ * reads and writes the device copies; host c changes at acc_data_end, for
+ * copy/copyout).  Enqueued on the region's stream.  1 <= len <= 65536.
+ * Errors: INVALID_ARG, NOT_PRESENT, OUT_OF_MEMORY (workspace), DEVICE. */
+ACCX_API acc_status acc_loopnest_matmul(acc_region region, acc_dtype t, const void *a, const void *b,
+                               void *c, int64_t len, uint32_t flags);
+
+/* ---- reduction(+) (section 2.3; SRAD paragraph of section 4.2) ---------- */
+
+/* *inout = *inout + sum of x[0..n), x a HOST address whose n elements lie in
+ * one mapped range of dtype `t`; *inout is a host float or int32.  n = 0
+ * leaves *inout unchanged.  Synchronous unless ACC_ASYNC, then *inout is
+ * written by the time acc_wait / acc_data_end returns.
+ * Errors: INVALID_ARG, NOT_PRESENT, DEVICE. */
+ACCX_API acc_status acc_reduce_sum(acc_region region, acc_dtype t, const void *x, int64_t n,
+                          void *inout_result, uint32_t flags);
+
+/* ---- device-pointer entries (memory owned by the caller, e.g. torch) ----- */
+
+/* Workspace bytes accx_matmul_dev needs for (t, len, flags); 0 for the plain
+ * kernels.  Errors: INVALID_ARG. */
+ACCX_API acc_status accx_matmul_workspace_size(acc_dtype t, int64_t len, uint32_t flags, size_t *bytes_out);
+
+/* The loop nest on device pointers dA, dB, dC (len*len elements each, 4-byte
+ * aligned, dC not overlapping dA or dB), enqueued on `hip_stream` (NULL = the
+ * null stream).  dWork: device workspace of at least the size above, or NULL
+ * to use a library-owned workspace of that stream (grown on demand).
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_matmul_dev(acc_dtype t, const void *dA, const void *dB, void *dC, int64_t len,
+                           uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
+
+/* Workspace bytes accx_reduce_sum_dev needs for (t, n, flags). */
+ACCX_API acc_status accx_reduce_workspace_size(acc_dtype t, int64_t n, uint32_t flags, size_t *bytes_out);
+
+/* dResult (device scalar of type t) = init + sum of dX[0..n), enqueued on
+ * `hip_stream`.  `init` points to a HOST float or int32.  dWork as above
+ * (NULL: library-owned per-stream workspace); a workspace passed in must be
+ * zero-filled before its first use, and the kernel leaves it so.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const void *init, void *dResult,
+                               uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
+
+/* ---- strings ------------------------------------------------------------ */
+ACCX_API const char *acc_status_string(acc_status s);
+ACCX_API const char *acc_last_error_string(void);
+ACCX_API const char *accx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACCX_H */

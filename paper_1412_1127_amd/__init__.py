@@ -1,0 +1,218 @@
+"""Python binding of libaccx (include/accx.h): argument marshalling only.
+
+Every step of the hot path runs in the HIP kernels of ``libaccx.so``; this
+module only converts Python arguments to the C ABI and raises ``AccxError`` on
+a failing status.  The names match the C entry points.
+
+torch is imported first so that libaccx binds to the same HIP runtime that
+torch loaded: device memory and streams handed over from torch tensors are
+then valid inside the library.  There is no fallback: if ``libaccx.so`` has
+not been built, importing this package fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (HIP runtime shared with libaccx)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaccx.so")
+
+# ---- constants (mirror include/accx.h) ------------------------------------
+ACC_OK = 0
+ACC_ERR_INVALID_ARG = -1
+ACC_ERR_NOT_PRESENT = -2
+ACC_ERR_ALREADY_PRESENT = -3
+ACC_ERR_OUT_OF_MEMORY = -4
+ACC_ERR_DEVICE = -5
+ACC_ERR_NO_DEVICE = -6
+
+ACC_COPY, ACC_COPYIN, ACC_COPYOUT, ACC_CREATE = 0, 1, 2, 3
+ACC_FLOAT32, ACC_INT32 = 0, 1
+
+ACC_KERNEL_AUTO = 0x0
+ACC_KERNEL_PLAIN = 0x1
+ACC_KERNEL_PLAIN_LISTING1B = 0x2
+ACC_KERNEL_TILED = 0x3
+ACC_PREC_AUTO = 0x00
+ACC_PREC_FULL6 = 0x10
+ACC_PREC_CHEAP3 = 0x20
+ACC_LIMBS_SHIFT = 8
+ACC_ASYNC = 0x1000
+ACC_REDUCE_FAST = 0x0
+ACC_REDUCE_PLAIN = 0x1
+
+
+def ACC_LIMBS(n: int) -> int:
+    return (int(n) & 0xF) << ACC_LIMBS_SHIFT
+
+
+class AccxError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__("%s: %s (%s)" % (where, status_string(status), detail))
+        self.status = status
+
+
+class acc_clause(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("host", ctypes.c_void_p),
+                ("start", ctypes.c_int64), ("n", ctypes.c_int64)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libaccx.so is not built (%s); run `python -m paper_1412_1127_amd.build` "
+                      "or __graft_entry__.build()" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_i32, _i64, _u32, _u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+_vp, _sz = ctypes.c_void_p, ctypes.c_size_t
+
+# name -> argtypes (every entry point returns acc_status unless listed below)
+_SIGS = {
+    "acc_init": [ctypes.c_int, _u64],
+    "acc_shutdown": [],
+    "acc_budget_used": [ctypes.POINTER(_u64)],
+    "acc_data_begin": [ctypes.POINTER(acc_clause), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
+    "acc_data_end": [_vp],
+    "acc_wait": [_vp],
+    "acc_deviceptr": [_vp, ctypes.POINTER(_vp)],
+    "acc_loopnest_matmul": [_vp, ctypes.c_int, _vp, _vp, _vp, _i64, _u32],
+    "acc_reduce_sum": [_vp, ctypes.c_int, _vp, _i64, _vp, _u32],
+    "accx_matmul_workspace_size": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_sz)],
+    "accx_matmul_dev": [ctypes.c_int, _vp, _vp, _vp, _i64, _u32, _vp, _sz, _vp],
+    "accx_reduce_workspace_size": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_sz)],
+    "accx_reduce_sum_dev": [ctypes.c_int, _vp, _i64, _vp, _vp, _u32, _vp, _sz, _vp],
+}
+_STRINGS = {"acc_status_string": [ctypes.c_int], "acc_last_error_string": [], "accx_version": []}
+
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+for _name, _args in _STRINGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_char_p
+
+EXPORTED = tuple(_SIGS) + tuple(_STRINGS)
+
+
+def status_string(s: int) -> str:
+    return _lib.acc_status_string(int(s)).decode()
+
+
+def last_error_string() -> str:
+    return _lib.acc_last_error_string().decode()
+
+
+def version() -> str:
+    return _lib.accx_version().decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != ACC_OK:
+        raise AccxError(status, where, last_error_string())
+
+
+def _addr(p) -> int | None:
+    """Address of a numpy array, torch tensor, ctypes object or plain int."""
+    if p is None:
+        return None
+    if isinstance(p, int):
+        return p
+    if hasattr(p, "data_ptr"):
+        return int(p.data_ptr())
+    if hasattr(p, "ctypes"):
+        return int(p.ctypes.data)
+    return ctypes.addressof(p)
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+# ---- entry points ----------------------------------------------------------
+
+def acc_init(device: int = 0, hbm_budget_bytes: int = 0) -> None:
+    _check(_lib.acc_init(int(device), int(hbm_budget_bytes)), "acc_init")
+
+
+def acc_shutdown() -> None:
+    _check(_lib.acc_shutdown(), "acc_shutdown")
+
+
+def acc_budget_used() -> int:
+    v = _u64(0)
+    _check(_lib.acc_budget_used(ctypes.byref(v)), "acc_budget_used")
+    return int(v.value)
+
+
+def clause(kind: int, dtype: int, host, start: int = 0, n: int | None = None) -> acc_clause:
+    """One data clause host[start:n]; n defaults to the array's size."""
+    if n is None:
+        n = int(host.size) - int(start)
+    return acc_clause(int(kind), int(dtype), _addr(host), int(start), int(n))
+
+
+def acc_data_begin(clauses, stream=None) -> int:
+    arr = (acc_clause * max(1, len(clauses)))(*clauses)
+    out = _vp(0)
+    _check(_lib.acc_data_begin(arr, len(clauses), _stream(stream), ctypes.byref(out)), "acc_data_begin")
+    return int(out.value)
+
+
+def acc_data_end(region: int) -> None:
+    _check(_lib.acc_data_end(region), "acc_data_end")
+
+
+def acc_wait(region: int) -> None:
+    _check(_lib.acc_wait(region), "acc_wait")
+
+
+def acc_deviceptr(host) -> int:
+    out = _vp(0)
+    _check(_lib.acc_deviceptr(_addr(host), ctypes.byref(out)), "acc_deviceptr")
+    return int(out.value or 0)
+
+
+def acc_loopnest_matmul(region: int, dtype: int, a, b, c, length: int, flags: int = 0) -> None:
+    _check(_lib.acc_loopnest_matmul(region, int(dtype), _addr(a), _addr(b), _addr(c), int(length), int(flags)),
+           "acc_loopnest_matmul")
+
+
+def acc_reduce_sum(region: int, dtype: int, x, n: int, inout, flags: int = 0) -> None:
+    """inout: a one-element numpy array (float32 or int32) or ctypes scalar, updated in place."""
+    _check(_lib.acc_reduce_sum(region, int(dtype), _addr(x), int(n), _addr(inout), int(flags)), "acc_reduce_sum")
+
+
+def accx_matmul_workspace_size(dtype: int, length: int, flags: int = 0) -> int:
+    v = _sz(0)
+    _check(_lib.accx_matmul_workspace_size(int(dtype), int(length), int(flags), ctypes.byref(v)),
+           "accx_matmul_workspace_size")
+    return int(v.value)
+
+
+def accx_matmul_dev(dtype: int, dA, dB, dC, length: int, flags: int = 0, work=None, work_bytes: int = 0,
+                    stream=None) -> None:
+    _check(_lib.accx_matmul_dev(int(dtype), _addr(dA), _addr(dB), _addr(dC), int(length), int(flags),
+                                _addr(work), int(work_bytes), _stream(stream)), "accx_matmul_dev")
+
+
+def accx_reduce_workspace_size(dtype: int, n: int, flags: int = 0) -> int:
+    v = _sz(0)
+    _check(_lib.accx_reduce_workspace_size(int(dtype), int(n), int(flags), ctypes.byref(v)),
+           "accx_reduce_workspace_size")
+    return int(v.value)
+
+
+def accx_reduce_sum_dev(dtype: int, dX, n: int, init, dResult, flags: int = 0, work=None, work_bytes: int = 0,
+                        stream=None) -> None:
+    """init: a Python number (marshalled to a host float / int32)."""
+    iv = ctypes.c_float(float(init)) if dtype == ACC_FLOAT32 else ctypes.c_int32(int(init))
+    _check(_lib.accx_reduce_sum_dev(int(dtype), _addr(dX), int(n), ctypes.byref(iv), _addr(dResult), int(flags),
+                                    _addr(work), int(work_bytes), _stream(stream)), "accx_reduce_sum_dev")

@@ -1,0 +1,96 @@
+// The loop nest of Listing 1a (section 1.3) as a translator emits it: one
+// lightweight thread per output element (i, j), the l loop run sequentially
+// inside the thread, no data shared between threads ("output
+// parallelization", the Matrix Multiplication paragraph of section 4.2).
+//
+// Two thread mappings:
+//  - gang/vector (default): j on the 64 lanes of a wavefront, i on the
+//    workgroup's y dimension and the grid.  Loads of b and stores of c are
+//    coalesced along j; a[i][l] is the same address for the whole wavefront.
+//  - Listing 1b's mapping: i = threadIdx.x + blockIdx.x*16,
+//    j = threadIdx.y + blockIdx.y*16, 16x16 blocks.  Neighbouring lanes then
+//    walk different rows of a (stride LEN) and store c with stride LEN.
+// Both guard i, j < LEN, so any LEN >= 1 is accepted (the listing's grid of
+// LEN/16 blocks assumes 16 | LEN and has no guard).
+//
+// float: `sum` is float and each step is one fused multiply-add (the listing
+// declares `float sum`; the contraction is the compiler's default).
+// int: unsigned 32-bit multiply-add, i.e. wraparound modulo 2^32.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace accx {
+namespace {
+
+template <typename T> struct Mac;
+template <> struct Mac<float> {
+    using Acc = float;
+    __device__ static inline float step(float s, float x, float y) { return __builtin_fmaf(x, y, s); }
+};
+template <> struct Mac<int32_t> {
+    using Acc = uint32_t;
+    __device__ static inline uint32_t step(uint32_t s, int32_t x, int32_t y)
+    {
+        return s + (uint32_t)x * (uint32_t)y;
+    }
+};
+
+constexpr int GV_X = 64;  // j lanes per wavefront
+constexpr int GV_Y = 4;   // rows i per workgroup (one wavefront each)
+
+template <typename T>
+__global__ __launch_bounds__(GV_X *GV_Y) void matmul_plain_gv(const T *__restrict__ a, const T *__restrict__ b,
+                                                              T *__restrict__ c, int64_t len)
+{
+    const int64_t j = (int64_t)blockIdx.x * GV_X + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.y * GV_Y + threadIdx.y;
+    if (i >= len || j >= len) return;
+    const T *arow = a + i * len;
+    const T *bcol = b + j;
+    typename Mac<T>::Acc sum = 0;
+    for (int64_t l = 0; l < len; ++l) sum = Mac<T>::step(sum, arow[l], bcol[l * len]);
+    c[i * len + j] = (T)sum;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void matmul_plain_listing1b(const T *__restrict__ a, const T *__restrict__ b,
+                                                              T *__restrict__ c, int64_t len)
+{
+    const int64_t i = (int64_t)threadIdx.x + (int64_t)blockIdx.x * 16;
+    const int64_t j = (int64_t)threadIdx.y + (int64_t)blockIdx.y * 16;
+    if (i >= len || j >= len) return;
+    typename Mac<T>::Acc sum = 0;
+    for (int64_t l = 0; l < len; ++l) sum = Mac<T>::step(sum, a[i * len + l], b[l * len + j]);
+    c[i * len + j] = (T)sum;
+}
+
+template <typename T>
+hipError_t launch(const T *a, const T *b, T *c, int64_t len, bool listing1b, hipStream_t s)
+{
+    if (len <= 0) return hipSuccess;
+    if (listing1b) {
+        const dim3 grid((unsigned)((len + 15) / 16), (unsigned)((len + 15) / 16));
+        hipLaunchKernelGGL(matmul_plain_listing1b<T>, grid, dim3(16, 16), 0, s, a, b, c, len);
+    } else {
+        const dim3 grid((unsigned)((len + GV_X - 1) / GV_X), (unsigned)((len + GV_Y - 1) / GV_Y));
+        hipLaunchKernelGGL(matmul_plain_gv<T>, grid, dim3(GV_X, GV_Y), 0, s, a, b, c, len);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_matmul_plain_f32(const float *a, const float *b, float *c, int64_t len, bool listing1b,
+                                   hipStream_t s)
+{
+    return launch<float>(a, b, c, len, listing1b, s);
+}
+
+hipError_t launch_matmul_plain_i32(const int32_t *a, const int32_t *b, int32_t *c, int64_t len, bool listing1b,
+                                   hipStream_t s)
+{
+    return launch<int32_t>(a, b, c, len, listing1b, s);
+}
+
+}  // namespace accx

@@ -1,0 +1,765 @@
+// libaccx runtime: the C ABI of include/accx.h.
+//
+// Holds the present table (mapped host range -> device copy), the data
+// regions with their streams, the HBM budget, library-owned workspaces and
+// the dispatch from the ABI calls to the kernels.  The data-management part
+// follows the paper's clause semantics (section 1.3: copy/copyin/copyout/
+// create over [start:n]; section 2.3: the data functions replace the dummy
+// data-clause calls with "host-accelerator pointer exchange, data copy in/out
+// to/from accelerator, and memory allocation").
+//
+// Failure handling: no C++ exception crosses the ABI; every entry point
+// returns an acc_status and leaves a thread-local message.  A device error
+// inside a region poisons it: later ops on it fail fast, acc_data_end still
+// frees everything and returns the first error.  For tests, ACCX_FAULT =
+// "alloc:N", "copy:N" or "launch:N" makes the N-th such call (counted from
+// acc_init) fail on the host, before any HIP call is made.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/accx.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string t_last_error;
+
+acc_status fail(acc_status s, const std::string &msg)
+{
+    t_last_error = msg;
+    return s;
+}
+
+acc_status fail_hip(hipError_t e, const char *what)
+{
+    return fail(ACC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Fault {
+    int alloc_at = 0, copy_at = 0, launch_at = 0;
+    int allocs = 0, copies = 0, launches = 0;
+};
+
+struct Entry {
+    uintptr_t hbeg = 0, hend = 0;  // host byte range [hbeg, hend)
+    void *dev = nullptr;
+    int kind = 0, dtype = 0;
+    acc_region_s *owner = nullptr;
+};
+
+struct Pending {  // an asynchronous reduction result waiting for acc_wait
+    void *host_dst;
+    int slot;
+};
+
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct acc_region_s {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<uintptr_t> keys;  // present-table keys owned by this region
+    acc_status err = ACC_OK;
+    std::string err_msg;
+    Workspace mm_work;            // matmul workspace
+    Workspace red_work;           // reduction workspace (zero-filled ticket)
+    Workspace red_plain_work;     // plain reduction partials
+    void *dres = nullptr;         // device result slots (4 bytes each)
+    uint32_t *hres = nullptr;     // pinned host staging for the slots
+    int nslots = 0, used_slots = 0;
+    std::vector<Pending> pending;
+};
+
+namespace {
+
+constexpr int kMaxSlots = 256;
+
+struct State {
+    std::recursive_mutex mu;
+    bool init = false;
+    int device = -1;
+    uint64_t budget = 0;  // 0 = unlimited
+    uint64_t used = 0;
+    std::map<uintptr_t, Entry> present;  // key = hbeg
+    std::set<acc_region_s *> regions;
+    std::map<hipStream_t, Workspace> mm_ws, red_ws, red_plain_ws;  // device-pointer entries
+    Fault fault;
+};
+
+State &S()
+{
+    static State *s = new State();  // never destroyed: safe at process exit
+    return *s;
+}
+
+bool fault_hit(int &counter, int at)
+{
+    ++counter;
+    return at > 0 && counter == at;
+}
+
+void parse_fault(Fault &f)
+{
+    f = Fault();
+    const char *env = std::getenv("ACCX_FAULT");
+    if (!env) return;
+    std::string s(env);
+    const size_t c = s.find(':');
+    if (c == std::string::npos) return;
+    const std::string kind = s.substr(0, c);
+    const int n = std::atoi(s.c_str() + c + 1);
+    if (kind == "alloc") f.alloc_at = n;
+    if (kind == "copy") f.copy_at = n;
+    if (kind == "launch") f.launch_at = n;
+}
+
+size_t elem_bytes(int) { return 4; }
+
+bool valid_dtype(int t) { return t == ACC_FLOAT32 || t == ACC_INT32; }
+
+// Device allocation charged against the budget.
+acc_status dev_alloc(void **p, size_t bytes)
+{
+    State &st = S();
+    *p = nullptr;
+    if (bytes == 0) return ACC_OK;
+    if (st.budget && st.used + bytes > st.budget)
+        return fail(ACC_ERR_OUT_OF_MEMORY, "HBM budget exceeded: " + std::to_string(st.used) + " used + " +
+                                               std::to_string(bytes) + " requested > " +
+                                               std::to_string(st.budget));
+    if (fault_hit(st.fault.allocs, st.fault.alloc_at))
+        return fail(ACC_ERR_OUT_OF_MEMORY, "injected allocation fault (ACCX_FAULT)");
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(ACC_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    st.used += bytes;
+    return ACC_OK;
+}
+
+void dev_free(void *p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    State &st = S();
+    st.used = st.used >= bytes ? st.used - bytes : 0;
+}
+
+acc_status ws_reserve(Workspace &w, size_t bytes, bool zero, hipStream_t stream)
+{
+    if (w.bytes >= bytes && w.ptr) return ACC_OK;
+    if (w.ptr) {
+        // the old buffer may still be in use by enqueued work
+        const hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+        dev_free(w.ptr, w.bytes);
+        w = Workspace();
+    }
+    void *p = nullptr;
+    acc_status s = dev_alloc(&p, bytes);
+    if (s != ACC_OK) return s;
+    if (zero) {
+        hipError_t e = hipMemsetAsync(p, 0, bytes, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            dev_free(p, bytes);
+            return fail_hip(e, "hipMemsetAsync");
+        }
+    }
+    w.ptr = p;
+    w.bytes = bytes;
+    return ACC_OK;
+}
+
+void ws_release(Workspace &w)
+{
+    dev_free(w.ptr, w.bytes);
+    w = Workspace();
+}
+
+// Entry whose range holds [p, p + bytes), or nullptr.
+Entry *lookup(const void *p, size_t bytes)
+{
+    State &st = S();
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    auto it = st.present.upper_bound(a);
+    if (it == st.present.begin()) return nullptr;
+    --it;
+    Entry &e = it->second;
+    if (a < e.hbeg || a + bytes > e.hend || a + bytes < a) return nullptr;
+    return &e;
+}
+
+bool overlaps_present(uintptr_t b, uintptr_t e)
+{
+    State &st = S();
+    auto it = st.present.lower_bound(b);
+    if (it != st.present.end() && it->second.hbeg < e) return true;
+    if (it != st.present.begin()) {
+        --it;
+        if (it->second.hend > b) return true;
+    }
+    return false;
+}
+
+acc_status check_ready()
+{
+    if (!S().init) return fail(ACC_ERR_NO_DEVICE, "acc_init has not been called (or failed)");
+    return ACC_OK;
+}
+
+acc_status poison(acc_region_s *r, acc_status s)
+{
+    if (r->err == ACC_OK) {
+        r->err = s;
+        r->err_msg = t_last_error;
+    }
+    return s;
+}
+
+// Device address for `bytes` at host address p, mapped with dtype t.
+acc_status resolve(const void *p, size_t bytes, int t, const char *what, void **dev)
+{
+    if (!p) return fail(ACC_ERR_INVALID_ARG, std::string(what) + " is NULL");
+    Entry *e = lookup(p, bytes);
+    if (!e)
+        return fail(ACC_ERR_NOT_PRESENT,
+                    std::string(what) + " is not inside a mapped host range (or extends past its end)");
+    if (e->dtype != t) return fail(ACC_ERR_INVALID_ARG, std::string(what) + " is mapped with another dtype");
+    *dev = static_cast<char *>(e->dev) + (reinterpret_cast<uintptr_t>(p) - e->hbeg);
+    return ACC_OK;
+}
+
+acc_status launch_fault()
+{
+    State &st = S();
+    if (fault_hit(st.fault.launches, st.fault.launch_at))
+        return fail(ACC_ERR_DEVICE, "injected launch fault (ACCX_FAULT)");
+    return ACC_OK;
+}
+
+acc_status check_launch(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return fail_hip(e, what);
+    return ACC_OK;
+}
+
+// ---- matmul dispatch ------------------------------------------------------
+
+acc_status validate_matmul(int t, int64_t len, uint32_t flags)
+{
+    if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
+    if (len < 1 || len > 65536) return fail(ACC_ERR_INVALID_ARG, "len must be in [1, 65536]");
+    const uint32_t known = ACC_KERNEL_MASK | ACC_PREC_MASK | ACC_LIMBS_MASK | ACC_ASYNC;
+    if (flags & ~known) return fail(ACC_ERR_INVALID_ARG, "unknown flag bits");
+    const uint32_t k = flags & ACC_KERNEL_MASK;
+    if (k > ACC_KERNEL_TILED) return fail(ACC_ERR_INVALID_ARG, "unknown kernel selector");
+    const uint32_t p = flags & ACC_PREC_MASK;
+    if (p != ACC_PREC_AUTO && p != ACC_PREC_FULL6 && p != ACC_PREC_CHEAP3)
+        return fail(ACC_ERR_INVALID_ARG, "unknown precision selector");
+    const uint32_t nl = (flags & ACC_LIMBS_MASK) >> ACC_LIMBS_SHIFT;
+    if (nl > 4) return fail(ACC_ERR_INVALID_ARG, "limb count must be 0 (probe) or 1..4");
+    return ACC_OK;
+}
+
+bool is_plain(uint32_t flags)
+{
+    const uint32_t k = flags & ACC_KERNEL_MASK;
+    return k == ACC_KERNEL_PLAIN || k == ACC_KERNEL_PLAIN_LISTING1B;
+}
+
+size_t matmul_ws_bytes(int t, int64_t len, uint32_t flags)
+{
+    (void)t;
+    (void)len;
+    if (is_plain(flags)) return 0;
+    return 0;
+}
+
+acc_status run_matmul(int t, const void *a, const void *b, void *c, int64_t len, uint32_t flags, void *work,
+                      size_t work_bytes, hipStream_t s)
+{
+    (void)work;
+    (void)work_bytes;
+    acc_status st = launch_fault();
+    if (st != ACC_OK) return st;
+    const uint32_t k = flags & ACC_KERNEL_MASK;
+    if (k == ACC_KERNEL_PLAIN || k == ACC_KERNEL_PLAIN_LISTING1B) {
+        const bool l1b = (k == ACC_KERNEL_PLAIN_LISTING1B);
+        hipError_t e = (t == ACC_FLOAT32)
+                           ? accx::launch_matmul_plain_f32(static_cast<const float *>(a),
+                                                           static_cast<const float *>(b), static_cast<float *>(c),
+                                                           len, l1b, s)
+                           : accx::launch_matmul_plain_i32(static_cast<const int32_t *>(a),
+                                                           static_cast<const int32_t *>(b),
+                                                           static_cast<int32_t *>(c), len, l1b, s);
+        return check_launch(e, "matmul (plain) launch");
+    }
+    return fail(ACC_ERR_INVALID_ARG, "the tiled matrix-core kernel is not available in this build");
+}
+
+// ---- reduction dispatch ---------------------------------------------------
+
+acc_status validate_reduce(int t, int64_t n, uint32_t flags)
+{
+    if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
+    if (n < 0) return fail(ACC_ERR_INVALID_ARG, "n must be >= 0");
+    if (flags & ~(ACC_REDUCE_PLAIN | ACC_ASYNC)) return fail(ACC_ERR_INVALID_ARG, "unknown flag bits");
+    return ACC_OK;
+}
+
+size_t reduce_ws_bytes(int64_t n, uint32_t flags)
+{
+    return (flags & ACC_REDUCE_PLAIN) ? accx::reduce_plain_workspace_bytes(n) : accx::reduce_fast_workspace_bytes(n);
+}
+
+acc_status run_reduce(int t, const void *x, int64_t n, const void *init, void *dres, uint32_t flags, void *work,
+                      hipStream_t s)
+{
+    acc_status st = launch_fault();
+    if (st != ACC_OK) return st;
+    const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
+    hipError_t e;
+    if (t == ACC_FLOAT32) {
+        float iv;
+        std::memcpy(&iv, init, 4);
+        e = accx::launch_reduce_f32(static_cast<const float *>(x), n, iv, static_cast<float *>(dres), work, plain, s);
+    } else {
+        int32_t iv;
+        std::memcpy(&iv, init, 4);
+        e = accx::launch_reduce_i32(static_cast<const int32_t *>(x), n, iv, static_cast<int32_t *>(dres), work,
+                                    plain, s);
+    }
+    return check_launch(e, "reduction launch");
+}
+
+void free_region(acc_region_s *r)
+{
+    State &st = S();
+    for (uintptr_t k : r->keys) {
+        auto it = st.present.find(k);
+        if (it == st.present.end()) continue;
+        dev_free(it->second.dev, it->second.hend - it->second.hbeg);
+        st.present.erase(it);
+    }
+    r->keys.clear();
+    ws_release(r->mm_work);
+    ws_release(r->red_work);
+    ws_release(r->red_plain_work);
+    if (r->dres) dev_free(r->dres, (size_t)r->nslots * 4);
+    if (r->hres) (void)hipHostFree(r->hres);
+    r->dres = nullptr;
+    r->hres = nullptr;
+    if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
+    r->stream = nullptr;
+}
+
+acc_status finish_pending(acc_region_s *r)
+{
+    if (r->pending.empty()) {
+        r->used_slots = 0;
+        return ACC_OK;
+    }
+    for (const Pending &p : r->pending) std::memcpy(p.host_dst, r->hres + p.slot, 4);
+    r->pending.clear();
+    r->used_slots = 0;
+    return ACC_OK;
+}
+
+acc_status wait_region(acc_region_s *r)
+{
+    const hipError_t e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return poison(r, fail_hip(e, "hipStreamSynchronize"));
+    return finish_pending(r);
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+acc_status acc_init(int device, uint64_t hbm_budget_bytes)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (device < 0) return fail(ACC_ERR_INVALID_ARG, "device must be >= 0");
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) {
+        (void)hipGetLastError();
+        return fail(ACC_ERR_NO_DEVICE, "no HIP device visible");
+    }
+    if (device >= count) return fail(ACC_ERR_NO_DEVICE, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(ACC_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", libaccx is built for gfx950");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    st.init = true;
+    st.device = device;
+    st.budget = hbm_budget_bytes;
+    parse_fault(st.fault);
+    return ACC_OK;
+}
+
+acc_status acc_shutdown(void)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!st.init) return ACC_OK;
+    (void)hipDeviceSynchronize();
+    for (acc_region_s *r : st.regions) {
+        free_region(r);
+        delete r;
+    }
+    st.regions.clear();
+    for (auto *m : {&st.mm_ws, &st.red_ws, &st.red_plain_ws}) {
+        for (auto &kv : *m) ws_release(kv.second);
+        m->clear();
+    }
+    st.present.clear();
+    st.used = 0;
+    st.init = false;
+    return ACC_OK;
+}
+
+acc_status acc_budget_used(uint64_t *bytes_out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
+    *bytes_out = st.used;
+    return ACC_OK;
+}
+
+acc_status acc_data_begin(const acc_clause *cl, int ncl, void *hip_stream, acc_region *out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!out) return fail(ACC_ERR_INVALID_ARG, "region_out is NULL");
+    *out = nullptr;
+    if (ncl < 0 || (ncl > 0 && !cl)) return fail(ACC_ERR_INVALID_ARG, "bad clause list");
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+
+    // Validate every clause before touching the device.
+    std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+    uint64_t total = 0;
+    for (int k = 0; k < ncl; ++k) {
+        const acc_clause &c = cl[k];
+        if (c.kind < ACC_COPY || c.kind > ACC_CREATE) return fail(ACC_ERR_INVALID_ARG, "unknown clause kind");
+        if (!valid_dtype(c.dtype)) return fail(ACC_ERR_INVALID_ARG, "unknown clause dtype");
+        if (c.start < 0 || c.n < 0) return fail(ACC_ERR_INVALID_ARG, "clause start and n must be >= 0");
+        if (c.n == 0) continue;
+        if (!c.host) return fail(ACC_ERR_INVALID_ARG, "clause host pointer is NULL");
+        if (c.n > (int64_t)(1ll << 40)) return fail(ACC_ERR_INVALID_ARG, "clause too large");
+        const uintptr_t b = reinterpret_cast<uintptr_t>(c.host) + (uintptr_t)c.start * elem_bytes(c.dtype);
+        const uintptr_t e = b + (uintptr_t)c.n * elem_bytes(c.dtype);
+        if (overlaps_present(b, e))
+            return fail(ACC_ERR_ALREADY_PRESENT, "clause " + std::to_string(k) + " overlaps a mapped host range");
+        for (auto &r : ranges)
+            if (b < r.second && r.first < e)
+                return fail(ACC_ERR_ALREADY_PRESENT, "clauses of one region overlap");
+        ranges.push_back({b, e});
+        total += e - b;
+    }
+    if (st.budget && st.used + total > st.budget)
+        return fail(ACC_ERR_OUT_OF_MEMORY, "region needs " + std::to_string(total) + " bytes; budget has " +
+                                               std::to_string(st.budget - std::min(st.budget, st.used)) + " left");
+
+    acc_region_s *r = new (std::nothrow) acc_region_s();
+    if (!r) return fail(ACC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    if (hip_stream) {
+        r->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        const hipError_t e = hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete r;
+            return fail_hip(e, "hipStreamCreate");
+        }
+        r->own_stream = true;
+    }
+
+    for (int k = 0; k < ncl; ++k) {
+        const acc_clause &c = cl[k];
+        if (c.n == 0) continue;
+        Entry en;
+        en.hbeg = reinterpret_cast<uintptr_t>(c.host) + (uintptr_t)c.start * elem_bytes(c.dtype);
+        en.hend = en.hbeg + (uintptr_t)c.n * elem_bytes(c.dtype);
+        en.kind = c.kind;
+        en.dtype = c.dtype;
+        en.owner = r;
+        s = dev_alloc(&en.dev, en.hend - en.hbeg);
+        if (s == ACC_OK && (c.kind == ACC_COPY || c.kind == ACC_COPYIN)) {
+            if (fault_hit(st.fault.copies, st.fault.copy_at)) {
+                s = fail(ACC_ERR_DEVICE, "injected copy fault (ACCX_FAULT)");
+            } else {
+                const hipError_t e = hipMemcpyAsync(en.dev, reinterpret_cast<void *>(en.hbeg), en.hend - en.hbeg,
+                                                    hipMemcpyHostToDevice, r->stream);
+                if (e != hipSuccess) s = fail_hip(e, "hipMemcpyAsync H2D");
+            }
+        }
+        if (s != ACC_OK) {
+            const std::string msg = t_last_error;
+            if (en.dev) {
+                (void)hipStreamSynchronize(r->stream);
+                dev_free(en.dev, en.hend - en.hbeg);
+            }
+            (void)hipStreamSynchronize(r->stream);
+            free_region(r);
+            delete r;
+            return fail(s, msg);
+        }
+        st.present[en.hbeg] = en;
+        r->keys.push_back(en.hbeg);
+    }
+    st.regions.insert(r);
+    *out = r;
+    return ACC_OK;
+}
+
+acc_status acc_wait(acc_region r)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!r || !st.regions.count(r)) return fail(ACC_ERR_INVALID_ARG, "unknown region");
+    acc_status s = wait_region(r);
+    if (s != ACC_OK) return s;
+    if (r->err != ACC_OK) return fail(r->err, r->err_msg);
+    return ACC_OK;
+}
+
+acc_status acc_data_end(acc_region r)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!r || !st.regions.count(r)) return fail(ACC_ERR_INVALID_ARG, "unknown region");
+    acc_status first = r->err;
+    std::string first_msg = r->err_msg;
+    acc_status s = wait_region(r);
+    if (first == ACC_OK && s != ACC_OK) {
+        first = s;
+        first_msg = t_last_error;
+    }
+    if (first == ACC_OK) {
+        for (uintptr_t k : r->keys) {
+            const Entry &en = st.present[k];
+            if (en.kind != ACC_COPY && en.kind != ACC_COPYOUT) continue;
+            if (fault_hit(st.fault.copies, st.fault.copy_at)) {
+                first = ACC_ERR_DEVICE;
+                first_msg = "injected copy fault (ACCX_FAULT)";
+                break;
+            }
+            const hipError_t e = hipMemcpyAsync(reinterpret_cast<void *>(en.hbeg), en.dev, en.hend - en.hbeg,
+                                                hipMemcpyDeviceToHost, r->stream);
+            if (e != hipSuccess) {
+                first = fail_hip(e, "hipMemcpyAsync D2H");
+                first_msg = t_last_error;
+                break;
+            }
+        }
+        const hipError_t e = hipStreamSynchronize(r->stream);
+        if (e != hipSuccess && first == ACC_OK) {
+            first = fail_hip(e, "hipStreamSynchronize");
+            first_msg = t_last_error;
+        }
+    }
+    free_region(r);
+    st.regions.erase(r);
+    delete r;
+    if (first != ACC_OK) return fail(first, first_msg);
+    return ACC_OK;
+}
+
+acc_status acc_deviceptr(const void *host, void **device_out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!device_out) return fail(ACC_ERR_INVALID_ARG, "device_out is NULL");
+    *device_out = nullptr;
+    Entry *e = lookup(host, 1);
+    if (!e) return fail(ACC_ERR_NOT_PRESENT, "host address is not mapped");
+    *device_out = static_cast<char *>(e->dev) + (reinterpret_cast<uintptr_t>(host) - e->hbeg);
+    return ACC_OK;
+}
+
+acc_status acc_loopnest_matmul(acc_region r, acc_dtype t, const void *a, const void *b, void *c, int64_t len,
+                               uint32_t flags)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!r || !st.regions.count(r)) return fail(ACC_ERR_INVALID_ARG, "unknown region");
+    if (r->err != ACC_OK) return fail(r->err, "region already failed: " + r->err_msg);
+    acc_status s = validate_matmul(t, len, flags);
+    if (s != ACC_OK) return s;
+    const size_t bytes = (size_t)len * (size_t)len * 4;
+    void *da, *db, *dc;
+    if ((s = resolve(a, bytes, t, "a", &da)) != ACC_OK) return s;
+    if ((s = resolve(b, bytes, t, "b", &db)) != ACC_OK) return s;
+    if ((s = resolve(c, bytes, t, "c", &dc)) != ACC_OK) return s;
+    const uintptr_t ci = reinterpret_cast<uintptr_t>(c);
+    for (const void *in : {a, b}) {
+        const uintptr_t ii = reinterpret_cast<uintptr_t>(in);
+        if (ci < ii + bytes && ii < ci + bytes) return fail(ACC_ERR_INVALID_ARG, "c overlaps an input");
+    }
+    const size_t wsb = matmul_ws_bytes(t, len, flags);
+    if (wsb && (s = ws_reserve(r->mm_work, wsb, false, r->stream)) != ACC_OK) return s;
+    s = run_matmul(t, da, db, dc, len, flags, r->mm_work.ptr, r->mm_work.bytes, r->stream);
+    if (s != ACC_OK) return poison(r, s);
+    return ACC_OK;
+}
+
+acc_status acc_reduce_sum(acc_region r, acc_dtype t, const void *x, int64_t n, void *inout, uint32_t flags)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!r || !st.regions.count(r)) return fail(ACC_ERR_INVALID_ARG, "unknown region");
+    if (r->err != ACC_OK) return fail(r->err, "region already failed: " + r->err_msg);
+    acc_status s = validate_reduce(t, n, flags);
+    if (s != ACC_OK) return s;
+    if (!inout) return fail(ACC_ERR_INVALID_ARG, "inout_result is NULL");
+    if (n == 0) return ACC_OK;  // *inout unchanged
+    void *dx;
+    if ((s = resolve(x, (size_t)n * 4, t, "x", &dx)) != ACC_OK) return s;
+    if (!r->dres) {
+        if ((s = dev_alloc(&r->dres, (size_t)kMaxSlots * 4)) != ACC_OK) return s;
+        r->nslots = kMaxSlots;
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&r->hres), (size_t)kMaxSlots * 4);
+        if (e != hipSuccess) return fail_hip(e, "hipHostMalloc");
+    }
+    if (r->used_slots == r->nslots) {
+        if ((s = wait_region(r)) != ACC_OK) return s;
+    }
+    const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
+    Workspace &w = plain ? r->red_plain_work : r->red_work;
+    if ((s = ws_reserve(w, reduce_ws_bytes(n, flags), !plain, r->stream)) != ACC_OK) return s;
+    const int slot = r->used_slots++;
+    void *dslot = static_cast<char *>(r->dres) + (size_t)slot * 4;
+    s = run_reduce(t, dx, n, inout, dslot, flags, w.ptr, r->stream);
+    if (s != ACC_OK) return poison(r, s);
+    hipError_t e = hipMemcpyAsync(r->hres + slot, dslot, 4, hipMemcpyDeviceToHost, r->stream);
+    if (e != hipSuccess) return poison(r, fail_hip(e, "hipMemcpyAsync D2H (result)"));
+    r->pending.push_back(Pending{inout, slot});
+    if (flags & ACC_ASYNC) return ACC_OK;
+    return wait_region(r);
+}
+
+acc_status accx_matmul_workspace_size(acc_dtype t, int64_t len, uint32_t flags, size_t *bytes_out)
+{
+    if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
+    acc_status s = validate_matmul(t, len, flags);
+    if (s != ACC_OK) return s;
+    *bytes_out = matmul_ws_bytes(t, len, flags);
+    return ACC_OK;
+}
+
+acc_status accx_matmul_dev(acc_dtype t, const void *dA, const void *dB, void *dC, int64_t len, uint32_t flags,
+                           void *dWork, size_t work_bytes, void *hip_stream)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if ((s = validate_matmul(t, len, flags)) != ACC_OK) return s;
+    if (!dA || !dB || !dC) return fail(ACC_ERR_INVALID_ARG, "NULL device pointer");
+    if (((uintptr_t)dA | (uintptr_t)dB | (uintptr_t)dC) & 3u)
+        return fail(ACC_ERR_INVALID_ARG, "device pointers must be 4-byte aligned");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const size_t need = matmul_ws_bytes(t, len, flags);
+    if (need) {
+        if (dWork) {
+            if (work_bytes < need) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
+        } else {
+            Workspace &w = st.mm_ws[stream];
+            if ((s = ws_reserve(w, need, false, stream)) != ACC_OK) return s;
+            dWork = w.ptr;
+            work_bytes = w.bytes;
+        }
+    }
+    return run_matmul(t, dA, dB, dC, len, flags, dWork, work_bytes, stream);
+}
+
+acc_status accx_reduce_workspace_size(acc_dtype t, int64_t n, uint32_t flags, size_t *bytes_out)
+{
+    if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
+    acc_status s = validate_reduce(t, n, flags);
+    if (s != ACC_OK) return s;
+    *bytes_out = reduce_ws_bytes(n, flags);
+    return ACC_OK;
+}
+
+acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const void *init, void *dResult,
+                               uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if ((s = validate_reduce(t, n, flags)) != ACC_OK) return s;
+    if (flags & ACC_ASYNC) return fail(ACC_ERR_INVALID_ARG, "ACC_ASYNC applies to region calls only");
+    if ((n > 0 && !dX) || !dResult || !init) return fail(ACC_ERR_INVALID_ARG, "NULL pointer");
+    if (((uintptr_t)dX | (uintptr_t)dResult) & 3u) return fail(ACC_ERR_INVALID_ARG, "pointers must be 4-byte aligned");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
+    const size_t need = reduce_ws_bytes(n, flags);
+    if (dWork) {
+        if (work_bytes < need) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
+    } else {
+        Workspace &w = plain ? st.red_plain_ws[stream] : st.red_ws[stream];
+        if ((s = ws_reserve(w, need, !plain, stream)) != ACC_OK) return s;
+        dWork = w.ptr;
+    }
+    return run_reduce(t, dX, n, init, dResult, flags, dWork, stream);
+}
+
+const char *acc_status_string(acc_status s)
+{
+    switch (s) {
+    case ACC_OK: return "ACC_OK";
+    case ACC_ERR_INVALID_ARG: return "ACC_ERR_INVALID_ARG";
+    case ACC_ERR_NOT_PRESENT: return "ACC_ERR_NOT_PRESENT";
+    case ACC_ERR_ALREADY_PRESENT: return "ACC_ERR_ALREADY_PRESENT";
+    case ACC_ERR_OUT_OF_MEMORY: return "ACC_ERR_OUT_OF_MEMORY";
+    case ACC_ERR_DEVICE: return "ACC_ERR_DEVICE";
+    case ACC_ERR_NO_DEVICE: return "ACC_ERR_NO_DEVICE";
+    }
+    return "unknown acc_status";
+}
+
+const char *acc_last_error_string(void) { return t_last_error.c_str(); }
+
+const char *accx_version(void) { return "libaccx 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+namespace accx {
+int device_cu_count()
+{
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cached = v;
+    return v;
+}
+}  // namespace accx
