@@ -186,6 +186,45 @@ ACCX_API acc_status accx_reduce_workspace_size(acc_dtype t, int64_t n, uint32_t 
 ACCX_API acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const void *init, void *dResult,
                                uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
 
+/* ---- matrix-core operand packing (the prepass of the tiled kernel) -------
+ * The tiled kernel reads its operands in a packed layout written by a
+ * prepass: float32 -> three bf16 planes hi = RN(x), mid = RN(x - hi),
+ * lo = RN(x - hi - mid) (RN = round to nearest even); int32 -> `planes`
+ * balanced base-256 digit planes d_k in [-128, 127], x = sum d_k 256^k
+ * (exactly for |x| within the digit range, else modulo 2^32).
+ * Layout: an operand of `rows` rows of `k` elements (transposed = 0: row r of
+ * the row-major rows x k array; transposed = 1: column r of the row-major
+ * k x rows array) is cut into units of 32 rows x 64 bytes per plane; unit
+ * (rb, kb) (rb < ceil(rows/32), kb < nkb = ceil(k * elem_bytes / 64)) starts
+ * at byte (rb*nkb + kb) * planes * 2048, and inside it plane p, 16-byte chunk
+ * c (0..3) of row r (0..31) is at p*2048 + c*512 + r*16.  Elements past rows
+ * or k are zero.  elem_bytes = 2 (bf16) or 1 (int8). */
+ACCX_API acc_status accx_packed_size(acc_dtype t, int64_t rows, int64_t k, int planes, size_t *bytes_out);
+/* Pack device array dX into dOut (at least accx_packed_size bytes) on
+ * `hip_stream`.  float32 needs planes = 3; int32 planes in 1..4.
+ * Errors: INVALID_ARG, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_pack_dev(acc_dtype t, const void *dX, int64_t rows, int64_t k, int transposed, int planes,
+                                  void *dOut, size_t out_bytes, void *hip_stream);
+
+/* ---- kernel timing -------------------------------------------------------
+ * The paper reports kernel execution time separately from launch and
+ * transfer time (section 3, "Performance evaluations").  With timing on, the
+ * library records a HIP event on the launch stream before and after every
+ * kernel it launches; accx_timing_read synchronizes on those events and
+ * returns per-kernel totals.  Off by default; costs two event records per
+ * kernel when on. */
+typedef struct {
+    char name[48];   /* kernel name, NUL-terminated */
+    int64_t launches;
+    double total_ms; /* sum of event-measured durations */
+    double min_ms, max_ms;
+} accx_kernel_time;
+
+ACCX_API acc_status accx_timing_enable(int on);
+/* Fills up to `cap` entries, sets *n_out to the number of kernels seen;
+ * reset != 0 clears the totals afterwards.  Errors: INVALID_ARG. */
+ACCX_API acc_status accx_timing_read(accx_kernel_time *out, int cap, int *n_out, int reset);
+
 /* ---- strings ------------------------------------------------------------ */
 ACCX_API const char *acc_status_string(acc_status s);
 ACCX_API const char *acc_last_error_string(void);

@@ -54,13 +54,18 @@ class AccxError(RuntimeError):
         self.status = status
 
 
+class accx_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
 class acc_clause(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("host", ctypes.c_void_p),
                 ("start", ctypes.c_int64), ("n", ctypes.c_int64)]
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libaccx.so is not built (%s); run `python -m paper_1412_1127_amd.build` "
+    raise ImportError("libaccx.so is not built (%s); run `python paper_1412_1127_amd/build.py` "
                       "or __graft_entry__.build()" % LIB_PATH)
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -83,6 +88,10 @@ _SIGS = {
     "accx_matmul_dev": [ctypes.c_int, _vp, _vp, _vp, _i64, _u32, _vp, _sz, _vp],
     "accx_reduce_workspace_size": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_sz)],
     "accx_reduce_sum_dev": [ctypes.c_int, _vp, _i64, _vp, _vp, _u32, _vp, _sz, _vp],
+    "accx_packed_size": [ctypes.c_int, _i64, _i64, ctypes.c_int, ctypes.POINTER(_sz)],
+    "accx_pack_dev": [ctypes.c_int, _vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _sz, _vp],
+    "accx_timing_enable": [ctypes.c_int],
+    "accx_timing_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
 }
 _STRINGS = {"acc_status_string": [ctypes.c_int], "acc_last_error_string": [], "accx_version": []}
 
@@ -96,6 +105,7 @@ for _name, _args in _STRINGS.items():
     _f.restype = ctypes.c_char_p
 
 EXPORTED = tuple(_SIGS) + tuple(_STRINGS)
+FEATURES = ("plain", "tiled")
 
 
 def status_string(s: int) -> str:
@@ -216,3 +226,29 @@ def accx_reduce_sum_dev(dtype: int, dX, n: int, init, dResult, flags: int = 0, w
     iv = ctypes.c_float(float(init)) if dtype == ACC_FLOAT32 else ctypes.c_int32(int(init))
     _check(_lib.accx_reduce_sum_dev(int(dtype), _addr(dX), int(n), ctypes.byref(iv), _addr(dResult), int(flags),
                                     _addr(work), int(work_bytes), _stream(stream)), "accx_reduce_sum_dev")
+
+
+def accx_packed_size(dtype: int, rows: int, k: int, planes: int) -> int:
+    v = _sz(0)
+    _check(_lib.accx_packed_size(int(dtype), int(rows), int(k), int(planes), ctypes.byref(v)), "accx_packed_size")
+    return int(v.value)
+
+
+def accx_pack_dev(dtype: int, dX, rows: int, k: int, transposed: bool, planes: int, dOut, out_bytes: int,
+                  stream=None) -> None:
+    _check(_lib.accx_pack_dev(int(dtype), _addr(dX), int(rows), int(k), int(bool(transposed)), int(planes),
+                              _addr(dOut), int(out_bytes), _stream(stream)), "accx_pack_dev")
+
+
+def accx_timing_enable(on: bool = True) -> None:
+    _check(_lib.accx_timing_enable(int(bool(on))), "accx_timing_enable")
+
+
+def accx_timing_read(reset: bool = False) -> dict:
+    """{kernel name: (launches, total_ms, min_ms, max_ms)}; synchronizes on the recorded events."""
+    cap = 64
+    buf = (accx_kernel_time * cap)()
+    n = ctypes.c_int(0)
+    _check(_lib.accx_timing_read(buf, cap, ctypes.byref(n), int(bool(reset))), "accx_timing_read")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms), float(buf[i].min_ms),
+                                   float(buf[i].max_ms)) for i in range(min(cap, n.value))}

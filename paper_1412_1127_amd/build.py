@@ -1,6 +1,7 @@
 """Build libaccx.so in-tree with hipcc for gfx950.
 
-``python -m paper_1412_1127_amd.build`` or ``build()`` compiles every source
+``python paper_1412_1127_amd/build.py`` (by path: importing the package
+would load the library being rebuilt) or ``build()`` compiles every source
 under ``csrc/`` (in parallel) and links ``paper_1412_1127_amd/libaccx.so``.
 """
 from __future__ import annotations
@@ -21,6 +22,7 @@ SOURCES = [
     "runtime.cpp",
     "matmul_plain.hip",
     "reduce.hip",
+    "gemm_mfma.hip",
 ]
 
 ARCH = "gfx950"

@@ -1,0 +1,496 @@
+// The loop nest of Listing 1a (section 1.3) on the matrix cores of gfx950,
+// tiled through LDS.  This is the MI355X form of what the Matrix
+// Multiplication paragraph of section 4.2 credits for the CUDA version's
+// speed: a workgroup fetches input tiles with a few wide, coalesced accesses
+// into the software-managed on-chip memory and shares them among its threads,
+// instead of each thread streaming a row of a and a column of b by itself.
+//
+// Two element paths share one tiled kernel:
+//  - float32 on bf16 matrix cores ("bf16x3"): each operand x is split into
+//    three bf16 terms x = hi + mid + lo (hi = RN(x), mid = RN(x - hi),
+//    lo = RN(x - hi - mid), RN = round to nearest even); C accumulates in
+//    float32 the products of term pairs (p, q): all six with p+q <= 2
+//    (FULL6), or the three with p+q <= 1 (CHEAP3).
+//  - int32 on int8 matrix cores: each operand is written in balanced
+//    base-256 digits d_k in [-128, 127], x = sum d_k 256^k (mod 2^32); C is
+//    the sum over digit pairs (k, m) with k+m <= 3 of (A_k B_m) << 8(k+m),
+//    modulo 2^32.  Products with the same shift share an int32 accumulator.
+//
+// Packed operand layout (written by the pack kernels below, read by the
+// GEMM).  An operand of R rows of K elements (A: rows of A; B: columns of B,
+// i.e. rows of B^T) with P planes is cut into units of 32 rows x 64 bytes of
+// each plane.  Unit (rb, kb) starts at byte (rb*nkb + kb) * P * 2048; inside
+// it, plane p, 16-byte chunk c (0..3) of row r (0..31) is at
+// p*2048 + c*512 + r*16.  Rows >= R and elements >= K are zero.  The layout
+// makes every global->LDS copy a contiguous 1 KB block (one direct-to-LDS
+// dwordx4 load per wavefront) and every matrix-core operand fetch a
+// conflict-free ds_read_b128 of 1 KB (lane l: row l%32, chunk l/32).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace accx {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int PLANE_BYTES = 2048;  // 32 rows x 64 bytes
+
+// ---------------------------------------------------------------- packing --
+
+__device__ inline uint16_t bf16_bits(__bf16 h) { return __builtin_bit_cast(uint16_t, h); }
+
+// x = hi + mid + lo, each term rounded to nearest even bf16 (v_cvt_pk_bf16_f32).
+// x - hi and (x - hi) - mid are exact in float32.
+__device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l)
+{
+    const __bf16 bh = (__bf16)x;
+    const float r1 = x - (float)bh;
+    const __bf16 bm = (__bf16)r1;
+    const float r2 = r1 - (float)bm;
+    h = bf16_bits(bh);
+    m = bf16_bits(bm);
+    l = bf16_bits((__bf16)r2);
+}
+
+// One thread per (unit, row, chunk): 8 consecutive K elements of one row.
+// TRANS = false: X is R x K row-major (operand row r = X row r).
+// TRANS = true:  X is K x R row-major (operand row r = X column r).
+template <bool TRANS>
+__global__ __launch_bounds__(256) void pack_bf16x3(const float *__restrict__ X, int64_t R, int64_t K,
+                                                   char *__restrict__ out, int64_t nrb, int64_t nkb)
+{
+    const int64_t total = nrb * nkb * 128;
+    for (int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x; id < total; id += (int64_t)gridDim.x * 256) {
+        const int64_t unit = id >> 7;
+        const int w = (int)(id & 127);
+        int r, c;
+        if (TRANS) {
+            r = w & 31;
+            c = w >> 5;
+        } else {
+            r = w >> 2;
+            c = w & 3;
+        }
+        const int64_t rb = unit / nkb, kb = unit - rb * nkb;
+        const int64_t row = rb * 32 + r;
+        const int64_t k0 = kb * 32 + c * 8;
+        float v[8];
+        if (TRANS) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[(k0 + t) * R + row] : 0.0f;
+        } else if (row < R && k0 + 8 <= K && ((K & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
+            const f32x4 *p = reinterpret_cast<const f32x4 *>(X + row * K + k0);
+            const f32x4 a = p[0], b = p[1];
+            v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[row * K + k0 + t] : 0.0f;
+        }
+        u16x8 h, m, l;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            uint16_t a, b, d;
+            split3(v[t], a, b, d);
+            h[t] = a;
+            m[t] = b;
+            l[t] = d;
+        }
+        char *u = out + unit * (3 * PLANE_BYTES) + c * 512 + r * 16;
+        *reinterpret_cast<u16x8 *>(u) = h;
+        *reinterpret_cast<u16x8 *>(u + PLANE_BYTES) = m;
+        *reinterpret_cast<u16x8 *>(u + 2 * PLANE_BYTES) = l;
+    }
+}
+
+// int32 -> P balanced base-256 digit planes (int8), 16 K elements per thread.
+// maxabs (optional): running max of |x| over the operand, as uint32.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K,
+                                               char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
+                                               uint32_t *__restrict__ maxabs)
+{
+    const int64_t total = nrb * nkb * 128;
+    uint32_t mx = 0;
+    for (int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x; id < total; id += (int64_t)gridDim.x * 256) {
+        const int64_t unit = id >> 7;
+        const int w = (int)(id & 127);
+        int r, c;
+        if (TRANS) {
+            r = w & 31;
+            c = w >> 5;
+        } else {
+            r = w >> 2;
+            c = w & 3;
+        }
+        const int64_t rb = unit / nkb, kb = unit - rb * nkb;
+        const int64_t row = rb * 32 + r;
+        const int64_t k0 = kb * 64 + c * 16;
+        int32_t v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const bool in = row < R && k0 + t < K;
+            v[t] = in ? (TRANS ? X[(k0 + t) * R + row] : X[row * K + k0 + t]) : 0;
+        }
+        int64_t rem[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            rem[t] = v[t];
+            const uint32_t a = v[t] < 0 ? (uint32_t)0 - (uint32_t)v[t] : (uint32_t)v[t];
+            mx = a > mx ? a : mx;
+        }
+        char *u = out + unit * ((int64_t)nplanes * PLANE_BYTES) + c * 512 + r * 16;
+        for (int p = 0; p < nplanes; ++p) {
+            i32x4 word = {0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int d = (int)(((uint32_t)rem[t] + 128u) & 255u) - 128;  // in [-128, 127]
+                rem[t] = (rem[t] - d) >> 8;                                     // exact division by 256
+                word[t >> 2] |= (int)((uint32_t)(uint8_t)(int8_t)d << (8 * (t & 3)));
+            }
+            *reinterpret_cast<i32x4 *>(u + (int64_t)p * PLANE_BYTES) = word;
+        }
+    }
+    if (maxabs) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t t = __shfl_xor(mx, o, 64);
+            mx = t > mx ? t : mx;
+        }
+        if ((threadIdx.x & 63) == 0) atomicMax(maxabs, mx);
+    }
+}
+
+// ------------------------------------------------------------------- GEMM --
+
+template <bool INT8> struct Mma;
+template <> struct Mma<false> {
+    using Frag = bf16x8;
+    using Acc = f32x16;
+    __device__ static inline Acc run(Frag a, Frag b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mma<true> {
+    using Frag = i32x4;
+    using Acc = i32x16;
+    __device__ static inline Acc run(Frag a, Frag b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+    }
+};
+
+// Product list: entry t = (plane of A, plane of B, accumulator) in 6 bits.
+constexpr uint64_t prod(int t, int p, int q, int acc)
+{
+    return (uint64_t)(p | (q << 2) | (acc << 4)) << (6 * t);
+}
+constexpr int prod_p(uint64_t L, int t) { return (int)((L >> (6 * t)) & 3); }
+constexpr int prod_q(uint64_t L, int t) { return (int)((L >> (6 * t + 2)) & 3); }
+constexpr int prod_acc(uint64_t L, int t) { return (int)((L >> (6 * t + 4)) & 3); }
+
+// bf16x3: hi*hi, hi*mid, mid*hi | hi*lo, lo*hi, mid*mid
+constexpr uint64_t PL_CHEAP3 = prod(0, 0, 0, 0) | prod(1, 0, 1, 0) | prod(2, 1, 0, 0);
+constexpr uint64_t PL_FULL6 = PL_CHEAP3 | prod(3, 0, 2, 0) | prod(4, 2, 0, 0) | prod(5, 1, 1, 0);
+constexpr uint64_t PL_CORR3 = prod(0, 0, 2, 0) | prod(1, 2, 0, 0) | prod(2, 1, 1, 0);
+// int8 limbs, accumulator = shift group k+m
+constexpr uint64_t PL_L1 = prod(0, 0, 0, 0);
+constexpr uint64_t PL_L2 = prod(0, 0, 0, 0) | prod(1, 0, 1, 1) | prod(2, 1, 0, 1) | prod(3, 1, 1, 2);
+constexpr uint64_t PL_L3 = prod(0, 0, 0, 0) | prod(1, 0, 1, 1) | prod(2, 1, 0, 1) | prod(3, 0, 2, 2) |
+                           prod(4, 1, 1, 2) | prod(5, 2, 0, 2) | prod(6, 1, 2, 3) | prod(7, 2, 1, 3);
+constexpr uint64_t PL_L4 = PL_L3 | prod(8, 0, 3, 3) | prod(9, 3, 0, 3);
+
+struct GemmArgs {
+    const char *A;  // packed A, P planes
+    const char *B;  // packed B^T, P planes
+    void *C;        // M x N row-major, leading dimension ldc
+    int64_t M, N, ldc;
+    int64_t nkb;     // 64-byte K units per row
+    int64_t nrb_a;   // 32-row blocks present in packed A
+    int64_t nrb_b;   // 32-row blocks present in packed B
+    int tiles_m, tiles_n;
+    int accumulate;  // float: C += result instead of C = result
+};
+
+// Map the linear workgroup id to an output tile.  Workgroups are dealt to
+// the 8 XCDs round-robin; give each XCD a contiguous run of the grouped tile
+// order so that the workgroups sharing an L2 also share A and B tiles.
+__device__ inline void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn)
+{
+    const int T = tiles_m * tiles_n;
+    int t = bid;
+    if ((T & 7) == 0) t = (bid & 7) * (T >> 3) + (bid >> 3);
+    constexpr int GM = 8;
+    const int per_group = GM * tiles_n;
+    const int g = t / per_group;
+    const int first = g * GM;
+    const int gsz = min(tiles_m - first, GM);
+    const int w = t - g * per_group;
+    tm = first + w % gsz;
+    tn = w / gsz;
+}
+
+template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NPROD, uint64_t PL, int NACC>
+__global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
+{
+    using M = Mma<INT8>;
+    using Frag = typename M::Frag;
+    using Acc = typename M::Acc;
+    constexpr int WAVES = WGM * WGN;
+    constexpr int MB = BM / 32, NB = BN / 32;          // 32-row units per tile
+    constexpr int WBM = MB / WGM, WBN = NB / WGN;      // 32x32 blocks per wave
+    constexpr int LUNIT = P * 32 * KBK;                // LDS bytes per unit per K-step
+    constexpr int CPU = P * KBK / 32;                  // 1 KB copies per unit per K-step
+    constexpr int NCOPY = (MB + NB) * CPU;
+    constexpr int STAGE = (MB + NB) * LUNIT;
+    constexpr int SUB = KBK / 32;                      // matrix-core K steps per K-step
+    constexpr int HALVES = 64 / KBK;                   // K-steps per 64-byte unit
+    static_assert(MB % WGM == 0 && NB % WGN == 0, "tile/wave mismatch");
+    static_assert(KBK == 32 || KBK == 64, "K step is 32 or 64 bytes");
+
+    __shared__ __attribute__((aligned(1024))) char lds[2 * STAGE];
+
+    int tm, tn;
+    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int64_t ustride_a = (int64_t)P * PLANE_BYTES;  // bytes per packed unit
+    const int64_t rb0 = (int64_t)tm * MB, cb0 = (int64_t)tn * NB;
+    const int nsteps = (int)(g.nkb * HALVES);
+
+    auto issue = [&](int step, int buf) {
+        const int64_t kb = step / HALVES;
+        const int h = step % HALVES;
+        char *sbase = lds + buf * STAGE;
+#pragma unroll
+        for (int q0 = 0; q0 < NCOPY; q0 += WAVES) {
+            const int q = q0 + wave;
+            if (q < NCOPY) {
+                const bool isA = q < MB * CPU;
+                const int qq = isA ? q : q - MB * CPU;
+                const int u = qq / CPU, part = qq % CPU;
+                const int p = part / (KBK / 32), piece = part % (KBK / 32);
+                const int64_t rb = (isA ? rb0 : cb0) + u;
+                if (rb < (isA ? g.nrb_a : g.nrb_b)) {
+                    const char *src = (isA ? g.A : g.B) + (rb * g.nkb + kb) * ustride_a + p * PLANE_BYTES +
+                                      h * (KBK * 32) + piece * 1024 + lane * 16;
+                    char *dst = sbase + (isA ? 0 : MB * LUNIT) + u * LUNIT + p * (32 * KBK) + piece * 1024;
+                    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+                }
+            }
+        }
+    };
+
+    Acc acc[NACC][WBM][WBN];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int i = 0; i < WBM; ++i)
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) acc[a][i][j] = (Acc)0;
+
+    issue(0, 0);
+    for (int step = 0; step < nsteps; ++step) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (step + 1 < nsteps) issue(step + 1, (step + 1) & 1);
+        const char *sA = lds + (step & 1) * STAGE;
+        const char *sB = sA + MB * LUNIT;
+#pragma unroll
+        for (int s = 0; s < SUB; ++s) {
+            const int off = (2 * s + (lane >> 5)) * 512 + (lane & 31) * 16;
+            Frag fa[P][WBM], fb[P][WBN];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int i = 0; i < WBM; ++i)
+                    fa[p][i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + p * 32 * KBK + off);
+#pragma unroll
+                for (int j = 0; j < WBN; ++j)
+                    fb[p][j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + p * 32 * KBK + off);
+            }
+#pragma unroll
+            for (int t = 0; t < NPROD; ++t) {
+#pragma unroll
+                for (int i = 0; i < WBM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WBN; ++j)
+                        acc[prod_acc(PL, t)][i][j] =
+                            M::run(fa[prod_p(PL, t)][i], fb[prod_q(PL, t)][j], acc[prod_acc(PL, t)][i][j]);
+            }
+        }
+    }
+
+    // Epilogue.  32x32 accumulator layout: register r of lane l holds
+    // row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block.
+#pragma unroll
+    for (int i = 0; i < WBM; ++i)
+#pragma unroll
+        for (int j = 0; j < WBN; ++j) {
+            const int64_t col = ((int64_t)tn * NB + wn * WBN + j) * 32 + (lane & 31);
+            const int64_t rowb = ((int64_t)tm * MB + wm * WBM + i) * 32 + (lane >> 5) * 4;
+            if (col >= g.N) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = rowb + (r >> 2) * 8 + (r & 3);
+                if (row >= g.M) continue;
+                if (INT8) {
+                    uint32_t v = 0;
+#pragma unroll
+                    for (int a = 0; a < NACC; ++a) v += (uint32_t)acc[a][i][j][r] << (8 * a);
+                    static_cast<int32_t *>(g.C)[row * g.ldc + col] = (int32_t)v;
+                } else {
+                    float *cp = static_cast<float *>(g.C) + row * g.ldc + col;
+                    const float v = (float)acc[0][i][j][r];
+                    *cp = g.accumulate ? *cp + v : v;
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------- tile configs --
+
+struct Cfg {
+    int bm, bn;
+};
+
+template <bool INT8, int P, int NPROD, uint64_t PL, int NACC>
+hipError_t run_gemm(const Cfg &cfg, GemmArgs g, hipStream_t s)
+{
+    g.tiles_m = (int)((g.M + cfg.bm - 1) / cfg.bm);
+    g.tiles_n = (int)((g.N + cfg.bn - 1) / cfg.bn);
+    const dim3 grid((unsigned)(g.tiles_m * g.tiles_n));
+    if (cfg.bm == 128 && cfg.bn == 128) {
+        hipLaunchKernelGGL((gemm_packed<INT8, P, 128, 128, 64, 2, 2, NPROD, PL, NACC>), grid, dim3(256), 0, s, g);
+    } else if (cfg.bm == 64 && cfg.bn == 64) {
+        hipLaunchKernelGGL((gemm_packed<INT8, P, 64, 64, 64, 2, 2, NPROD, PL, NACC>), grid, dim3(256), 0, s, g);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+Cfg choose_cfg(int64_t len, int planes)
+{
+    (void)planes;
+    if (len <= 512) return Cfg{64, 64};
+    return Cfg{128, 128};
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__global__ void zero_u32(uint32_t *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+unsigned pack_grid(int64_t units)
+{
+    int64_t blocks = cdiv(units * 128, 256);
+    const int64_t cap = (int64_t)device_cu_count() * 16;
+    if (blocks > cap) blocks = cap;
+    return (unsigned)(blocks < 1 ? 1 : blocks);
+}
+
+}  // namespace
+
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+size_t packed_bytes(int64_t rows, int64_t k_elems, int elem_bytes, int planes)
+{
+    const int64_t nrb = cdiv(rows, 32);
+    const int64_t nkb = cdiv(k_elems * elem_bytes, 64);
+    return (size_t)(nrb * nkb * planes * PLANE_BYTES);
+}
+
+hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, bool trans, void *out, hipStream_t s)
+{
+    const int64_t nrb = cdiv(rows, 32), nkb = cdiv(k, 32);
+    const unsigned grid = pack_grid(nrb * nkb);
+    tmark("pack_bf16x3", s, true);
+    if (trans)
+        hipLaunchKernelGGL(pack_bf16x3<true>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out), nrb,
+                           nkb);
+    else
+        hipLaunchKernelGGL(pack_bf16x3<false>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out),
+                           nrb, nkb);
+    tmark("pack_bf16x3", s, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans, int planes, void *out,
+                          uint32_t *maxabs, hipStream_t s)
+{
+    const int64_t nrb = cdiv(rows, 32), nkb = cdiv(k, 64);
+    const unsigned grid = pack_grid(nrb * nkb);
+    tmark("pack_i8", s, true);
+    if (trans)
+        hipLaunchKernelGGL(pack_i8<true>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out), nrb, nkb,
+                           planes, maxabs);
+    else
+        hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out), nrb,
+                           nkb, planes, maxabs);
+    tmark("pack_i8", s, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t len, int products, bool accumulate,
+                              hipStream_t s)
+{
+    GemmArgs g{};
+    g.A = static_cast<const char *>(pa);
+    g.B = static_cast<const char *>(pb);
+    g.C = c;
+    g.M = g.N = g.ldc = len;
+    g.nkb = cdiv(len * 2, 64);
+    g.nrb_a = g.nrb_b = cdiv(len, 32);
+    g.accumulate = accumulate ? 1 : 0;
+    const Cfg cfg = choose_cfg(len, 3);
+    hipError_t e;
+    tmark("gemm_bf16x3", s, true);
+    if (products == 6)
+        e = run_gemm<false, 3, 6, PL_FULL6, 1>(cfg, g, s);
+    else if (products == 3)
+        e = run_gemm<false, 3, 3, PL_CHEAP3, 1>(cfg, g, s);
+    else if (products == -3)
+        e = run_gemm<false, 3, 3, PL_CORR3, 1>(cfg, g, s);
+    else
+        e = hipErrorInvalidValue;
+    tmark("gemm_bf16x3", s, false);
+    return e;
+}
+
+hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, hipStream_t s)
+{
+    GemmArgs g{};
+    g.A = static_cast<const char *>(pa);
+    g.B = static_cast<const char *>(pb);
+    g.C = c;
+    g.M = g.N = g.ldc = len;
+    g.nkb = cdiv(len, 64);
+    g.nrb_a = g.nrb_b = cdiv(len, 32);
+    const Cfg cfg = choose_cfg(len, limbs);
+    hipError_t e;
+    tmark("gemm_i8", s, true);
+    switch (limbs) {
+    case 1: e = run_gemm<true, 1, 1, PL_L1, 1>(cfg, g, s); break;
+    case 2: e = run_gemm<true, 2, 4, PL_L2, 3>(Cfg{64, 64}, g, s); break;
+    case 3: e = run_gemm<true, 3, 8, PL_L3, 4>(Cfg{64, 64}, g, s); break;
+    case 4: e = run_gemm<true, 4, 10, PL_L4, 4>(Cfg{64, 64}, g, s); break;
+    default: e = hipErrorInvalidValue;
+    }
+    tmark("gemm_i8", s, false);
+    return e;
+}
+
+}  // namespace accx

@@ -27,6 +27,29 @@ hipError_t launch_reduce_f32(const float *x, int64_t n, float init, float *resul
 hipError_t launch_reduce_i32(const int32_t *x, int64_t n, int32_t init, int32_t *result, void *work,
                              bool plain, hipStream_t s);
 
+// ---- tiled matrix-core path (gemm_mfma.hip) --------------------------------
+// Bytes of a packed operand: `rows` rows of `k_elems` elements of
+// `elem_bytes` bytes, `planes` planes (units of 32 rows x 64 bytes per plane).
+size_t packed_bytes(int64_t rows, int64_t k_elems, int elem_bytes, int planes);
+// float32 -> hi/mid/lo bf16 planes.  trans = false: x is rows x k row-major;
+// trans = true: x is k x rows row-major (packs the columns, i.e. B^T).
+hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, bool trans, void *out, hipStream_t s);
+// int32 -> `planes` balanced base-256 digit planes; maxabs (nullable) gets
+// atomicMax of |x| (must hold 0 or a smaller value beforehand).
+hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans, int planes, void *out,
+                          uint32_t *maxabs, hipStream_t s);
+// C (len x len) = sum over the product set of A-plane x B-plane.
+// products: 6 = FULL6, 3 = CHEAP3, -3 = the three products FULL6 adds to
+// CHEAP3.  accumulate: C += instead of C =.
+hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t len, int products, bool accumulate,
+                              hipStream_t s);
+hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
+
 int device_cu_count();  // compute units of the current device (cached)
+
+// Kernel timing hooks (runtime.cpp): when timing is enabled, record a HIP
+// event on `s` before (begin = true) and after each kernel launch.
+void tmark(const char *name, hipStream_t s, bool begin);
 
 }  // namespace accx

@@ -71,10 +71,14 @@ hipError_t launch(const T *a, const T *b, T *c, int64_t len, bool listing1b, hip
     if (len <= 0) return hipSuccess;
     if (listing1b) {
         const dim3 grid((unsigned)((len + 15) / 16), (unsigned)((len + 15) / 16));
+        tmark("matmul_plain_listing1b", s, true);
         hipLaunchKernelGGL(matmul_plain_listing1b<T>, grid, dim3(16, 16), 0, s, a, b, c, len);
+        tmark("matmul_plain_listing1b", s, false);
     } else {
         const dim3 grid((unsigned)((len + GV_X - 1) / GV_X), (unsigned)((len + GV_Y - 1) / GV_Y));
+        tmark("matmul_plain", s, true);
         hipLaunchKernelGGL(matmul_plain_gv<T>, grid, dim3(GV_X, GV_Y), 0, s, a, b, c, len);
+        tmark("matmul_plain", s, false);
     }
     return hipGetLastError();
 }

@@ -174,13 +174,21 @@ hipError_t launch_reduce(const L *x, int64_t n, L init, L *result, void *work, b
     if (plain) {
         const int64_t g = plain_blocks(n);
         L *partials = static_cast<L *>(work);
-        if (n > 0) hipLaunchKernelGGL(reduce_plain_blocks<L>, dim3((unsigned)g), dim3(RT), 0, s, x, n, partials);
+        if (n > 0) {
+            tmark("reduce_plain_blocks", s, true);
+            hipLaunchKernelGGL(reduce_plain_blocks<L>, dim3((unsigned)g), dim3(RT), 0, s, x, n, partials);
+            tmark("reduce_plain_blocks", s, false);
+        }
+        tmark("reduce_plain_final", s, true);
         hipLaunchKernelGGL(reduce_plain_final<L>, dim3(1), dim3(RT), 0, s, partials, n > 0 ? g : 0, init, result);
+        tmark("reduce_plain_final", s, false);
     } else {
         const int64_t g = fast_blocks(n);
         uint32_t *ticket = static_cast<uint32_t *>(work);
         uint32_t *partials = reinterpret_cast<uint32_t *>(static_cast<char *>(work) + TICKET_BYTES);
+        tmark("reduce_fast", s, true);
         hipLaunchKernelGGL(reduce_fast<L>, dim3((unsigned)g), dim3(RT), 0, s, x, n, init, result, ticket, partials);
+        tmark("reduce_fast", s, false);
     }
     return hipGetLastError();
 }

@@ -284,19 +284,73 @@ bool is_plain(uint32_t flags)
     return k == ACC_KERNEL_PLAIN || k == ACC_KERNEL_PLAIN_LISTING1B;
 }
 
+constexpr size_t kMaxabsBytes = 256;  // int path: two max|x| words, padded
+
+int flag_limbs(uint32_t flags) { return (int)((flags & ACC_LIMBS_MASK) >> ACC_LIMBS_SHIFT); }
+
+// Fewest balanced base-256 digits that represent every |x| <= m exactly.
+int limbs_for(uint32_t m)
+{
+    if (m <= 127u) return 1;
+    if (m <= 32639u) return 2;
+    if (m <= 8355711u) return 3;
+    return 4;
+}
+
 size_t matmul_ws_bytes(int t, int64_t len, uint32_t flags)
 {
-    (void)t;
-    (void)len;
     if (is_plain(flags)) return 0;
-    return 0;
+    if (t == ACC_FLOAT32) return 2 * accx::packed_bytes(len, len, 2, 3);
+    const int nl = flag_limbs(flags) ? flag_limbs(flags) : 4;
+    return kMaxabsBytes + 2 * accx::packed_bytes(len, len, 1, nl);
+}
+
+acc_status run_tiled_f32(const float *a, const float *b, float *c, int64_t len, uint32_t flags, char *work,
+                         hipStream_t s)
+{
+    const size_t pb = accx::packed_bytes(len, len, 2, 3);
+    char *pa = work, *pbt = work + pb;
+    hipError_t e = accx::launch_pack_bf16x3(a, len, len, false, pa, s);
+    if (e == hipSuccess) e = accx::launch_pack_bf16x3(b, len, len, true, pbt, s);
+    if (e != hipSuccess) return fail_hip(e, "pack (bf16x3) launch");
+    const uint32_t prec = flags & ACC_PREC_MASK;
+    const int products = (prec == ACC_PREC_CHEAP3) ? 3 : 6;
+    e = accx::launch_gemm_bf16x3(pa, pbt, c, len, products, false, s);
+    return check_launch(e, "gemm (bf16x3) launch");
+}
+
+acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, int64_t len, uint32_t flags, char *work,
+                         hipStream_t s)
+{
+    uint32_t *maxabs = reinterpret_cast<uint32_t *>(work);
+    char *pa = work + kMaxabsBytes;
+    int nl = flag_limbs(flags);
+    hipError_t e;
+    if (nl == 0) {
+        // Probe: write digit 0 of both operands and max|x| in one pass; the
+        // digit-0 planes are final when one digit is enough.
+        const size_t pb1 = accx::packed_bytes(len, len, 1, 1);
+        e = accx::launch_zero_u32(maxabs, 2, s);
+        if (e == hipSuccess) e = accx::launch_pack_i8(a, len, len, false, 1, pa, maxabs, s);
+        if (e == hipSuccess) e = accx::launch_pack_i8(b, len, len, true, 1, pa + pb1, maxabs + 1, s);
+        if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
+        uint32_t m[2] = {0, 0};
+        e = hipMemcpyAsync(m, maxabs, sizeof m, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail_hip(e, "max|x| probe readback");
+        nl = std::max(limbs_for(m[0]), limbs_for(m[1]));
+        if (nl == 1) return check_launch(accx::launch_gemm_i8(pa, pa + pb1, c, len, 1, s), "gemm (int8) launch");
+    }
+    const size_t pbn = accx::packed_bytes(len, len, 1, nl);
+    e = accx::launch_pack_i8(a, len, len, false, nl, pa, nullptr, s);
+    if (e == hipSuccess) e = accx::launch_pack_i8(b, len, len, true, nl, pa + pbn, nullptr, s);
+    if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
+    return check_launch(accx::launch_gemm_i8(pa, pa + pbn, c, len, nl, s), "gemm (int8) launch");
 }
 
 acc_status run_matmul(int t, const void *a, const void *b, void *c, int64_t len, uint32_t flags, void *work,
                       size_t work_bytes, hipStream_t s)
 {
-    (void)work;
-    (void)work_bytes;
     acc_status st = launch_fault();
     if (st != ACC_OK) return st;
     const uint32_t k = flags & ACC_KERNEL_MASK;
@@ -311,7 +365,12 @@ acc_status run_matmul(int t, const void *a, const void *b, void *c, int64_t len,
                                                            static_cast<int32_t *>(c), len, l1b, s);
         return check_launch(e, "matmul (plain) launch");
     }
-    return fail(ACC_ERR_INVALID_ARG, "the tiled matrix-core kernel is not available in this build");
+    if (work_bytes < matmul_ws_bytes(t, len, flags)) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
+    if (t == ACC_FLOAT32)
+        return run_tiled_f32(static_cast<const float *>(a), static_cast<const float *>(b), static_cast<float *>(c),
+                             len, flags, static_cast<char *>(work), s);
+    return run_tiled_i32(static_cast<const int32_t *>(a), static_cast<const int32_t *>(b), static_cast<int32_t *>(c),
+                         len, flags, static_cast<char *>(work), s);
 }
 
 // ---- reduction dispatch ---------------------------------------------------
@@ -389,10 +448,123 @@ acc_status wait_region(acc_region_s *r)
     return finish_pending(r);
 }
 
+
+// ---- kernel timing (accx_timing_*) ----------------------------------------
+
+struct TimingRec {
+    const char *name;
+    hipEvent_t start, stop;
+};
+
+struct TimingStats {
+    int64_t launches = 0;
+    double total = 0, mn = 1e300, mx = 0;
+};
+
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<TimingRec> pending;
+    int open = -1;
+    std::map<std::string, TimingStats> stats;
+};
+
+Timing &TM()
+{
+    static Timing *t = new Timing();
+    return *t;
+}
+
+hipEvent_t tm_event(Timing &t)
+{
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void tm_collect(Timing &t)
+{
+    for (TimingRec &r : t.pending) {
+        if (r.start && r.stop && hipEventSynchronize(r.stop) == hipSuccess) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+                TimingStats &st = t.stats[r.name];
+                st.launches += 1;
+                st.total += ms;
+                st.mn = std::min(st.mn, (double)ms);
+                st.mx = std::max(st.mx, (double)ms);
+            }
+        }
+        if (r.start) t.pool.push_back(r.start);
+        if (r.stop) t.pool.push_back(r.stop);
+    }
+    t.pending.clear();
+    t.open = -1;
+}
+
 }  // namespace
+
+namespace accx {
+void tmark(const char *name, hipStream_t s, bool begin)
+{
+    Timing &t = TM();
+    if (!t.on) return;
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (begin) {
+        TimingRec r{name, tm_event(t), nullptr};
+        if (r.start) (void)hipEventRecord(r.start, s);
+        t.pending.push_back(r);
+        t.open = (int)t.pending.size() - 1;
+    } else if (t.open >= 0) {
+        TimingRec &r = t.pending[(size_t)t.open];
+        r.stop = tm_event(t);
+        if (r.stop) (void)hipEventRecord(r.stop, s);
+        t.open = -1;
+        if (t.pending.size() > 4096) tm_collect(t);
+    }
+}
+}  // namespace accx
 
 // =========================================================================
 extern "C" {
+
+acc_status accx_timing_enable(int on)
+{
+    Timing &t = TM();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.on = on != 0;
+    return ACC_OK;
+}
+
+acc_status accx_timing_read(accx_kernel_time *out, int cap, int *n_out, int reset)
+{
+    if (!n_out || cap < 0 || (cap > 0 && !out)) return fail(ACC_ERR_INVALID_ARG, "bad output buffer");
+    Timing &t = TM();
+    std::lock_guard<std::mutex> lk(t.mu);
+    tm_collect(t);
+    int n = 0;
+    for (const auto &kv : t.stats) {
+        if (n < cap) {
+            accx_kernel_time &o = out[n];
+            std::memset(&o, 0, sizeof o);
+            std::strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+            o.launches = kv.second.launches;
+            o.total_ms = kv.second.total;
+            o.min_ms = kv.second.launches ? kv.second.mn : 0.0;
+            o.max_ms = kv.second.mx;
+        }
+        ++n;
+    }
+    *n_out = n;
+    if (reset) t.stats.clear();
+    return ACC_OK;
+}
 
 acc_status acc_init(int device, uint64_t hbm_budget_bytes)
 {
@@ -728,6 +900,40 @@ acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const voi
         dWork = w.ptr;
     }
     return run_reduce(t, dX, n, init, dResult, flags, dWork, stream);
+}
+
+acc_status accx_packed_size(acc_dtype t, int64_t rows, int64_t k, int planes, size_t *bytes_out)
+{
+    if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
+    if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
+    if (rows < 1 || k < 1 || rows > 65536 || k > 65536) return fail(ACC_ERR_INVALID_ARG, "rows and k in [1, 65536]");
+    if (t == ACC_FLOAT32 ? planes != 3 : (planes < 1 || planes > 4))
+        return fail(ACC_ERR_INVALID_ARG, "planes: 3 for float32, 1..4 for int32");
+    *bytes_out = accx::packed_bytes(rows, k, t == ACC_FLOAT32 ? 2 : 1, planes);
+    return ACC_OK;
+}
+
+acc_status accx_pack_dev(acc_dtype t, const void *dX, int64_t rows, int64_t k, int transposed, int planes, void *dOut,
+                         size_t out_bytes, void *hip_stream)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    size_t need = 0;
+    if ((s = accx_packed_size(t, rows, k, planes, &need)) != ACC_OK) return s;
+    if (!dX || !dOut) return fail(ACC_ERR_INVALID_ARG, "NULL device pointer");
+    if (out_bytes < need) return fail(ACC_ERR_INVALID_ARG, "output buffer too small");
+    if ((uintptr_t)dX & 3u) return fail(ACC_ERR_INVALID_ARG, "dX must be 4-byte aligned");
+    if ((uintptr_t)dOut & 15u) return fail(ACC_ERR_INVALID_ARG, "dOut must be 16-byte aligned");
+    if ((s = launch_fault()) != ACC_OK) return s;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const hipError_t e =
+        (t == ACC_FLOAT32)
+            ? accx::launch_pack_bf16x3(static_cast<const float *>(dX), rows, k, transposed != 0, dOut, stream)
+            : accx::launch_pack_i8(static_cast<const int32_t *>(dX), rows, k, transposed != 0, planes, dOut, nullptr,
+                                   stream);
+    return check_launch(e, "pack launch");
 }
 
 const char *acc_status_string(acc_status s)

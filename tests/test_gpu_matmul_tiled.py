@@ -1,0 +1,151 @@
+"""Parity of the LDS-tiled matrix-core loop nest (bf16x3 for float32, int8
+limbs for int32) with the CPU oracle and with the plain kernel."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _util import FP32_REL_FRO_TOL, SEED, rel_fro, sample_entries
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 31, 32, 33, 64, 100, 128, 255, 256, 257, 300, 513, 640, 1000]
+
+
+@pytest.fixture(scope="module")
+def ax():
+    import paper_1412_1127_amd as ax
+    ax.acc_init(0, 0)
+    yield ax
+    ax.acc_shutdown()
+
+
+def _run(ax, a, b, flags):
+    import torch
+    n = a.shape[0]
+    dt = ax.ACC_FLOAT32 if a.dtype == np.float32 else ax.ACC_INT32
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    dc = torch.full((n, n), -7, dtype=da.dtype, device="cuda")
+    print("matmul dtype=%s LEN=%d flags=%#x" % (a.dtype, n, flags), flush=True)
+    ax.accx_matmul_dev(dt, da, db, dc, n, flags)
+    torch.cuda.synchronize()
+    return dc.cpu().numpy()
+
+
+def _tiled(ax, prec=None):
+    return ax.ACC_KERNEL_TILED | (ax.ACC_PREC_FULL6 if prec is None else prec)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_f32_full6_parity(ax, n):
+    a = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_A)
+    b = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_B)
+    c = _run(ax, a, b, _tiled(ax))
+    err = rel_fro(c, oracle.matmul_f32(a, b))
+    print("LEN=%d FULL6 rel_fro=%.3g" % (n, err))
+    assert err <= FP32_REL_FRO_TOL
+
+
+@pytest.mark.parametrize("n", [33, 256, 1000])
+def test_f32_cheap3_error_is_bf16_scale(ax, n):
+    # Three products drop terms of relative size ~2^-16; the error is stated,
+    # not held to the float32 bound.
+    a = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_A)
+    b = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_B)
+    err = rel_fro(_run(ax, a, b, _tiled(ax, ax.ACC_PREC_CHEAP3)), oracle.matmul_f32(a, b))
+    print("LEN=%d CHEAP3 rel_fro=%.3g" % (n, err))
+    assert err <= 2.0 ** -12
+
+
+@pytest.mark.parametrize("prec", ["FULL6", "CHEAP3"])
+def test_identity_ones_exact(ax, prec):
+    p = getattr(ax, "ACC_PREC_" + prec)
+    n = 160
+    a = synth.uniform_pm1_f32((n, n), SEED, 5)
+    eye = np.eye(n, dtype=np.float32)
+    if prec == "FULL6":   # hi + mid + lo == a exactly, and 1 * term is exact
+        assert np.array_equal(_run(ax, eye, a, _tiled(ax, p)), a)
+        assert np.array_equal(_run(ax, a, eye, _tiled(ax, p)), a)
+    one = np.ones((n, n), np.float32)
+    assert np.all(_run(ax, one, one, _tiled(ax, p)) == n)
+
+
+@pytest.mark.parametrize("prec", ["FULL6", "CHEAP3"])
+def test_integer_valued_floats_bitwise_equal_int(ax, prec):
+    # |C| <= LEN*256 < 2^24: every partial sum is exact on every path.
+    n = 512
+    ai = synth.int_uniform_i32((n, n), -16, 16, SEED, synth.STREAM_A)
+    bi = synth.int_uniform_i32((n, n), -16, 16, SEED, synth.STREAM_B)
+    cf = _run(ax, ai.astype(np.float32), bi.astype(np.float32), _tiled(ax, getattr(ax, "ACC_PREC_" + prec)))
+    assert np.array_equal(cf, oracle.matmul_i32(ai, bi).astype(np.float32))
+
+
+LIMB_RANGES = {1: 127, 2: 32639, 3: 8355711, 4: None}
+
+
+@pytest.mark.parametrize("limbs", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", [1, 33, 64, 200, 257, 512])
+def test_i32_bit_exact_probe(ax, limbs, n):
+    bound = LIMB_RANGES[limbs]
+    if bound is None:
+        a = synth.full_range_i32((n, n), SEED, synth.STREAM_A)
+        b = synth.full_range_i32((n, n), SEED, synth.STREAM_B)
+    else:
+        a = synth.int_uniform_i32((n, n), -bound, bound, SEED, synth.STREAM_A)
+        b = synth.int_uniform_i32((n, n), -bound, bound, SEED, synth.STREAM_B)
+        a.flat[0] = bound  # the probe must see the extreme
+    ref = oracle.matmul_i32(a, b)
+    assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED), ref)          # limb count by probe
+    assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED | ax.ACC_LIMBS(4)), ref)  # forced 4
+    assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED | ax.ACC_LIMBS(limbs)), ref)
+
+
+def test_i32_wraparound(ax):
+    n = 48
+    a = np.full((n, n), 2 ** 31 - 1, np.int32)
+    b = np.full((n, n), -(2 ** 31), np.int32)
+    a[::3] = -(2 ** 31)
+    assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED), oracle.matmul_i32(a, b))
+
+
+def test_deterministic(ax):
+    n = 777
+    a = synth.uniform_pm1_f32((n, n), SEED, 7)
+    b = synth.uniform_pm1_f32((n, n), SEED, 8)
+    c1 = _run(ax, a, b, _tiled(ax))
+    c2 = _run(ax, a, b, _tiled(ax))
+    assert np.array_equal(c1, c2)
+
+
+def test_scale_4096_vs_oracle_and_plain(ax):
+    # The plain-method-at-scale workload: LEN = 4096, float32 uniform[-1,1]
+    # and int32 in [-16,16]; sampled entries vs the oracle, the whole matrix
+    # vs the plain kernel.
+    n = 4096
+    a = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_A)
+    b = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_B)
+    ct = _run(ax, a, b, _tiled(ax))
+    cp = _run(ax, a, b, ax.ACC_KERNEL_PLAIN)
+    ii, jj = sample_entries(n, 512)
+    ref = oracle.matmul_at(a, b, ii, jj)
+    e_or, e_pl = rel_fro(ct[ii, jj], ref), rel_fro(ct, cp)
+    print("LEN=4096 FULL6 rel_fro vs oracle(sampled)=%.3g vs plain=%.3g plain-vs-oracle=%.3g"
+          % (e_or, e_pl, rel_fro(cp[ii, jj], ref)))
+    assert e_or <= FP32_REL_FRO_TOL and e_pl <= FP32_REL_FRO_TOL
+    ai = synth.int_uniform_i32((n, n), -16, 16, SEED, synth.STREAM_A)
+    bi = synth.int_uniform_i32((n, n), -16, 16, SEED, synth.STREAM_B)
+    ci = _run(ax, ai, bi, ax.ACC_KERNEL_TILED)
+    assert np.array_equal(ci[ii, jj], oracle.matmul_at(ai, bi, ii, jj))
+    assert np.array_equal(ci, _run(ax, ai, bi, ax.ACC_KERNEL_PLAIN))
+
+
+def test_precision_8192_rowscaled(ax):
+    # The precision workload: LEN = 8192, N(0,1) * 2^U(-8,8) per row.
+    n = 8192
+    a = synth.normal_rowscaled_f32(n, n, SEED, synth.STREAM_A)
+    b = synth.normal_rowscaled_f32(n, n, SEED, synth.STREAM_B)
+    c = _run(ax, a, b, _tiled(ax))
+    ii, jj = sample_entries(n, 1024)
+    err = rel_fro(c[ii, jj], oracle.matmul_at(a, b, ii, jj))
+    print("LEN=8192 rowscaled FULL6 rel_fro(sampled)=%.3g" % err)
+    assert err <= FP32_REL_FRO_TOL
