@@ -1,0 +1,266 @@
+"""Benchmark of the offload hot path on one MI355X.
+
+One step is one pass of the whole path over the plain-method-at-scale
+workload: the loop-nest matmul of Listing 1a at LEN = 4096 in float32
+(uniform[-1, 1], LDS-tiled bf16x3 matrix-core kernel) and in int32
+(uniform integers in [-16, 16], int8-limb matrix-core kernel with its max|x|
+probe), then reduction(+) over 2^28 float32 values uniform in [0, 1), on
+device-resident inputs (the data region is opened before the timed region,
+as the data directive keeps arrays on the device across the kernels).
+
+value = matmul operations of the step (2*LEN^3 for each of the two matmuls)
+divided by the wall time of the step, in TFLOP/s; the reduction's time is in
+the step.  Per-kernel durations come from HIP events that the library records
+on the launch stream around each kernel.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
+PEAK_INT8_TOPS = 5000.0     # MI355X dense int8 matrix peak
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def _args():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--len", type=int, default=4096)
+    p.add_argument("--n-reduce", type=int, default=1 << 28)
+    p.add_argument("--prec", choices=["full6", "auto", "cheap3"], default="full6")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-rows", type=int, default=1024,
+                   help="rows of C the CPU baseline computes per matmul (scaled to the whole step)")
+    p.add_argument("--no-verify", action="store_true")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="skip the tile autotuner before the timed region (size heuristic instead)")
+    p.add_argument("--copy-calib", action="store_true",
+                   help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
+    return p.parse_args()
+
+
+def _source_hash(*names) -> str:
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1412_1127_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        e = t[kernel][workload]
+        if e.get("source_hash") != _source_hash("gemm_mfma.hip"):
+            return None
+        return float(e["fetch_bytes"]) + float(e["write_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def main() -> int:
+    args = _args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the offload path here has no multi-GPU form "
+              "(how it would shard is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1412_1127_amd as ax
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    n, nred = args.len, args.n_reduce
+    seed = synth.DEFAULT_SEED
+    prec = {"full6": ax.ACC_PREC_FULL6, "auto": ax.ACC_PREC_AUTO, "cheap3": ax.ACC_PREC_CHEAP3}[args.prec]
+    nprod = {"full6": 6, "auto": 6, "cheap3": 3}[args.prec]
+
+    t_gen = time.time()
+    a = synth.uniform_pm1_f32((n, n), seed, synth.STREAM_A)
+    b = synth.uniform_pm1_f32((n, n), seed, synth.STREAM_B)
+    ai = synth.int_uniform_i32((n, n), -16, 16, seed, synth.STREAM_A)
+    bi = synth.int_uniform_i32((n, n), -16, 16, seed, synth.STREAM_B)
+    x = synth.uniform01_f32(nred, seed, synth.STREAM_X)
+    print("inputs generated in %.1f s" % (time.time() - t_gen), file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    ax.acc_init(0, 0)
+    da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    dai, dbi = torch.from_numpy(ai).to(dev), torch.from_numpy(bi).to(dev)
+    dx = torch.from_numpy(x).to(dev)
+    dc = torch.empty((n, n), dtype=torch.float32, device=dev)
+    dci = torch.empty((n, n), dtype=torch.int32, device=dev)
+    dr = torch.empty(1, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    # Library workspaces, allocated once outside the timed region.
+    f_flags = ax.ACC_KERNEL_TILED | prec
+    i_flags = ax.ACC_KERNEL_TILED
+    wf = torch.empty(ax.accx_matmul_workspace_size(ax.ACC_FLOAT32, n, f_flags), dtype=torch.uint8, device=dev)
+    wi = torch.empty(ax.accx_matmul_workspace_size(ax.ACC_INT32, n, i_flags), dtype=torch.uint8, device=dev)
+    wr = torch.zeros(ax.accx_reduce_workspace_size(ax.ACC_FLOAT32, nred, 0), dtype=torch.uint8, device=dev)
+
+    tuned = {}
+    if not args.no_autotune:
+        tuned["f32"] = ax.accx_autotune(ax.ACC_FLOAT32, n, f_flags)
+        tuned["i32"] = ax.accx_autotune(ax.ACC_INT32, n, ax.ACC_LIMBS(1))
+        print("autotuned tiles:", tuned, file=sys.stderr, flush=True)
+
+    def step():
+        ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, f_flags, wf, wf.numel(), sh)
+        ax.accx_matmul_dev(ax.ACC_INT32, dai, dbi, dci, n, i_flags, wi, wi.numel(), sh)
+        ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, nred, 0.0, dr, 0, wr, wr.numel(), sh)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("warmup done", file=sys.stderr, flush=True)
+
+    ax.accx_timing_enable(True)
+    ax.accx_timing_read(reset=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        step()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ktimes = ax.accx_timing_read(reset=True)
+    ax.accx_timing_enable(False)
+    step_ms = [s.elapsed_time(e) for s, e in ev]
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    print("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
+
+    if args.copy_calib:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    ops = 2.0 * 2.0 * n ** 3
+    value = ops / (ms_per_step * 1e-3) / 1e12
+
+    def kavg(name):
+        v = ktimes.get(name)
+        return (v[1] / v[0]) if v and v[0] else None
+
+    g_ms = kavg("gemm_bf16x3")
+    gi_ms = kavg("gemm_i8")
+    red_ms = kavg("reduce_fast")
+    g_flops = nprod * 2.0 * n ** 3
+    achieved = g_flops / (g_ms * 1e-3) / 1e12 if g_ms else None
+    workload = "len%d" % n
+    roofline = {"kernel": "gemm_bf16x3", "bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                "unit": "TFLOP/s", "frac": (achieved / PEAK_BF16_TFLOPS) if achieved else None,
+                "traffic": _traffic("gemm_bf16x3", workload),
+                "flops_per_launch": g_flops, "avg_ms": g_ms}
+
+    components = {}
+    f32_total = sum(v[1] for k, v in ktimes.items() if "bf16x3" in k) / args.steps
+    components["f32_matmul"] = {"kernels_ms_per_step": f32_total, "gemm_ms": g_ms,
+                                "tflops_fp32_equiv_gemm": 2.0 * n ** 3 / (g_ms * 1e-3) / 1e12 if g_ms else None,
+                                "tflops_fp32_equiv_with_pack": 2.0 * n ** 3 / (f32_total * 1e-3) / 1e12,
+                                "products": nprod}
+    i_total = sum(v[1] for k, v in ktimes.items() if k in ("gemm_i8", "pack_i8")) / args.steps
+    components["i32_matmul"] = {"kernels_ms_per_step": i_total, "gemm_ms": gi_ms,
+                                "tops_int32_equiv_gemm": 2.0 * n ** 3 / (gi_ms * 1e-3) / 1e12 if gi_ms else None,
+                                "frac_int8_peak_gemm": (2.0 * n ** 3 / (gi_ms * 1e-3) / 1e12 / PEAK_INT8_TOPS)
+                                if gi_ms else None}
+    components["reduce"] = {"ms": red_ms, "gbs": 4.0 * nred / (red_ms * 1e-3) / 1e9 if red_ms else None,
+                            "frac_hbm": (4.0 * nred / (red_ms * 1e-3) / 1e9 / PEAK_HBM_GBS) if red_ms else None}
+    components["kernels"] = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "min_ms": v[2], "max_ms": v[3]}
+                             for k, v in ktimes.items()}
+
+    accuracy = {}
+    if not args.no_verify:
+        import oracle
+        g = synth.rng(seed, 99)
+        ii, jj = g.integers(0, n, 2048), g.integers(0, n, 2048)
+        c = dc.cpu().numpy()
+        ref = oracle.matmul_at(a, b, ii, jj)
+        accuracy["f32_rel_fro_vs_oracle_sampled"] = float(np.linalg.norm(c[ii, jj] - ref) / np.linalg.norm(ref))
+        dcp = torch.empty_like(dc)
+        ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dcp, n, ax.ACC_KERNEL_PLAIN, None, 0, sh)
+        torch.cuda.synchronize()
+        cp = dcp.cpu().numpy().astype(np.float64)
+        accuracy["f32_rel_fro_vs_plain"] = float(np.linalg.norm(c - cp) / np.linalg.norm(cp))
+        ci = dci.cpu().numpy()
+        accuracy["i32_bit_exact_sampled"] = bool(np.array_equal(ci[ii, jj], oracle.matmul_at(ai, bi, ii, jj)))
+        sref = oracle.sum_f32(x)
+        accuracy["reduce_rel_err"] = abs(float(dr.item()) - sref) / sref
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rows = min(args.cpu_rows, n)
+        t = time.perf_counter()
+        oracle.matmul_rows(a, b, 0, rows)
+        tf = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.matmul_rows(ai, bi, 0, rows)
+        ti = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.sum_f32(x)
+        tr = time.perf_counter() - t
+        cpu_step_s = (tf + ti) * (n / rows) + tr
+        cpu = {"value": ops / cpu_step_s / 1e12, "unit": "TFLOP/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": "float64 and uint64 oracle on rows 0..%d of both LEN=%d matmuls (scaled by %d/%d) plus the "
+                         "serial float64 sum of all %d values; measured %.1f s" % (rows - 1, n, n, rows, nred,
+                                                                                   tf + ti + tr),
+               "step_s_scaled": cpu_step_s}
+
+    line = {
+        "metric": "matmul TFLOP/s (% MFMA peak) at <=1e-5 rel err vs plain kernel; p50/p99 latency",
+        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (bf16x3 matrix cores, f32 accumulate) + int32 (int8-limb matrix cores)",
+        "data": "synthetic",
+        "config": {"workload": "plain method at scale: LEN=%d square row-major matmul in float32 uniform[-1,1] "
+                               "and int32 uniform [-16,16], plus reduction(+) over %d float32 uniform[0,1)"
+                               % (n, nred),
+                   "len": n, "n_reduce": nred, "precision": args.prec, "seed": seed,
+                   "tiles": {k: {"tile": [t for t, v in ax.TILES.items() if v == tv][0], "tune_ms": ms}
+                             for k, (tv, ms) in tuned.items()}},
+        "latency_ms": {"p50": _pct(step_ms, 50), "p99": _pct(step_ms, 99),
+                       "hmean": len(step_ms) / sum(1.0 / s for s in step_ms)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "components": components,
+        "accuracy": accuracy,
+    }
+    ax.acc_shutdown()
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

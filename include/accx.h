@@ -96,6 +96,16 @@ typedef struct acc_region_s *acc_region; /* opaque */
 #define ACC_LIMBS_MASK 0xF00u
 /* asynchronous completion (acc_reduce_sum): *inout valid after acc_wait */
 #define ACC_ASYNC 0x1000u
+/* tile configuration of the tiled kernel (bits 16..19).  AUTO takes the
+ * autotuner's choice for the size class (see accx_autotune), else a size
+ * heuristic; the others force one configuration. */
+#define ACC_TILE_SHIFT 16
+#define ACC_TILE_MASK 0xF0000u
+#define ACC_TILE_AUTO 0x00000u
+#define ACC_TILE_256 0x10000u     /* 256 x 256 output tile, 8 wavefronts */
+#define ACC_TILE_256x128 0x20000u /* 256 x 128, 4 wavefronts, 2 workgroups/CU */
+#define ACC_TILE_128 0x30000u     /* 128 x 128, 4 wavefronts */
+#define ACC_TILE_64 0x40000u      /* 64 x 64, 4 wavefronts */
 
 /* ---- flags for acc_reduce_sum / accx_reduce_sum_dev --------------------- */
 #define ACC_REDUCE_FAST 0x0u  /* single pass, last-block-done final stage */
@@ -185,6 +195,20 @@ ACCX_API acc_status accx_reduce_workspace_size(acc_dtype t, int64_t n, uint32_t 
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
 ACCX_API acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const void *init, void *dResult,
                                uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
+
+/* ---- autotuner ------------------------------------------------------------
+ * Times every tile configuration of the tiled kernel for (t, len, and the
+ * precision / limb bits of flags) on the current device, on scratch operands
+ * of len x len, and records the fastest for len's size class (len rounded up
+ * to a power of two).  Later tiled calls with ACC_TILE_AUTO in that class use
+ * it.  Allocates and frees its scratch (charged to the budget while held).
+ * best_tile_out: the ACC_TILE_* value chosen; ms_out: its kernel time (both
+ * nullable).  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_autotune(acc_dtype t, int64_t len, uint32_t flags, uint32_t *best_tile_out, double *ms_out);
+/* Write / read the tuned table as text, one line per entry:
+ * "dtype variant size_class tile ms".  Errors: INVALID_ARG (I/O, format). */
+ACCX_API acc_status accx_tune_save(const char *path);
+ACCX_API acc_status accx_tune_load(const char *path);
 
 /* ---- matrix-core operand packing (the prepass of the tiled kernel) -------
  * The tiled kernel reads its operands in a packed layout written by a

@@ -49,6 +49,8 @@ def lib():
             "oracle_matmul_f32": (None, [i64, vp, vp, vp]),
             "oracle_matmul_i32_ijl": (None, [i64, vp, vp, vp]),
             "oracle_matmul_i32": (None, [i64, vp, vp, vp]),
+            "oracle_matmul_f32_rows": (None, [i64, i64, i64, vp, vp, vp]),
+            "oracle_matmul_i32_rows": (None, [i64, i64, i64, vp, vp, vp]),
             "oracle_matmul_f32_at": (None, [i64, vp, vp, i64, vp, vp, vp]),
             "oracle_matmul_i32_at": (None, [i64, vp, vp, i64, vp, vp, vp]),
             "oracle_sum_f32": (f64, [i64, vp, f64]),
@@ -104,6 +106,22 @@ def matmul_i32(a: np.ndarray, b: np.ndarray, literal_order: bool = False) -> np.
     fn = lib().oracle_matmul_i32_ijl if literal_order else lib().oracle_matmul_i32
     fn(n, _p(a), _p(b), _p(c))
     return c
+
+
+def matmul_rows(a: np.ndarray, b: np.ndarray, row0: int, nrows: int) -> np.ndarray:
+    """Rows [row0, row0+nrows) of matmul_f32 / matmul_i32 (same arithmetic)."""
+    if a.dtype == np.float32:
+        n = _square(a, b, np.float32)
+        out = np.empty((nrows, n), dtype=np.float64)
+        fn = lib().oracle_matmul_f32_rows
+    else:
+        n = _square(a, b, np.int32)
+        out = np.empty((nrows, n), dtype=np.int32)
+        fn = lib().oracle_matmul_i32_rows
+    if row0 < 0 or nrows < 0 or row0 + nrows > n:
+        raise IndexError("row range out of bounds")
+    fn(n, int(row0), int(nrows), _p(a), _p(b), _p(out))
+    return out
 
 
 def matmul_at(a: np.ndarray, b: np.ndarray, ii, jj) -> np.ndarray:

@@ -103,6 +103,44 @@ void oracle_matmul_i32(int64_t len, const int32_t *a, const int32_t *b, int32_t 
     }
 }
 
+/* Rows [row0, row0 + nrows) of C only, same arithmetic as the full product
+ * (c holds nrows * len entries): a bounded slice of a large problem. */
+void oracle_matmul_f32_rows(int64_t len, int64_t row0, int64_t nrows, const float *a, const float *b, double *c)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t i = row0 + r;
+        double *crow = c + r * len;
+        for (int64_t j = 0; j < len; ++j) crow[j] = 0.0;
+        for (int64_t l = 0; l < len; ++l) {
+            const double ail = (double)a[i * len + l];
+            const float *brow = b + l * len;
+            for (int64_t j = 0; j < len; ++j) crow[j] += ail * (double)brow[j];
+        }
+    }
+}
+
+void oracle_matmul_i32_rows(int64_t len, int64_t row0, int64_t nrows, const int32_t *a, const int32_t *b,
+                            int32_t *c)
+{
+#pragma omp parallel
+    {
+        uint64_t *acc = (uint64_t *)malloc((size_t)(len > 0 ? len : 1) * sizeof(uint64_t));
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < nrows; ++r) {
+            const int64_t i = row0 + r;
+            for (int64_t j = 0; j < len; ++j) acc[j] = 0;
+            for (int64_t l = 0; l < len; ++l) {
+                const uint64_t ail = (uint64_t)(int64_t)a[i * len + l];
+                const int32_t *brow = b + l * len;
+                for (int64_t j = 0; j < len; ++j) acc[j] += ail * (uint64_t)(int64_t)brow[j];
+            }
+            for (int64_t j = 0; j < len; ++j) c[r * len + j] = (int32_t)(uint32_t)acc[j];
+        }
+        free(acc);
+    }
+}
+
 /* Selected entries only, each by the literal l-ascending loop: for sizes
  * where the full product would take too long on the host. */
 void oracle_matmul_f32_at(int64_t len, const float *a, const float *b, int64_t m,

@@ -42,6 +42,13 @@ ACC_LIMBS_SHIFT = 8
 ACC_ASYNC = 0x1000
 ACC_REDUCE_FAST = 0x0
 ACC_REDUCE_PLAIN = 0x1
+ACC_TILE_SHIFT = 16
+ACC_TILE_AUTO = 0x00000
+ACC_TILE_256 = 0x10000
+ACC_TILE_256x128 = 0x20000
+ACC_TILE_128 = 0x30000
+ACC_TILE_64 = 0x40000
+TILES = {"256": ACC_TILE_256, "256x128": ACC_TILE_256x128, "128": ACC_TILE_128, "64": ACC_TILE_64}
 
 
 def ACC_LIMBS(n: int) -> int:
@@ -90,6 +97,9 @@ _SIGS = {
     "accx_reduce_sum_dev": [ctypes.c_int, _vp, _i64, _vp, _vp, _u32, _vp, _sz, _vp],
     "accx_packed_size": [ctypes.c_int, _i64, _i64, ctypes.c_int, ctypes.POINTER(_sz)],
     "accx_pack_dev": [ctypes.c_int, _vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _sz, _vp],
+    "accx_autotune": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_double)],
+    "accx_tune_save": [ctypes.c_char_p],
+    "accx_tune_load": [ctypes.c_char_p],
     "accx_timing_enable": [ctypes.c_int],
     "accx_timing_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
 }
@@ -252,3 +262,20 @@ def accx_timing_read(reset: bool = False) -> dict:
     _check(_lib.accx_timing_read(buf, cap, ctypes.byref(n), int(bool(reset))), "accx_timing_read")
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms), float(buf[i].min_ms),
                                    float(buf[i].max_ms)) for i in range(min(cap, n.value))}
+
+
+def accx_autotune(dtype: int, length: int, flags: int = 0):
+    """Time every tile configuration for (dtype, length, flags); returns (ACC_TILE_* chosen, ms)."""
+    tile = _u32(0)
+    ms = ctypes.c_double(0)
+    _check(_lib.accx_autotune(int(dtype), int(length), int(flags), ctypes.byref(tile), ctypes.byref(ms)),
+           "accx_autotune")
+    return int(tile.value), float(ms.value)
+
+
+def accx_tune_save(path: str) -> None:
+    _check(_lib.accx_tune_save(os.fsencode(path)), "accx_tune_save")
+
+
+def accx_tune_load(path: str) -> None:
+    _check(_lib.accx_tune_load(os.fsencode(path)), "accx_tune_load")

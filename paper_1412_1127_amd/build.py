@@ -56,6 +56,12 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    # every kernel referenced by host code must have its launch stub
+    nm = subprocess.run(["nm", "-u", tmp], capture_output=True, text=True)
+    missing = [l.split()[-1] for l in nm.stdout.splitlines() if "__device_stub__" in l]
+    if missing:
+        os.unlink(tmp)
+        raise RuntimeError("kernel launch stubs missing from libaccx.so:\n  " + "\n  ".join(missing))
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

@@ -27,6 +27,8 @@
 // conflict-free ds_read_b128 of 1 KB (lane l: row l%32, chunk l/32).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace accx {
@@ -132,10 +134,19 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
         const int64_t row = rb * 32 + r;
         const int64_t k0 = kb * 64 + c * 16;
         int32_t v[16];
+        if (!TRANS && row < R && k0 + 16 <= K && ((K & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
+            const i32x4 *p = reinterpret_cast<const i32x4 *>(X + row * K + k0);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const bool in = row < R && k0 + t < K;
-            v[t] = in ? (TRANS ? X[(k0 + t) * R + row] : X[row * K + k0 + t]) : 0;
+            for (int q = 0; q < 4; ++q) {
+                const i32x4 w4 = p[q];
+                v[4 * q] = w4.x, v[4 * q + 1] = w4.y, v[4 * q + 2] = w4.z, v[4 * q + 3] = w4.w;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const bool in = row < R && k0 + t < K;
+                v[t] = in ? (TRANS ? X[(k0 + t) * R + row] : X[row * K + k0 + t]) : 0;
+            }
         }
         int64_t rem[16];
 #pragma unroll
@@ -162,11 +173,20 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
             const uint32_t t = __shfl_xor(mx, o, 64);
             mx = t > mx ? t : mx;
         }
-        if ((threadIdx.x & 63) == 0) atomicMax(maxabs, mx);
+        // Most wavefronts find the running maximum already as large: skip
+        // the atomic then (one contended address otherwise serialises).
+        if ((threadIdx.x & 63) == 0 && mx > __hip_atomic_load(maxabs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(maxabs, mx);
     }
 }
 
 // ------------------------------------------------------------------- GEMM --
+
+// 16-byte direct global->LDS load of one wavefront: lane l reads 16 bytes at
+// its own `src` and they land at dst + 16*l (dst is wavefront-uniform).
+// Kept out of the kernel templates: the builtin is device-only, and a kernel
+// template that names it directly loses its host launch stub.
+__device__ inline void dma16(const void *src, void *dst) { __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0); }
 
 template <bool INT8> struct Mma;
 template <> struct Mma<false> {
@@ -236,7 +256,23 @@ __device__ inline void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &
     tn = w / gsz;
 }
 
-template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NPROD, uint64_t PL, int NACC>
+// s_waitcnt immediate that waits until at most N vector-memory operations of
+// this wavefront are outstanding (gfx9 encoding: vmcnt[3:0] and [15:14],
+// expcnt and lgkmcnt left at their maxima).
+template <int N> constexpr int vmcnt_imm() { return (N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14); }
+
+// One workgroup computes one BM x BN tile of C with WGM x WGN wavefronts.
+// The K loop runs over K-steps of KBK bytes per row per plane, staged in LDS
+// through an NS-deep ring: the direct-to-LDS loads of step s+NS-1 are in
+// flight while step s is computed.  Every wavefront issues the same number
+// of loads per step (row blocks past the operand are clamped to its last
+// block; those rows of C are never stored), so the wait for step s is a
+// fixed count of younger loads.  A raw s_barrier (no memory fence, which
+// would wait for every load) separates the steps: each wavefront waits for
+// its own loads first, and every LDS read of a step is consumed by a matrix
+// instruction before the wavefront reaches the next barrier, so a buffer is
+// only overwritten after all wavefronts are done reading it.
+template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC>
 __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 {
     using M = Mma<INT8>;
@@ -248,43 +284,50 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
     constexpr int LUNIT = P * 32 * KBK;                // LDS bytes per unit per K-step
     constexpr int CPU = P * KBK / 32;                  // 1 KB copies per unit per K-step
     constexpr int NCOPY = (MB + NB) * CPU;
+    constexpr int LPW = NCOPY / WAVES;                 // loads per wave per K-step
     constexpr int STAGE = (MB + NB) * LUNIT;
     constexpr int SUB = KBK / 32;                      // matrix-core K steps per K-step
     constexpr int HALVES = 64 / KBK;                   // K-steps per 64-byte unit
     static_assert(MB % WGM == 0 && NB % WGN == 0, "tile/wave mismatch");
     static_assert(KBK == 32 || KBK == 64, "K step is 32 or 64 bytes");
+    static_assert(NCOPY % WAVES == 0, "loads must divide evenly over the wavefronts");
+    static_assert(NS >= 2 && LPW * (NS - 2) < 64, "vmcnt range");
+    static_assert(NS * STAGE <= 160 * 1024, "LDS");
 
-    __shared__ __attribute__((aligned(1024))) char lds[2 * STAGE];
+    __shared__ __attribute__((aligned(1024))) char lds[NS * STAGE];
 
     int tm, tn;
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = wave / WGN, wn = wave % WGN;
-    const int64_t ustride_a = (int64_t)P * PLANE_BYTES;  // bytes per packed unit
+    const int64_t ustride = (int64_t)P * PLANE_BYTES;  // bytes per packed unit
     const int64_t rb0 = (int64_t)tm * MB, cb0 = (int64_t)tn * NB;
     const int nsteps = (int)(g.nkb * HALVES);
 
-    auto issue = [&](int step, int buf) {
+    // Per-wave copy descriptors: global unit-row base and LDS offset.
+    const char *src_base[LPW];
+    int dst_off[LPW];
+#pragma unroll
+    for (int c = 0; c < LPW; ++c) {
+        const int q = c * WAVES + wave;
+        const bool isA = q < MB * CPU;
+        const int qq = isA ? q : q - MB * CPU;
+        const int u = qq / CPU, part = qq % CPU;
+        const int p = part / (KBK / 32), piece = part % (KBK / 32);
+        int64_t rb = (isA ? rb0 : cb0) + u;
+        const int64_t nrb = isA ? g.nrb_a : g.nrb_b;
+        if (rb >= nrb) rb = nrb - 1;
+        src_base[c] = (isA ? g.A : g.B) + rb * g.nkb * ustride + p * PLANE_BYTES + piece * 1024 + lane * 16;
+        dst_off[c] = (isA ? 0 : MB * LUNIT) + u * LUNIT + p * (32 * KBK) + piece * 1024;
+    }
+
+    auto issue = [&](int step) {
         const int64_t kb = step / HALVES;
         const int h = step % HALVES;
-        char *sbase = lds + buf * STAGE;
+        char *sbase = lds + (step % NS) * STAGE;
 #pragma unroll
-        for (int q0 = 0; q0 < NCOPY; q0 += WAVES) {
-            const int q = q0 + wave;
-            if (q < NCOPY) {
-                const bool isA = q < MB * CPU;
-                const int qq = isA ? q : q - MB * CPU;
-                const int u = qq / CPU, part = qq % CPU;
-                const int p = part / (KBK / 32), piece = part % (KBK / 32);
-                const int64_t rb = (isA ? rb0 : cb0) + u;
-                if (rb < (isA ? g.nrb_a : g.nrb_b)) {
-                    const char *src = (isA ? g.A : g.B) + (rb * g.nkb + kb) * ustride_a + p * PLANE_BYTES +
-                                      h * (KBK * 32) + piece * 1024 + lane * 16;
-                    char *dst = sbase + (isA ? 0 : MB * LUNIT) + u * LUNIT + p * (32 * KBK) + piece * 1024;
-                    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
-                }
-            }
-        }
+        for (int c = 0; c < LPW; ++c)
+            dma16(src_base[c] + kb * ustride + h * (KBK * 32), sbase + dst_off[c]);
     };
 
     Acc acc[NACC][WBM][WBN];
@@ -295,12 +338,21 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 #pragma unroll
             for (int j = 0; j < WBN; ++j) acc[a][i][j] = (Acc)0;
 
-    issue(0, 0);
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+        if (s < nsteps) issue(s);
+
     for (int step = 0; step < nsteps; ++step) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (step + 1 < nsteps) issue(step + 1, (step + 1) & 1);
-        const char *sA = lds + (step & 1) * STAGE;
+        // stage `step` has landed once at most (younger stages issued) x LPW loads are outstanding
+        if (step + NS - 2 < nsteps)
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 2)>());
+        else
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (step + NS - 1 < nsteps) issue(step + NS - 1);
+        const char *sA = lds + (step % NS) * STAGE;
         const char *sB = sA + MB * LUNIT;
 #pragma unroll
         for (int s = 0; s < SUB; ++s) {
@@ -356,34 +408,77 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 
 // ---------------------------------------------------------- tile configs --
 
-struct Cfg {
-    int bm, bn;
-};
-
-template <bool INT8, int P, int NPROD, uint64_t PL, int NACC>
-hipError_t run_gemm(const Cfg &cfg, GemmArgs g, hipStream_t s)
+// Tile configurations (BM x BN, wavefront grid, K-step bytes, ring depth):
+//  T256     256 x 256, 8 waves (2x4), 32 B (bf16x3) / 64 B (int8), 3 stages:
+//           one workgroup per CU, 144 / 96 KB LDS.
+//  T256x128 256 x 128, 4 waves (2x2), 32 B / 64 B, 2 stages: 72 / 48 KB LDS,
+//           two workgroups per CU that do not share barriers.
+//  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3).
+//  T64       64 x 64,  4 waves (2x2), 64 B, 2 stages (several int8 planes).
+template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC>
+hipError_t launch_tile(GemmArgs g, hipStream_t s)
 {
-    g.tiles_m = (int)((g.M + cfg.bm - 1) / cfg.bm);
-    g.tiles_n = (int)((g.N + cfg.bn - 1) / cfg.bn);
+    g.tiles_m = (int)((g.M + BM - 1) / BM);
+    g.tiles_n = (int)((g.N + BN - 1) / BN);
     const dim3 grid((unsigned)(g.tiles_m * g.tiles_n));
-    if (cfg.bm == 128 && cfg.bn == 128) {
-        hipLaunchKernelGGL((gemm_packed<INT8, P, 128, 128, 64, 2, 2, NPROD, PL, NACC>), grid, dim3(256), 0, s, g);
-    } else if (cfg.bm == 64 && cfg.bn == 64) {
-        hipLaunchKernelGGL((gemm_packed<INT8, P, 64, 64, 64, 2, 2, NPROD, PL, NACC>), grid, dim3(256), 0, s, g);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL((gemm_packed<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC>), grid,
+                       dim3(WGM * WGN * 64), 0, s, g);
     return hipGetLastError();
 }
 
-Cfg choose_cfg(int64_t len, int planes)
+template <bool INT8, int P, int NPROD, uint64_t PL, int NACC>
+hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
 {
-    (void)planes;
-    if (len <= 512) return Cfg{64, 64};
-    return Cfg{128, 128};
+    // Several int8 limb planes need up to 4 accumulator sets: small tiles only.
+    constexpr bool multi = INT8 && P > 1;
+    constexpr int KS = multi ? 64 : (P == 3 ? 32 : 64);  // K-step bytes of the big tiles
+    if (multi) tile = GEMM_TILE_64;
+    switch (tile) {
+    case GEMM_TILE_256:
+        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, multi ? 2 : 4, multi ? 2 : 3, NPROD, PL,
+                           NACC>(g, s);
+    case GEMM_TILE_256x128:
+        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 128, KS, 2, 2, 2, NPROD, PL, NACC>(g, s);
+    case GEMM_TILE_128:
+        return launch_tile<INT8, P, multi ? 64 : 128, multi ? 64 : 128, multi ? 64 : 32, 2, 2, multi ? 2 : 3, NPROD,
+                           PL, NACC>(g, s);
+    default: break;
+    }
+    return launch_tile<INT8, P, 64, 64, 64, 2, 2, 2, NPROD, PL, NACC>(g, s);
+}
+
+int default_tile(int64_t len)
+{
+    if (len <= 512) return GEMM_TILE_64;
+    if (len <= 2048) return GEMM_TILE_128;
+    return GEMM_TILE_256;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Pseudo-random operands for timing runs (not part of any result): a
+// 32-bit integer hash of the element index, mapped to float32 in [-1, 1) or
+// to int32 in [-16, 16].
+__device__ inline uint32_t hash32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void fill_hash(uint32_t *p, int64_t n, int as_int)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const uint32_t h = hash32((uint32_t)i * 2654435761u + 12345u);
+        if (as_int)
+            p[i] = (uint32_t)((int32_t)(h % 33u) - 16);
+        else
+            p[i] = __float_as_uint((float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f);
+    }
+}
 
 __global__ void zero_u32(uint32_t *p, int n)
 {
@@ -403,6 +498,13 @@ unsigned pack_grid(int64_t units)
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_hash, dim3((unsigned)std::min<int64_t>(4096, cdiv(n, 256))), dim3(256), 0, s,
+                       static_cast<uint32_t *>(p), n, as_int ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -445,7 +547,7 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans,
 }
 
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t len, int products, bool accumulate,
-                              hipStream_t s)
+                              int tile, hipStream_t s)
 {
     GemmArgs g{};
     g.A = static_cast<const char *>(pa);
@@ -455,22 +557,22 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t 
     g.nkb = cdiv(len * 2, 64);
     g.nrb_a = g.nrb_b = cdiv(len, 32);
     g.accumulate = accumulate ? 1 : 0;
-    const Cfg cfg = choose_cfg(len, 3);
+    const int t = tile ? tile : default_tile(len);
     hipError_t e;
     tmark("gemm_bf16x3", s, true);
     if (products == 6)
-        e = run_gemm<false, 3, 6, PL_FULL6, 1>(cfg, g, s);
+        e = run_gemm<false, 3, 6, PL_FULL6, 1>(t, g, s);
     else if (products == 3)
-        e = run_gemm<false, 3, 3, PL_CHEAP3, 1>(cfg, g, s);
+        e = run_gemm<false, 3, 3, PL_CHEAP3, 1>(t, g, s);
     else if (products == -3)
-        e = run_gemm<false, 3, 3, PL_CORR3, 1>(cfg, g, s);
+        e = run_gemm<false, 3, 3, PL_CORR3, 1>(t, g, s);
     else
         e = hipErrorInvalidValue;
     tmark("gemm_bf16x3", s, false);
     return e;
 }
 
-hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, hipStream_t s)
+hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s)
 {
     GemmArgs g{};
     g.A = static_cast<const char *>(pa);
@@ -479,14 +581,14 @@ hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t le
     g.M = g.N = g.ldc = len;
     g.nkb = cdiv(len, 64);
     g.nrb_a = g.nrb_b = cdiv(len, 32);
-    const Cfg cfg = choose_cfg(len, limbs);
+    const int t = tile ? tile : default_tile(len);
     hipError_t e;
     tmark("gemm_i8", s, true);
     switch (limbs) {
-    case 1: e = run_gemm<true, 1, 1, PL_L1, 1>(cfg, g, s); break;
-    case 2: e = run_gemm<true, 2, 4, PL_L2, 3>(Cfg{64, 64}, g, s); break;
-    case 3: e = run_gemm<true, 3, 8, PL_L3, 4>(Cfg{64, 64}, g, s); break;
-    case 4: e = run_gemm<true, 4, 10, PL_L4, 4>(Cfg{64, 64}, g, s); break;
+    case 1: e = run_gemm<true, 1, 1, PL_L1, 1>(t, g, s); break;
+    case 2: e = run_gemm<true, 2, 4, PL_L2, 3>(GEMM_TILE_64, g, s); break;
+    case 3: e = run_gemm<true, 3, 8, PL_L3, 4>(GEMM_TILE_64, g, s); break;
+    case 4: e = run_gemm<true, 4, 10, PL_L4, 4>(GEMM_TILE_64, g, s); break;
     default: e = hipErrorInvalidValue;
     }
     tmark("gemm_i8", s, false);

@@ -41,10 +41,15 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans,
 // C (len x len) = sum over the product set of A-plane x B-plane.
 // products: 6 = FULL6, 3 = CHEAP3, -3 = the three products FULL6 adds to
 // CHEAP3.  accumulate: C += instead of C =.
+// tile: one of GEMM_TILE_* (0 = size heuristic).
+enum { GEMM_TILE_DEFAULT = 0, GEMM_TILE_256 = 1, GEMM_TILE_256x128 = 2, GEMM_TILE_128 = 3, GEMM_TILE_64 = 4,
+       GEMM_TILE_COUNT = 5 };
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t len, int products, bool accumulate,
-                              hipStream_t s);
-hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, hipStream_t s);
+                              int tile, hipStream_t s);
+hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
+// n pseudo-random 32-bit words for timing runs: float32 in [-1, 1) or int32 in [-16, 16].
+hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s);
 
 int device_cu_count();  // compute units of the current device (cached)
 

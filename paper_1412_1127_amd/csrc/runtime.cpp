@@ -25,6 +25,7 @@
 #include <new>
 #include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/accx.h"
@@ -266,7 +267,7 @@ acc_status validate_matmul(int t, int64_t len, uint32_t flags)
 {
     if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
     if (len < 1 || len > 65536) return fail(ACC_ERR_INVALID_ARG, "len must be in [1, 65536]");
-    const uint32_t known = ACC_KERNEL_MASK | ACC_PREC_MASK | ACC_LIMBS_MASK | ACC_ASYNC;
+    const uint32_t known = ACC_KERNEL_MASK | ACC_PREC_MASK | ACC_LIMBS_MASK | ACC_ASYNC | ACC_TILE_MASK;
     if (flags & ~known) return fail(ACC_ERR_INVALID_ARG, "unknown flag bits");
     const uint32_t k = flags & ACC_KERNEL_MASK;
     if (k > ACC_KERNEL_TILED) return fail(ACC_ERR_INVALID_ARG, "unknown kernel selector");
@@ -275,6 +276,8 @@ acc_status validate_matmul(int t, int64_t len, uint32_t flags)
         return fail(ACC_ERR_INVALID_ARG, "unknown precision selector");
     const uint32_t nl = (flags & ACC_LIMBS_MASK) >> ACC_LIMBS_SHIFT;
     if (nl > 4) return fail(ACC_ERR_INVALID_ARG, "limb count must be 0 (probe) or 1..4");
+    if (((flags & ACC_TILE_MASK) >> ACC_TILE_SHIFT) >= (uint32_t)accx::GEMM_TILE_COUNT)
+        return fail(ACC_ERR_INVALID_ARG, "unknown tile selector");
     return ACC_OK;
 }
 
@@ -305,6 +308,42 @@ size_t matmul_ws_bytes(int t, int64_t len, uint32_t flags)
     return kMaxabsBytes + 2 * accx::packed_bytes(len, len, 1, nl);
 }
 
+// ---- autotuned tile table -----------------------------------------------
+
+int size_class(int64_t len)
+{
+    int c = 0;
+    while ((int64_t)1 << c < len) ++c;
+    return c;
+}
+
+// Variant of the kernel a tile choice applies to: float products or int limbs.
+int tune_variant(int t, uint32_t flags, int limbs)
+{
+    if (t == ACC_FLOAT32) return (flags & ACC_PREC_MASK) == ACC_PREC_CHEAP3 ? 3 : 6;
+    return limbs;
+}
+
+struct TuneEntry {
+    int tile;
+    double ms;
+};
+
+std::map<std::tuple<int, int, int>, TuneEntry> &tune_table()
+{
+    static auto *t = new std::map<std::tuple<int, int, int>, TuneEntry>();
+    return *t;
+}
+
+int resolve_tile(int t, int64_t len, uint32_t flags, int limbs)
+{
+    const int forced = (int)((flags & ACC_TILE_MASK) >> ACC_TILE_SHIFT);
+    if (forced) return forced;
+    auto &tab = tune_table();
+    auto it = tab.find(std::make_tuple(t, tune_variant(t, flags, limbs), size_class(len)));
+    return it == tab.end() ? 0 : it->second.tile;
+}
+
 acc_status run_tiled_f32(const float *a, const float *b, float *c, int64_t len, uint32_t flags, char *work,
                          hipStream_t s)
 {
@@ -315,7 +354,8 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, int64_t len, 
     if (e != hipSuccess) return fail_hip(e, "pack (bf16x3) launch");
     const uint32_t prec = flags & ACC_PREC_MASK;
     const int products = (prec == ACC_PREC_CHEAP3) ? 3 : 6;
-    e = accx::launch_gemm_bf16x3(pa, pbt, c, len, products, false, s);
+    e = accx::launch_gemm_bf16x3(pa, pbt, c, len, products, false,
+                                 resolve_tile(ACC_FLOAT32, len, flags, 0), s);
     return check_launch(e, "gemm (bf16x3) launch");
 }
 
@@ -339,13 +379,16 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, int64_t
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return fail_hip(e, "max|x| probe readback");
         nl = std::max(limbs_for(m[0]), limbs_for(m[1]));
-        if (nl == 1) return check_launch(accx::launch_gemm_i8(pa, pa + pb1, c, len, 1, s), "gemm (int8) launch");
+        if (nl == 1)
+            return check_launch(accx::launch_gemm_i8(pa, pa + pb1, c, len, 1, resolve_tile(ACC_INT32, len, flags, 1), s),
+                                "gemm (int8) launch");
     }
     const size_t pbn = accx::packed_bytes(len, len, 1, nl);
     e = accx::launch_pack_i8(a, len, len, false, nl, pa, nullptr, s);
     if (e == hipSuccess) e = accx::launch_pack_i8(b, len, len, true, nl, pa + pbn, nullptr, s);
     if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
-    return check_launch(accx::launch_gemm_i8(pa, pa + pbn, c, len, nl, s), "gemm (int8) launch");
+    return check_launch(accx::launch_gemm_i8(pa, pa + pbn, c, len, nl, resolve_tile(ACC_INT32, len, flags, nl), s),
+                        "gemm (int8) launch");
 }
 
 acc_status run_matmul(int t, const void *a, const void *b, void *c, int64_t len, uint32_t flags, void *work,
@@ -934,6 +977,131 @@ acc_status accx_pack_dev(acc_dtype t, const void *dX, int64_t rows, int64_t k, i
             : accx::launch_pack_i8(static_cast<const int32_t *>(dX), rows, k, transposed != 0, planes, dOut, nullptr,
                                    stream);
     return check_launch(e, "pack launch");
+}
+
+acc_status accx_autotune(acc_dtype t, int64_t len, uint32_t flags, uint32_t *best_tile_out, double *ms_out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if ((s = validate_matmul(t, len, flags)) != ACC_OK) return s;
+    const int limbs = (t == ACC_INT32) ? (flag_limbs(flags) ? flag_limbs(flags) : 1) : 0;
+    const size_t mat = (size_t)len * (size_t)len * 4;
+    const size_t pk = (t == ACC_FLOAT32) ? accx::packed_bytes(len, len, 2, 3) : accx::packed_bytes(len, len, 1, limbs);
+    void *x = nullptr, *c = nullptr, *pk2 = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = 0;
+    double best_ms = 1e300;
+    hipError_t he = hipSuccess;
+    if ((s = dev_alloc(&x, mat)) != ACC_OK) goto out;
+    if ((s = dev_alloc(&c, mat)) != ACC_OK) goto out;
+    if ((s = dev_alloc(&pk2, 2 * pk)) != ACC_OK) goto out;
+    if ((he = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking)) != hipSuccess) goto hip_out;
+    if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess) goto hip_out;
+    // Operands: hashed uniform values, float in [-1, 1) or int in [-16, 16]
+    // (one limb); constant operands run the matrix cores at a higher clock
+    // than real data and would mislead the choice.
+    if ((he = accx::launch_fill_hash(x, len * len, t == ACC_INT32, stream)) != hipSuccess) goto hip_out;
+    if (t == ACC_FLOAT32) {
+        he = accx::launch_pack_bf16x3(static_cast<float *>(x), len, len, false, pk2, stream);
+        if (he == hipSuccess)
+            he = accx::launch_pack_bf16x3(static_cast<float *>(x), len, len, true, static_cast<char *>(pk2) + pk, stream);
+    } else {
+        he = accx::launch_pack_i8(static_cast<int32_t *>(x), len, len, false, limbs, pk2, nullptr, stream);
+        if (he == hipSuccess)
+            he = accx::launch_pack_i8(static_cast<int32_t *>(x), len, len, true, limbs, static_cast<char *>(pk2) + pk,
+                                      nullptr, stream);
+    }
+    if (he != hipSuccess) goto hip_out;
+    {
+        // Round-robin over the candidates, several rounds, best per-call time
+        // of each: the first rounds also bring the clocks to their loaded
+        // steady state, so no candidate is timed alone on a cold device.
+        auto run = [&](int tile) {
+            return (t == ACC_FLOAT32)
+                       ? accx::launch_gemm_bf16x3(pk2, static_cast<char *>(pk2) + pk, static_cast<float *>(c), len,
+                                                  tune_variant(t, flags, 0), false, tile, stream)
+                       : accx::launch_gemm_i8(pk2, static_cast<char *>(pk2) + pk, static_cast<int32_t *>(c), len, limbs,
+                                              tile, stream);
+        };
+        const double work = 2.0 * (double)len * (double)len * (double)len;
+        const int reps = (int)std::max<double>(2.0, std::min<double>(50.0, 2e11 / work));
+        const int rounds = 4;
+        std::vector<double> per(accx::GEMM_TILE_COUNT, 1e300);
+        for (int r = 0; r < rounds; ++r) {
+            for (int tile = 1; tile < accx::GEMM_TILE_COUNT; ++tile) {
+                if (limbs > 1 && tile != accx::GEMM_TILE_64) continue;  // several limbs: small tile only
+                if ((he = run(tile)) != hipSuccess) goto hip_out;
+                if ((he = hipEventRecord(e0, stream)) != hipSuccess) goto hip_out;
+                for (int k = 0; k < reps && he == hipSuccess; ++k) he = run(tile);
+                if (he != hipSuccess) goto hip_out;
+                if ((he = hipEventRecord(e1, stream)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess)
+                    goto hip_out;
+                float ms = 0;
+                if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) goto hip_out;
+                if (r > 0) per[tile] = std::min(per[tile], (double)ms / reps);  // round 0 warms up
+            }
+        }
+        for (int tile = 1; tile < accx::GEMM_TILE_COUNT; ++tile)
+            if (per[tile] < best_ms) {
+                best_ms = per[tile];
+                best = tile;
+            }
+    }
+    tune_table()[std::make_tuple((int)t, tune_variant(t, flags, limbs), size_class(len))] = TuneEntry{best, best_ms};
+    if (best_tile_out) *best_tile_out = (uint32_t)best << ACC_TILE_SHIFT;
+    if (ms_out) *ms_out = best_ms;
+    goto out;
+hip_out:
+    s = fail_hip(he, "autotune");
+out:
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (stream) (void)hipStreamDestroy(stream);
+    dev_free(x, mat);
+    dev_free(c, mat);
+    dev_free(pk2, 2 * pk);
+    return s;
+}
+
+acc_status accx_tune_save(const char *path)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!path) return fail(ACC_ERR_INVALID_ARG, "path is NULL");
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(ACC_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    for (const auto &kv : tune_table())
+        std::fprintf(f, "%d %d %d %d %.6f\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                     kv.second.tile, kv.second.ms);
+    std::fclose(f);
+    return ACC_OK;
+}
+
+acc_status accx_tune_load(const char *path)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!path) return fail(ACC_ERR_INVALID_ARG, "path is NULL");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(ACC_ERR_INVALID_ARG, std::string("cannot read ") + path);
+    int dt, var, cls, tile;
+    double ms;
+    int n;
+    acc_status s = ACC_OK;
+    while ((n = std::fscanf(f, "%d %d %d %d %lf", &dt, &var, &cls, &tile, &ms)) == 5) {
+        if (!valid_dtype(dt) || tile < 1 || tile >= accx::GEMM_TILE_COUNT || cls < 0 || cls > 16) {
+            s = fail(ACC_ERR_INVALID_ARG, "bad tune table entry");
+            break;
+        }
+        tune_table()[std::make_tuple(dt, var, cls)] = TuneEntry{tile, ms};
+    }
+    if (s == ACC_OK && n != EOF) s = fail(ACC_ERR_INVALID_ARG, "malformed tune table");
+    std::fclose(f);
+    return s;
 }
 
 const char *acc_status_string(acc_status s)

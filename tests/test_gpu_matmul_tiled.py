@@ -149,3 +149,34 @@ def test_precision_8192_rowscaled(ax):
     err = rel_fro(c[ii, jj], oracle.matmul_at(a, b, ii, jj))
     print("LEN=8192 rowscaled FULL6 rel_fro(sampled)=%.3g" % err)
     assert err <= FP32_REL_FRO_TOL
+
+
+@pytest.mark.parametrize("tile", ["256", "256x128", "128", "64"])
+@pytest.mark.parametrize("n", [100, 257, 1000])
+def test_every_tile_config(ax, tile, n):
+    t = ax.TILES[tile]
+    a = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_A)
+    b = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_B)
+    c = _run(ax, a, b, _tiled(ax) | t)
+    assert rel_fro(c, oracle.matmul_f32(a, b)) <= FP32_REL_FRO_TOL
+    ai = synth.int_uniform_i32((n, n), -16, 16, SEED, synth.STREAM_A)
+    bi = synth.int_uniform_i32((n, n), -16, 16, SEED, synth.STREAM_B)
+    assert np.array_equal(_run(ax, ai, bi, ax.ACC_KERNEL_TILED | t), oracle.matmul_i32(ai, bi))
+
+
+def test_autotune_then_auto_uses_it(ax, tmp_path):
+    n = 640
+    tile, ms = ax.accx_autotune(ax.ACC_FLOAT32, n, ax.ACC_PREC_FULL6)
+    assert tile in ax.TILES.values() and ms > 0
+    a = synth.uniform_pm1_f32((n, n), SEED, 1)
+    b = synth.uniform_pm1_f32((n, n), SEED, 2)
+    auto = _run(ax, a, b, _tiled(ax))
+    forced = _run(ax, a, b, _tiled(ax) | tile)
+    assert np.array_equal(auto, forced)
+    ti, _ = ax.accx_autotune(ax.ACC_INT32, n, ax.ACC_LIMBS(1))
+    assert ti in ax.TILES.values()
+    p = tmp_path / "tune.txt"
+    ax.accx_tune_save(str(p))
+    lines = p.read_text().split("\n")
+    assert any(l.startswith("0 6 10 ") for l in lines)
+    ax.accx_tune_load(str(p))

@@ -168,6 +168,16 @@ def test_sampled_entries_match_full():
         oracle.matmul_at(a, b, [n], [0])
 
 
+def test_row_slices_match_full():
+    n = 61
+    a, b = _rand_f32(n, 76), _rand_f32(n, 77)
+    ai, bi = synth.full_range_i32((n, n), SEED, 78), synth.full_range_i32((n, n), SEED, 79)
+    assert np.array_equal(oracle.matmul_rows(a, b, 10, 17), oracle.matmul_f32(a, b)[10:27])
+    assert np.array_equal(oracle.matmul_rows(ai, bi, 44, 17), oracle.matmul_i32(ai, bi)[44:61])
+    with pytest.raises(IndexError):
+        oracle.matmul_rows(a, b, 50, 20)
+
+
 # --------------------------------------------------------------- matmul i32 --
 
 @pytest.mark.parametrize("n", [1, 2, 4, 8])
