@@ -45,6 +45,8 @@ def _args():
     p.add_argument("--cpu-rows", type=int, default=1024,
                    help="rows of C the CPU baseline computes per matmul (scaled to the whole step)")
     p.add_argument("--no-verify", action="store_true")
+    p.add_argument("--tile", choices=["256", "256x128", "128", "64"], default=None,
+                   help="force the float32 tile configuration (implies --no-autotune)")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the tile autotuner before the timed region (size heuristic instead)")
     p.add_argument("--copy-calib", action="store_true",
@@ -120,14 +122,14 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
     # Library workspaces, allocated once outside the timed region.
-    f_flags = ax.ACC_KERNEL_TILED | prec
+    f_flags = ax.ACC_KERNEL_TILED | prec | (ax.TILES[args.tile] if args.tile else 0)
     i_flags = ax.ACC_KERNEL_TILED
     wf = torch.empty(ax.accx_matmul_workspace_size(ax.ACC_FLOAT32, n, f_flags), dtype=torch.uint8, device=dev)
     wi = torch.empty(ax.accx_matmul_workspace_size(ax.ACC_INT32, n, i_flags), dtype=torch.uint8, device=dev)
     wr = torch.zeros(ax.accx_reduce_workspace_size(ax.ACC_FLOAT32, nred, 0), dtype=torch.uint8, device=dev)
 
     tuned = {}
-    if not args.no_autotune:
+    if not args.no_autotune and not args.tile:
         tuned["f32"] = ax.accx_autotune(ax.ACC_FLOAT32, n, f_flags)
         tuned["i32"] = ax.accx_autotune(ax.ACC_INT32, n, ax.ACC_LIMBS(1))
         print("autotuned tiles:", tuned, file=sys.stderr, flush=True)

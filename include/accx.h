@@ -196,6 +196,82 @@ ACCX_API acc_status accx_reduce_workspace_size(acc_dtype t, int64_t n, uint32_t 
 ACCX_API acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const void *init, void *dResult,
                                uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
 
+/* ---- batched launch --------------------------------------------------------
+ * Many independent float32 loop-nest matmuls and reductions on device
+ * pointers, run by one hipGraph of two kernels: a packing kernel for every
+ * matmul operand, then a persistent kernel whose workgroups take matmul
+ * output tiles and reduction chunks from one shared queue.  A matmul runs
+ * 128 x 128 tiles when its LEN reaches a threshold, else 64 x 64 (or the
+ * tile its flags force); ACC_BATCH_AUTOTUNE picks the threshold by timing
+ * the batch itself, otherwise it is 512.  Matmuls in a batch use the six-product bf16x3 split; a matmul's
+ * result is bitwise that of accx_matmul_dev with ACC_PREC_FULL6 and the same
+ * tile.  Reductions are deterministic (fixed chunking, chunk-order combine). */
+#define ACC_BATCH_MATMUL 0
+#define ACC_BATCH_REDUCE 1
+typedef struct {
+    int32_t kind;  /* ACC_BATCH_MATMUL or ACC_BATCH_REDUCE */
+    int32_t dtype; /* ACC_FLOAT32 */
+    const void *a; /* matmul: device A (n x n); reduce: device x (n elements) */
+    const void *b; /* matmul: device B (n x n); reduce: unused */
+    void *c;       /* matmul: device C (n x n); reduce: device float result */
+    int64_t n;     /* matmul: LEN in [1, 65536]; reduce: element count >= 0 */
+    float init;    /* reduce: result = init + sum */
+    uint32_t flags;/* matmul: ACC_TILE_128, ACC_TILE_64 or ACC_TILE_AUTO */
+} accx_batch_item;
+
+typedef struct accx_batch_s *accx_batch; /* opaque */
+
+#define ACC_BATCH_AUTOTUNE 0x1u /* create: time the tile policies on this batch, keep the fastest */
+
+typedef struct {
+    int64_t units;        /* queue entries: matmul tiles + reduction chunks */
+    int64_t tiles, chunks;
+    int64_t tile_threshold; /* LEN from which un-forced matmuls take 128 x 128 tiles */
+    int32_t workgroups;   /* persistent workgroups */
+    int32_t matmuls, reductions;
+    int32_t pad;
+    uint64_t device_bytes;/* descriptors, packed operands, partials */
+    double flops;         /* sum of 2 n^3 over the matmuls */
+    double mfma_flops;    /* bf16 matrix-core flops actually executed (6 products) */
+    double reduce_bytes;  /* sum of 4 n over the reductions */
+} accx_batch_info_t;
+
+/* Plan a batch: validates the items, picks tiles, allocates the device
+ * workspace (charged to the budget), uploads descriptors and captures the
+ * graph.  The item pointers are baked in: the same arrays are used at every
+ * launch.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t flags, accx_batch *out);
+/* One hipGraphLaunch of the batch on `hip_stream`.  Launches of one batch
+ * must not overlap (they share its queue and workspace). */
+ACCX_API acc_status accx_batch_launch(accx_batch b, void *hip_stream);
+/* The same two kernels launched directly, without the graph. */
+ACCX_API acc_status accx_batch_launch_eager(accx_batch b, void *hip_stream);
+ACCX_API acc_status accx_batch_info(accx_batch b, accx_batch_info_t *out);
+/* Waits for the device, frees the workspace and the graph. */
+ACCX_API acc_status accx_batch_destroy(accx_batch b);
+
+/* ---- float64 error probe (ACC_PREC_AUTO) ----------------------------------
+ * With ACC_PREC_AUTO the float32 tiled matmul runs the three-product split
+ * first, then, per output tile of the tile configuration in use, computes 16
+ * sampled entries (4 rows x 4 columns of the tile, one hashed position in
+ * each quarter) as float64 dot products of the float32 inputs, compares them
+ * with the cheap result and marks the tile when the sampled relative
+ * Frobenius error exceeds 5e-6 (half the 1e-5 bound; the environment variable
+ * ACCX_PROBE_TAU overrides it); a correction pass then adds the three missing
+ * products (hi*lo, lo*hi, mid*mid) to the marked tiles only.  One record per
+ * tile is left in the workspace (row-major tile order) for inspection: */
+typedef struct {
+    int32_t rows[4], cols[4]; /* sampled rows and columns */
+    double ref[16];           /* float64 dot product at (rows[u], cols[v]) in ref[4*u+v] */
+    double err2, ref2;        /* sums over the samples of (C_cheap - ref)^2 and ref^2 */
+    int32_t corrected;        /* 1: the tile received the correction products */
+    int32_t pad[3];
+} accx_probe_record;          /* 192 bytes */
+/* Byte offset of the records inside the workspace of accx_matmul_dev and
+ * their count, for a float32 tiled call with (len, flags), flags carrying
+ * ACC_PREC_AUTO.  Errors: INVALID_ARG. */
+ACCX_API acc_status accx_probe_layout(int64_t len, uint32_t flags, size_t *offset_out, int *count_out);
+
 /* ---- autotuner ------------------------------------------------------------
  * Times every tile configuration of the tiled kernel for (t, len, and the
  * precision / limb bits of flags) on the current device, on scratch operands

@@ -48,6 +48,9 @@ ACC_TILE_256 = 0x10000
 ACC_TILE_256x128 = 0x20000
 ACC_TILE_128 = 0x30000
 ACC_TILE_64 = 0x40000
+ACC_BATCH_MATMUL = 0
+ACC_BATCH_REDUCE = 1
+ACC_BATCH_AUTOTUNE = 0x1
 TILES = {"256": ACC_TILE_256, "256x128": ACC_TILE_256x128, "128": ACC_TILE_128, "64": ACC_TILE_64}
 
 
@@ -64,6 +67,24 @@ class AccxError(RuntimeError):
 class accx_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
+class accx_probe_record(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32 * 4), ("cols", ctypes.c_int32 * 4), ("ref", ctypes.c_double * 16),
+                ("err2", ctypes.c_double), ("ref2", ctypes.c_double), ("corrected", ctypes.c_int32),
+                ("pad", ctypes.c_int32 * 3)]
+
+
+class accx_batch_item(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("n", ctypes.c_int64), ("init", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class accx_batch_info_t(ctypes.Structure):
+    _fields_ = [("units", ctypes.c_int64), ("tiles", ctypes.c_int64), ("chunks", ctypes.c_int64),
+                ("tile_threshold", ctypes.c_int64), ("workgroups", ctypes.c_int32), ("matmuls", ctypes.c_int32), ("reductions", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("device_bytes", ctypes.c_uint64), ("flops", ctypes.c_double),
+                ("mfma_flops", ctypes.c_double), ("reduce_bytes", ctypes.c_double)]
 
 
 class acc_clause(ctypes.Structure):
@@ -97,6 +118,12 @@ _SIGS = {
     "accx_reduce_sum_dev": [ctypes.c_int, _vp, _i64, _vp, _vp, _u32, _vp, _sz, _vp],
     "accx_packed_size": [ctypes.c_int, _i64, _i64, ctypes.c_int, ctypes.POINTER(_sz)],
     "accx_pack_dev": [ctypes.c_int, _vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _sz, _vp],
+    "accx_batch_create": [ctypes.POINTER(accx_batch_item), ctypes.c_int, _u32, ctypes.POINTER(_vp)],
+    "accx_batch_launch": [_vp, _vp],
+    "accx_batch_launch_eager": [_vp, _vp],
+    "accx_batch_info": [_vp, ctypes.POINTER(accx_batch_info_t)],
+    "accx_batch_destroy": [_vp],
+    "accx_probe_layout": [_i64, _u32, ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_int)],
     "accx_autotune": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_double)],
     "accx_tune_save": [ctypes.c_char_p],
     "accx_tune_load": [ctypes.c_char_p],
@@ -279,3 +306,54 @@ def accx_tune_save(path: str) -> None:
 
 def accx_tune_load(path: str) -> None:
     _check(_lib.accx_tune_load(os.fsencode(path)), "accx_tune_load")
+
+
+def accx_probe_layout(length: int, flags: int):
+    """(byte offset of the probe records in the matmul workspace, record count)."""
+    off = _sz(0)
+    cnt = ctypes.c_int(0)
+    _check(_lib.accx_probe_layout(int(length), int(flags), ctypes.byref(off), ctypes.byref(cnt)), "accx_probe_layout")
+    return int(off.value), int(cnt.value)
+
+
+def probe_records(raw: bytes, count: int):
+    """Decode `count` accx_probe_record structs from raw workspace bytes."""
+    size = ctypes.sizeof(accx_probe_record)
+    return [accx_probe_record.from_buffer_copy(raw[i * size:(i + 1) * size]) for i in range(count)]
+
+
+def batch_matmul(a, b, c, length: int, tile: int = 0) -> accx_batch_item:
+    """A float32 matmul item on device arrays (torch tensors or addresses)."""
+    return accx_batch_item(ACC_BATCH_MATMUL, ACC_FLOAT32, _addr(a), _addr(b), _addr(c), int(length), 0.0, int(tile))
+
+
+def batch_reduce(x, n: int, result, init: float = 0.0) -> accx_batch_item:
+    """A float32 reduction item: result = init + sum x[0:n]."""
+    return accx_batch_item(ACC_BATCH_REDUCE, ACC_FLOAT32, _addr(x), None, _addr(result), int(n), float(init), 0)
+
+
+def accx_batch_create(items, flags: int = 0) -> int:
+    arr = (accx_batch_item * max(1, len(items)))(*items)
+    out = _vp(0)
+    _check(_lib.accx_batch_create(arr, len(items), int(flags), ctypes.byref(out)), "accx_batch_create")
+    return int(out.value)
+
+
+def accx_batch_launch(batch: int, stream=None) -> None:
+    _check(_lib.accx_batch_launch(batch, _stream(stream)), "accx_batch_launch")
+
+
+def accx_batch_launch_eager(batch: int, stream=None) -> None:
+    _check(_lib.accx_batch_launch_eager(batch, _stream(stream)), "accx_batch_launch_eager")
+
+
+def accx_batch_info(batch: int) -> dict:
+    info = accx_batch_info_t()
+    _check(_lib.accx_batch_info(batch, ctypes.byref(info)), "accx_batch_info")
+    d = {f: getattr(info, f) for f, _ in accx_batch_info_t._fields_}
+    d["graph_nodes"] = d.pop("pad")
+    return d
+
+
+def accx_batch_destroy(batch: int) -> None:
+    _check(_lib.accx_batch_destroy(batch), "accx_batch_destroy")

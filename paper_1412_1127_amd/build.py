@@ -23,6 +23,7 @@ SOURCES = [
     "matmul_plain.hip",
     "reduce.hip",
     "gemm_mfma.hip",
+    "batch.hip",
 ]
 
 ARCH = "gfx950"

@@ -1,0 +1,196 @@
+// Batched offload: many independent loop-nest matmuls (Listing 1a,
+// section 1.3) and reduction(+) clauses (section 2.3; SRAD paragraph of
+// section 4.2) run as one graph of two kernels:
+//
+//  1. batch_pack: the bf16x3 split of every matmul operand, one grid row per
+//     operand (descriptor table of pack jobs);
+//  2. batch_persistent: a persistent kernel (a fixed number of workgroups per
+//     CU) that pulls work units from one queue through an atomic counter:
+//     either one output tile of one matmul (the same LDS-tiled matrix-core
+//     tile as the standalone kernel, in the tile configuration chosen for
+//     that matmul's size class) or one chunk of one reduction.  The queue
+//     interleaves matmul tiles (largest matmuls first) with reduction chunks
+//     so that HBM-bound and matrix-core-bound work share the CUs.
+//
+// A reduction's chunk partials are combined by the workgroup that finishes
+// its last chunk (atomic ticket), in chunk order, so results do not depend
+// on which workgroup ran what.  A matmul tile is computed by one workgroup in
+// fixed K order, bitwise as by the standalone kernel in the same tile
+// configuration.  The last workgroup to leave resets the queue counters, so
+// the graph can be replayed with no memset node.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "mfma_tile.h"
+
+namespace accx {
+namespace {
+
+using namespace dev;
+
+constexpr int BT = 256;              // threads per workgroup (both kernels)
+constexpr int WG_PER_CU = 2;         // persistent workgroups per CU (LDS: 2 x 72 KB)
+constexpr uint32_t UNIT_RED = 0x80000000u;
+
+// Tile variants the persistent kernel carries: T128 and T64, six products
+// (FULL6).  More variants in one kernel push its register need past the 256
+// that two wavefronts per SIMD allow.
+#define ACCX_T128(NP, PLIST) false, 3, 128, 128, 32, 2, 2, 3, NP, PLIST, 1
+#define ACCX_T64(NP, PLIST) false, 3, 64, 64, 64, 2, 2, 2, NP, PLIST, 1
+
+constexpr int LDS_T128_FULL = gemm_lds_bytes<128, 128, 32, 3, 6, PL_FULL6>();
+constexpr int LDS_T64_FULL = gemm_lds_bytes<64, 64, 64, 2, 6, PL_FULL6>();
+constexpr int LDS_MAX = LDS_T128_FULL > LDS_T64_FULL ? LDS_T128_FULL : LDS_T64_FULL;
+static_assert(LDS_MAX * WG_PER_CU <= 160 * 1024, "persistent kernel LDS");
+
+__global__ __launch_bounds__(BT) void batch_pack(const BatchPackJob *__restrict__ jobs)
+{
+    const BatchPackJob j = jobs[blockIdx.y];
+    const int64_t id0 = (int64_t)blockIdx.x * BT + threadIdx.x, step = (int64_t)gridDim.x * BT;
+    if (j.trans)
+        pack_bf16x3_range<true>(j.x, j.rows, j.k, j.out, j.nrb, j.nkb, id0, step);
+    else
+        pack_bf16x3_range<false>(j.x, j.rows, j.k, j.out, j.nrb, j.nkb, id0, step);
+}
+
+__device__ inline float wave_sum_f(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the workgroup in fixed order; valid in thread 0.
+__device__ inline float block_sum_f(float v, float *red4)
+{
+    v = wave_sum_f(v);
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const float r = (threadIdx.x == 0) ? (red4[0] + red4[1]) + (red4[2] + red4[3]) : 0.0f;
+    __syncthreads();
+    return r;
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __attribute__((always_inline)) inline void reduce_chunk(const BatchRed &r, uint32_t chunk, float *red4, int *is_last)
+{
+    const int64_t b0 = (int64_t)chunk * r.chunk;
+    const int64_t b1 = b0 + r.chunk < r.n ? b0 + r.chunk : r.n;
+    const float *__restrict__ x = r.x;
+    float s = 0.0f;
+    if ((((uintptr_t)(x + b0)) & 15u) == 0) {
+        const int64_t nv = (b1 - b0) >> 2;
+        const f4v *__restrict__ xv = reinterpret_cast<const f4v *>(x + b0);
+        // eight 16-byte loads in flight per thread
+        f4v acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = (f4v)0;
+        int64_t v = threadIdx.x;
+        for (; v + 7 * BT < nv; v += 8 * BT) {
+            f4v t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = __builtin_nontemporal_load(xv + v + u * BT);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += t[u];
+        }
+        for (; v < nv; v += BT) acc[0] += xv[v];
+#pragma unroll
+        for (int w = 4; w > 0; w >>= 1)
+#pragma unroll
+            for (int u = 0; u < w; ++u) acc[u] += acc[u + w];
+        s = (acc[0].x + acc[0].y) + (acc[0].z + acc[0].w);
+        for (int64_t e = b0 + (nv << 2) + threadIdx.x; e < b1; e += BT) s += x[e];
+    } else {
+        for (int64_t e = b0 + threadIdx.x; e < b1; e += BT) s += x[e];
+    }
+    s = block_sum_f(s, red4);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(r.partials + chunk, __float_as_uint(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        *is_last = (atomicAdd(r.ticket, 1u) == (uint32_t)r.nchunks - 1);
+    }
+    __syncthreads();
+    if (!*is_last) return;
+    __threadfence();
+    float t = 0.0f;
+    for (int k = threadIdx.x; k < r.nchunks; k += BT)
+        t += __uint_as_float(__hip_atomic_load(r.partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    t = block_sum_f(t, red4);
+    if (threadIdx.x == 0) {
+        *r.result = r.init + t;
+        __hip_atomic_store(r.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__device__ __attribute__((always_inline)) inline void matmul_unit(const BatchMat &m, uint32_t tile, char *lds)
+{
+    GemmArgs g{};
+    g.A = m.pa;
+    g.B = m.pb;
+    g.C = m.c;
+    g.M = g.N = g.ldc = m.len;
+    g.nkb = m.nkb;
+    g.nrb_a = g.nrb_b = (m.len + 31) / 32;
+    g.tiles_m = m.tiles_m;
+    g.tiles_n = m.tiles_n;
+    const int tm = (int)(tile / (uint32_t)m.tiles_n), tn = (int)(tile % (uint32_t)m.tiles_n);
+    if (m.tile == GEMM_TILE_128)
+        gemm_tile<ACCX_T128(6, PL_FULL6)>(g, tm, tn, lds);
+    else
+        gemm_tile<ACCX_T64(6, PL_FULL6)>(g, tm, tn, lds);
+}
+
+__global__ __launch_bounds__(BT, WG_PER_CU) void batch_persistent(BatchQueue q)
+{
+    __shared__ __attribute__((aligned(1024))) char lds[LDS_MAX];
+    __shared__ uint32_t cur;
+    __shared__ float red4[4];
+    __shared__ int is_last;
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(q.counter, 1u);
+        __syncthreads();
+        const uint32_t u = cur;
+        __syncthreads();  // every thread has read `cur` before it is rewritten
+        if (u >= q.nunits) break;
+        const BatchUnit w = q.units[u];
+        if (w.item & UNIT_RED)
+            reduce_chunk(q.reds[w.item & ~UNIT_RED], w.sub, red4, &is_last);
+        else
+            matmul_unit(q.mats[w.item], w.sub, lds);
+        __syncthreads();  // LDS and shared scalars are reused by the next unit
+    }
+    // The last workgroup out resets the queue for the next launch.
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(q.done, 1u) == gridDim.x - 1) {
+            __hip_atomic_store(q.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(q.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+}  // namespace
+
+int batch_tile_supported(int tile) { return tile == GEMM_TILE_128 || tile == GEMM_TILE_64; }
+
+int batch_workgroups() { return device_cu_count() * WG_PER_CU; }
+
+hipError_t launch_batch_pack(const BatchPackJob *jobs, int njobs, hipStream_t s)
+{
+    if (njobs <= 0) return hipSuccess;
+    tmark("batch_pack", s, true);
+    hipLaunchKernelGGL(batch_pack, dim3(64, (unsigned)njobs), dim3(BT), 0, s, jobs);
+    tmark("batch_pack", s, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_persistent(const BatchQueue &q, hipStream_t s)
+{
+    tmark("batch_persistent", s, true);
+    hipLaunchKernelGGL(batch_persistent, dim3((unsigned)batch_workgroups()), dim3(BT), 0, s, q);
+    tmark("batch_persistent", s, false);
+    return hipGetLastError();
+}
+
+}  // namespace accx

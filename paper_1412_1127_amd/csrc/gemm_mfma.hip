@@ -30,85 +30,22 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "mfma_tile.h"
 
 namespace accx {
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-typedef int i32x16 __attribute__((ext_vector_type(16)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-
-constexpr int PLANE_BYTES = 2048;  // 32 rows x 64 bytes
-
-// ---------------------------------------------------------------- packing --
-
-__device__ inline uint16_t bf16_bits(__bf16 h) { return __builtin_bit_cast(uint16_t, h); }
-
-// x = hi + mid + lo, each term rounded to nearest even bf16 (v_cvt_pk_bf16_f32).
-// x - hi and (x - hi) - mid are exact in float32.
-__device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l)
-{
-    const __bf16 bh = (__bf16)x;
-    const float r1 = x - (float)bh;
-    const __bf16 bm = (__bf16)r1;
-    const float r2 = r1 - (float)bm;
-    h = bf16_bits(bh);
-    m = bf16_bits(bm);
-    l = bf16_bits((__bf16)r2);
-}
+using namespace dev;
 
 // One thread per (unit, row, chunk): 8 consecutive K elements of one row.
-// TRANS = false: X is R x K row-major (operand row r = X row r).
-// TRANS = true:  X is K x R row-major (operand row r = X column r).
 template <bool TRANS>
 __global__ __launch_bounds__(256) void pack_bf16x3(const float *__restrict__ X, int64_t R, int64_t K,
                                                    char *__restrict__ out, int64_t nrb, int64_t nkb)
 {
-    const int64_t total = nrb * nkb * 128;
-    for (int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x; id < total; id += (int64_t)gridDim.x * 256) {
-        const int64_t unit = id >> 7;
-        const int w = (int)(id & 127);
-        int r, c;
-        if (TRANS) {
-            r = w & 31;
-            c = w >> 5;
-        } else {
-            r = w >> 2;
-            c = w & 3;
-        }
-        const int64_t rb = unit / nkb, kb = unit - rb * nkb;
-        const int64_t row = rb * 32 + r;
-        const int64_t k0 = kb * 32 + c * 8;
-        float v[8];
-        if (TRANS) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[(k0 + t) * R + row] : 0.0f;
-        } else if (row < R && k0 + 8 <= K && ((K & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
-            const f32x4 *p = reinterpret_cast<const f32x4 *>(X + row * K + k0);
-            const f32x4 a = p[0], b = p[1];
-            v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
-        } else {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[row * K + k0 + t] : 0.0f;
-        }
-        u16x8 h, m, l;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            uint16_t a, b, d;
-            split3(v[t], a, b, d);
-            h[t] = a;
-            m[t] = b;
-            l[t] = d;
-        }
-        char *u = out + unit * (3 * PLANE_BYTES) + c * 512 + r * 16;
-        *reinterpret_cast<u16x8 *>(u) = h;
-        *reinterpret_cast<u16x8 *>(u + PLANE_BYTES) = m;
-        *reinterpret_cast<u16x8 *>(u + 2 * PLANE_BYTES) = l;
-    }
+    pack_bf16x3_range<TRANS>(X, R, K, out, nrb, nkb, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                             (int64_t)gridDim.x * 256);
 }
+
 
 // int32 -> P balanced base-256 digit planes (int8), 16 K elements per thread.
 // maxabs (optional): running max of |x| over the operand, as uint32.
@@ -180,233 +117,128 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
     }
 }
 
-// ------------------------------------------------------------------- GEMM --
 
-// 16-byte direct global->LDS load of one wavefront: lane l reads 16 bytes at
-// its own `src` and they land at dst + 16*l (dst is wavefront-uniform).
-// Kept out of the kernel templates: the builtin is device-only, and a kernel
-// template that names it directly loses its host launch stub.
-__device__ inline void dma16(const void *src, void *dst) { __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0); }
-
-template <bool INT8> struct Mma;
-template <> struct Mma<false> {
-    using Frag = bf16x8;
-    using Acc = f32x16;
-    __device__ static inline Acc run(Frag a, Frag b, Acc c)
-    {
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-    }
-};
-template <> struct Mma<true> {
-    using Frag = i32x4;
-    using Acc = i32x16;
-    __device__ static inline Acc run(Frag a, Frag b, Acc c)
-    {
-        return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
-    }
-};
-
-// Product list: entry t = (plane of A, plane of B, accumulator) in 6 bits.
-constexpr uint64_t prod(int t, int p, int q, int acc)
-{
-    return (uint64_t)(p | (q << 2) | (acc << 4)) << (6 * t);
-}
-constexpr int prod_p(uint64_t L, int t) { return (int)((L >> (6 * t)) & 3); }
-constexpr int prod_q(uint64_t L, int t) { return (int)((L >> (6 * t + 2)) & 3); }
-constexpr int prod_acc(uint64_t L, int t) { return (int)((L >> (6 * t + 4)) & 3); }
-
-// bf16x3: hi*hi, hi*mid, mid*hi | hi*lo, lo*hi, mid*mid
-constexpr uint64_t PL_CHEAP3 = prod(0, 0, 0, 0) | prod(1, 0, 1, 0) | prod(2, 1, 0, 0);
-constexpr uint64_t PL_FULL6 = PL_CHEAP3 | prod(3, 0, 2, 0) | prod(4, 2, 0, 0) | prod(5, 1, 1, 0);
-constexpr uint64_t PL_CORR3 = prod(0, 0, 2, 0) | prod(1, 2, 0, 0) | prod(2, 1, 1, 0);
-// int8 limbs, accumulator = shift group k+m
-constexpr uint64_t PL_L1 = prod(0, 0, 0, 0);
-constexpr uint64_t PL_L2 = prod(0, 0, 0, 0) | prod(1, 0, 1, 1) | prod(2, 1, 0, 1) | prod(3, 1, 1, 2);
-constexpr uint64_t PL_L3 = prod(0, 0, 0, 0) | prod(1, 0, 1, 1) | prod(2, 1, 0, 1) | prod(3, 0, 2, 2) |
-                           prod(4, 1, 1, 2) | prod(5, 2, 0, 2) | prod(6, 1, 2, 3) | prod(7, 2, 1, 3);
-constexpr uint64_t PL_L4 = PL_L3 | prod(8, 0, 3, 3) | prod(9, 3, 0, 3);
-
-struct GemmArgs {
-    const char *A;  // packed A, P planes
-    const char *B;  // packed B^T, P planes
-    void *C;        // M x N row-major, leading dimension ldc
-    int64_t M, N, ldc;
-    int64_t nkb;     // 64-byte K units per row
-    int64_t nrb_a;   // 32-row blocks present in packed A
-    int64_t nrb_b;   // 32-row blocks present in packed B
-    int tiles_m, tiles_n;
-    int accumulate;  // float: C += result instead of C = result
-};
-
-// Map the linear workgroup id to an output tile.  Workgroups are dealt to
-// the 8 XCDs round-robin; give each XCD a contiguous run of the grouped tile
-// order so that the workgroups sharing an L2 also share A and B tiles.
-__device__ inline void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn)
-{
-    const int T = tiles_m * tiles_n;
-    int t = bid;
-    if ((T & 7) == 0) t = (bid & 7) * (T >> 3) + (bid >> 3);
-    constexpr int GM = 8;
-    const int per_group = GM * tiles_n;
-    const int g = t / per_group;
-    const int first = g * GM;
-    const int gsz = min(tiles_m - first, GM);
-    const int w = t - g * per_group;
-    tm = first + w % gsz;
-    tn = w / gsz;
-}
-
-// s_waitcnt immediate that waits until at most N vector-memory operations of
-// this wavefront are outstanding (gfx9 encoding: vmcnt[3:0] and [15:14],
-// expcnt and lgkmcnt left at their maxima).
-template <int N> constexpr int vmcnt_imm() { return (N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14); }
-
-// One workgroup computes one BM x BN tile of C with WGM x WGN wavefronts.
-// The K loop runs over K-steps of KBK bytes per row per plane, staged in LDS
-// through an NS-deep ring: the direct-to-LDS loads of step s+NS-1 are in
-// flight while step s is computed.  Every wavefront issues the same number
-// of loads per step (row blocks past the operand are clamped to its last
-// block; those rows of C are never stored), so the wait for step s is a
-// fixed count of younger loads.  A raw s_barrier (no memory fence, which
-// would wait for every load) separates the steps: each wavefront waits for
-// its own loads first, and every LDS read of a step is consumed by a matrix
-// instruction before the wavefront reaches the next barrier, so a buffer is
-// only overwritten after all wavefronts are done reading it.
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC>
 __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 {
-    using M = Mma<INT8>;
-    using Frag = typename M::Frag;
-    using Acc = typename M::Acc;
-    constexpr int WAVES = WGM * WGN;
-    constexpr int MB = BM / 32, NB = BN / 32;          // 32-row units per tile
-    constexpr int WBM = MB / WGM, WBN = NB / WGN;      // 32x32 blocks per wave
-    constexpr int LUNIT = P * 32 * KBK;                // LDS bytes per unit per K-step
-    constexpr int CPU = P * KBK / 32;                  // 1 KB copies per unit per K-step
-    constexpr int NCOPY = (MB + NB) * CPU;
-    constexpr int LPW = NCOPY / WAVES;                 // loads per wave per K-step
-    constexpr int STAGE = (MB + NB) * LUNIT;
-    constexpr int SUB = KBK / 32;                      // matrix-core K steps per K-step
-    constexpr int HALVES = 64 / KBK;                   // K-steps per 64-byte unit
-    static_assert(MB % WGM == 0 && NB % WGN == 0, "tile/wave mismatch");
-    static_assert(KBK == 32 || KBK == 64, "K step is 32 or 64 bytes");
-    static_assert(NCOPY % WAVES == 0, "loads must divide evenly over the wavefronts");
-    static_assert(NS >= 2 && LPW * (NS - 2) < 64, "vmcnt range");
-    static_assert(NS * STAGE <= 160 * 1024, "LDS");
-
-    __shared__ __attribute__((aligned(1024))) char lds[NS * STAGE];
-
+    __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPROD, PL>()];
     int tm, tn;
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wm = wave / WGN, wn = wave % WGN;
-    const int64_t ustride = (int64_t)P * PLANE_BYTES;  // bytes per packed unit
-    const int64_t rb0 = (int64_t)tm * MB, cb0 = (int64_t)tn * NB;
-    const int nsteps = (int)(g.nkb * HALVES);
-
-    // Per-wave copy descriptors: global unit-row base and LDS offset.
-    const char *src_base[LPW];
-    int dst_off[LPW];
-#pragma unroll
-    for (int c = 0; c < LPW; ++c) {
-        const int q = c * WAVES + wave;
-        const bool isA = q < MB * CPU;
-        const int qq = isA ? q : q - MB * CPU;
-        const int u = qq / CPU, part = qq % CPU;
-        const int p = part / (KBK / 32), piece = part % (KBK / 32);
-        int64_t rb = (isA ? rb0 : cb0) + u;
-        const int64_t nrb = isA ? g.nrb_a : g.nrb_b;
-        if (rb >= nrb) rb = nrb - 1;
-        src_base[c] = (isA ? g.A : g.B) + rb * g.nkb * ustride + p * PLANE_BYTES + piece * 1024 + lane * 16;
-        dst_off[c] = (isA ? 0 : MB * LUNIT) + u * LUNIT + p * (32 * KBK) + piece * 1024;
-    }
-
-    auto issue = [&](int step) {
-        const int64_t kb = step / HALVES;
-        const int h = step % HALVES;
-        char *sbase = lds + (step % NS) * STAGE;
-#pragma unroll
-        for (int c = 0; c < LPW; ++c)
-            dma16(src_base[c] + kb * ustride + h * (KBK * 32), sbase + dst_off[c]);
-    };
-
-    Acc acc[NACC][WBM][WBN];
-#pragma unroll
-    for (int a = 0; a < NACC; ++a)
-#pragma unroll
-        for (int i = 0; i < WBM; ++i)
-#pragma unroll
-            for (int j = 0; j < WBN; ++j) acc[a][i][j] = (Acc)0;
-
-#pragma unroll
-    for (int s = 0; s < NS - 1; ++s)
-        if (s < nsteps) issue(s);
-
-    for (int step = 0; step < nsteps; ++step) {
-        // stage `step` has landed once at most (younger stages issued) x LPW loads are outstanding
-        if (step + NS - 2 < nsteps)
-            __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 2)>());
-        else
-            __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-        if (step + NS - 1 < nsteps) issue(step + NS - 1);
-        const char *sA = lds + (step % NS) * STAGE;
-        const char *sB = sA + MB * LUNIT;
-#pragma unroll
-        for (int s = 0; s < SUB; ++s) {
-            const int off = (2 * s + (lane >> 5)) * 512 + (lane & 31) * 16;
-            Frag fa[P][WBM], fb[P][WBN];
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-#pragma unroll
-                for (int i = 0; i < WBM; ++i)
-                    fa[p][i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + p * 32 * KBK + off);
-#pragma unroll
-                for (int j = 0; j < WBN; ++j)
-                    fb[p][j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + p * 32 * KBK + off);
-            }
-#pragma unroll
-            for (int t = 0; t < NPROD; ++t) {
-#pragma unroll
-                for (int i = 0; i < WBM; ++i)
-#pragma unroll
-                    for (int j = 0; j < WBN; ++j)
-                        acc[prod_acc(PL, t)][i][j] =
-                            M::run(fa[prod_p(PL, t)][i], fb[prod_q(PL, t)][j], acc[prod_acc(PL, t)][i][j]);
-            }
-        }
-    }
-
-    // Epilogue.  32x32 accumulator layout: register r of lane l holds
-    // row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block.
-#pragma unroll
-    for (int i = 0; i < WBM; ++i)
-#pragma unroll
-        for (int j = 0; j < WBN; ++j) {
-            const int64_t col = ((int64_t)tn * NB + wn * WBN + j) * 32 + (lane & 31);
-            const int64_t rowb = ((int64_t)tm * MB + wm * WBM + i) * 32 + (lane >> 5) * 4;
-            if (col >= g.N) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = rowb + (r >> 2) * 8 + (r & 3);
-                if (row >= g.M) continue;
-                if (INT8) {
-                    uint32_t v = 0;
-#pragma unroll
-                    for (int a = 0; a < NACC; ++a) v += (uint32_t)acc[a][i][j][r] << (8 * a);
-                    static_cast<int32_t *>(g.C)[row * g.ldc + col] = (int32_t)v;
-                } else {
-                    float *cp = static_cast<float *>(g.C) + row * g.ldc + col;
-                    const float v = (float)acc[0][i][j][r];
-                    *cp = g.accumulate ? *cp + v : v;
-                }
-            }
-        }
+    if (g.probe && !g.probe[tm * g.tiles_n + tn].corrected) return;  // whole workgroup: uniform
+    gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC>(g, tm, tn, lds);
 }
 
+
 // ---------------------------------------------------------- tile configs --
+
+// ------------------------------------------------------- float64 probe --
+
+
+// bf16 element (plane p, operand row r, element k) of a packed bf16x3 operand
+// with nkb 64-byte units per row.
+__device__ inline float packed_bf16(const char *base, int64_t nkb, int p, int64_t r, int64_t k)
+{
+    const int64_t unit = (r >> 5) * nkb + (k >> 5);
+    const uint16_t h = *reinterpret_cast<const uint16_t *>(base + unit * (3 * PLANE_BYTES) + p * PLANE_BYTES +
+                                                           ((k & 31) >> 3) * 512 + (r & 31) * 16 + (k & 7) * 2);
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+// The 8 float32 values of elements k8..k8+7 (k8 a multiple of 8) of operand
+// row r, rebuilt exactly in float64 as hi + mid + lo from the three planes.
+__device__ inline void load_exact8(const char *base, int64_t nkb, int64_t r, int64_t k8, double out[8])
+{
+    const int64_t unit = (r >> 5) * nkb + (k8 >> 5);
+    const char *c = base + unit * (3 * PLANE_BYTES) + ((k8 & 31) >> 3) * 512 + (r & 31) * 16;
+    const u16x8 h = *reinterpret_cast<const u16x8 *>(c);
+    const u16x8 m = *reinterpret_cast<const u16x8 *>(c + PLANE_BYTES);
+    const u16x8 l = *reinterpret_cast<const u16x8 *>(c + 2 * PLANE_BYTES);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        out[e] = ((double)__uint_as_float((uint32_t)h[e] << 16) + (double)__uint_as_float((uint32_t)m[e] << 16)) +
+                 (double)__uint_as_float((uint32_t)l[e] << 16);
+}
+
+__device__ inline int probe_pick(int64_t tile, int k, int extent)
+{
+    // k-th quarter of [0, extent), a hashed position inside it
+    const int q = (extent + 3) / 4;
+    const int v = k * q + (int)(hash32((uint32_t)(tile * 8 + k) * 2654435761u + 977u) % (uint32_t)q);
+    return v < extent ? v : extent - 1;
+}
+
+// One workgroup per output tile of the correction GEMM.  It takes 4 rows and
+// 4 columns of the tile (one hashed position in each quarter), computes the
+// 16 dot products in float64 from the exact operands (hi + mid + lo of every
+// element, summed in float64, is the float32 input itself), compares them with
+// the cheap result C, and marks the tile for correction when the sampled
+// relative Frobenius error exceeds tau (or the samples are all zero but C is
+// not).
+__global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, const char *__restrict__ pb,
+                                                 const float *__restrict__ C, int64_t len, int bm, int bn,
+                                                 int tiles_n, int64_t nkb, double tau2, ProbeRecord *__restrict__ rec)
+{
+    __shared__ double part[4][16];
+    const int64_t tile = blockIdx.x;
+    const int tm = (int)(tile / tiles_n), tn = (int)(tile % tiles_n);
+    const int64_t row0 = (int64_t)tm * bm, col0 = (int64_t)tn * bn;
+    const int rext = (int)min<int64_t>(bm, len - row0), cext = (int)min<int64_t>(bn, len - col0);
+    int64_t rows[4], cols[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        rows[k] = row0 + probe_pick(tile, k, rext);
+        cols[k] = col0 + probe_pick(tile, 4 + k, cext);
+    }
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    // one 16-byte chunk (8 consecutive k) per plane and vector per step;
+    // elements past len are zero in the packed operands
+    for (int64_t k8 = (int64_t)threadIdx.x * 8; k8 < len; k8 += 256 * 8) {
+        double av[4][8], bv[4][8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            load_exact8(pa, nkb, rows[u], k8, av[u]);
+            load_exact8(pb, nkb, cols[u], k8, bv[u]);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u * 4 + v] = __builtin_fma(av[u][e], bv[v][e], acc[u * 4 + v]);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ProbeRecord r;
+        double e2 = 0.0, r2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const double ref = (part[0][q] + part[1][q]) + (part[2][q] + part[3][q]);
+            const double c = (double)C[rows[q / 4] * len + cols[q % 4]];
+            r.ref[q] = ref;
+            e2 += (c - ref) * (c - ref);
+            r2 += ref * ref;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            r.rows[k] = (int32_t)rows[k];
+            r.cols[k] = (int32_t)cols[k];
+        }
+        r.err2 = e2;
+        r.ref2 = r2;
+        r.corrected = (r2 > 0.0) ? (e2 > tau2 * r2) : (e2 > 0.0);
+        r.pad[0] = r.pad[1] = r.pad[2] = 0;
+        rec[tile] = r;
+    }
+}
 
 // Tile configurations (BM x BN, wavefront grid, K-step bytes, ring depth):
 //  T256     256 x 256, 8 waves (2x4), 32 B (bf16x3) / 64 B (int8), 3 stages:
@@ -459,15 +291,6 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Pseudo-random operands for timing runs (not part of any result): a
 // 32-bit integer hash of the element index, mapped to float32 in [-1, 1) or
 // to int32 in [-16, 16].
-__device__ inline uint32_t hash32(uint32_t x)
-{
-    x ^= x >> 16;
-    x *= 0x7feb352dU;
-    x ^= x >> 15;
-    x *= 0x846ca68bU;
-    x ^= x >> 16;
-    return x;
-}
 
 __global__ void fill_hash(uint32_t *p, int64_t n, int as_int)
 {
@@ -546,8 +369,35 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans,
     return hipGetLastError();
 }
 
+void tile_dims(int tile, int64_t len, int &bm, int &bn)
+{
+    const int t = tile ? tile : default_tile(len);
+    bm = t == GEMM_TILE_256 || t == GEMM_TILE_256x128 ? 256 : t == GEMM_TILE_128 ? 128 : 64;
+    bn = t == GEMM_TILE_256 ? 256 : t == GEMM_TILE_256x128 ? 128 : bm;
+}
+
+hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, int64_t len, int tile, double tau,
+                            ProbeRecord *rec, hipStream_t s)
+{
+    int bm, bn;
+    tile_dims(tile, len, bm, bn);
+    const int tiles_m = (int)cdiv(len, bm), tiles_n = (int)cdiv(len, bn);
+    tmark("probe_f64", s, true);
+    hipLaunchKernelGGL(probe_f64, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s, static_cast<const char *>(pa),
+                       static_cast<const char *>(pb), c, len, bm, bn, tiles_n, cdiv(len * 2, 64), tau * tau, rec);
+    tmark("probe_f64", s, false);
+    return hipGetLastError();
+}
+
+int probe_tiles(int tile, int64_t len)
+{
+    int bm, bn;
+    tile_dims(tile, len, bm, bn);
+    return (int)(cdiv(len, bm) * cdiv(len, bn));
+}
+
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t len, int products, bool accumulate,
-                              int tile, hipStream_t s)
+                              int tile, hipStream_t s, const ProbeRecord *probe)
 {
     GemmArgs g{};
     g.A = static_cast<const char *>(pa);
@@ -557,6 +407,7 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t 
     g.nkb = cdiv(len * 2, 64);
     g.nrb_a = g.nrb_b = cdiv(len, 32);
     g.accumulate = accumulate ? 1 : 0;
+    g.probe = probe;
     const int t = tile ? tile : default_tile(len);
     hipError_t e;
     tmark("gemm_bf16x3", s, true);

@@ -44,12 +44,65 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans,
 // tile: one of GEMM_TILE_* (0 = size heuristic).
 enum { GEMM_TILE_DEFAULT = 0, GEMM_TILE_256 = 1, GEMM_TILE_256x128 = 2, GEMM_TILE_128 = 3, GEMM_TILE_64 = 4,
        GEMM_TILE_COUNT = 5 };
+// Per-tile record of the float64 error probe (layout documented in accx.h).
+struct ProbeRecord {
+    int32_t rows[4], cols[4];  // sampled rows and columns of the tile
+    double ref[16];            // float64 dot products, ref[4*u + v] at (rows[u], cols[v])
+    double err2, ref2;         // sum over the samples of (C - ref)^2 and of ref^2
+    int32_t corrected;         // 1 if the tile got the three correction products
+    int32_t pad[3];
+};
+static_assert(sizeof(ProbeRecord) == 192, "probe record layout");
+
+// probe: non-null = skip the tiles whose record has corrected == 0.
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t len, int products, bool accumulate,
-                              int tile, hipStream_t s);
+                              int tile, hipStream_t s, const ProbeRecord *probe = nullptr);
+// Float64 probe of C (len x len) per output tile of `tile`; tau: relative
+// Frobenius threshold above which a tile is marked for correction.
+hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, int64_t len, int tile, double tau,
+                            ProbeRecord *rec, hipStream_t s);
+int probe_tiles(int tile, int64_t len);
 hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
 // n pseudo-random 32-bit words for timing runs: float32 in [-1, 1) or int32 in [-16, 16].
 hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s);
+
+// ---- batched launch (batch.hip) -------------------------------------------
+struct BatchPackJob {   // one bf16x3 operand to pack
+    const float *x;
+    char *out;
+    int64_t rows, k, nrb, nkb;
+    int32_t trans, pad;
+};
+struct BatchMat {       // one matmul: packed operands, output, tiling
+    const char *pa, *pb;
+    float *c;
+    int64_t len, nkb;
+    int32_t tile, tiles_m, tiles_n, products;
+};
+struct BatchRed {       // one reduction: input, chunking, result slot
+    const float *x;
+    float *result;
+    uint32_t *ticket;   // zero before the first launch; left at zero
+    uint32_t *partials; // nchunks words
+    int64_t n, chunk;
+    int32_t nchunks;
+    float init;
+};
+struct BatchUnit {      // item index (top bit set: reduction), tile or chunk
+    uint32_t item, sub;
+};
+struct BatchQueue {
+    const BatchMat *mats;
+    const BatchRed *reds;
+    const BatchUnit *units;
+    uint32_t nunits;
+    uint32_t *counter, *done;  // zero before the first launch; left at zero
+};
+int batch_tile_supported(int tile);
+int batch_workgroups();
+hipError_t launch_batch_pack(const BatchPackJob *jobs, int njobs, hipStream_t s);
+hipError_t launch_batch_persistent(const BatchQueue &q, hipStream_t s);
 
 int device_cu_count();  // compute units of the current device (cached)
 

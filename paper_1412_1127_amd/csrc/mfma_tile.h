@@ -1,0 +1,360 @@
+// Device-side building blocks shared by the tiled matmul kernels
+// (gemm_mfma.hip) and the persistent batch kernel (batch.hip): the bf16x3
+// split, the packed operand layout, and the LDS-tiled matrix-core tile.
+// Device functions and constants only; the kernels live in the .hip files.
+//
+// Packed operand layout.  An operand of R rows of K elements (A: rows of A;
+// B: columns of B, i.e. rows of B^T) with P planes is cut into units of 32
+// rows x 64 bytes of each plane.  Unit (rb, kb) starts at byte
+// (rb*nkb + kb) * P * 2048; inside it, plane p, 16-byte chunk c (0..3) of
+// row r (0..31) is at p*2048 + c*512 + r*16.  Rows >= R and elements >= K
+// are zero.  The layout makes every global->LDS copy a contiguous 1 KB block
+// (one direct-to-LDS dwordx4 load per wavefront) and every matrix-core
+// operand fetch a conflict-free ds_read_b128 of 1 KB (lane l: row l%32,
+// chunk l/32).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace accx {
+namespace dev {
+
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int PLANE_BYTES = 2048;  // 32 rows x 64 bytes
+
+// ---------------------------------------------------------------- packing --
+
+__device__ inline uint16_t bf16_bits(__bf16 h) { return __builtin_bit_cast(uint16_t, h); }
+
+// x = hi + mid + lo, each term rounded to nearest even bf16 (v_cvt_pk_bf16_f32).
+// x - hi and (x - hi) - mid are exact in float32.
+__device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l)
+{
+    const __bf16 bh = (__bf16)x;
+    const float r1 = x - (float)bh;
+    const __bf16 bm = (__bf16)r1;
+    const float r2 = r1 - (float)bm;
+    h = bf16_bits(bh);
+    m = bf16_bits(bm);
+    l = bf16_bits((__bf16)r2);
+}
+
+// One thread per (unit, row, chunk): 8 consecutive K elements of one row.
+// TRANS = false: X is R x K row-major (operand row r = X row r).
+// TRANS = true:  X is K x R row-major (operand row r = X column r).
+// Work items id0, id0 + step, ... of one operand (128 items per unit).
+template <bool TRANS>
+__device__ __attribute__((always_inline)) inline void pack_bf16x3_range(const float *__restrict__ X, int64_t R,
+                                                                        int64_t K, char *__restrict__ out,
+                                                                        int64_t nrb, int64_t nkb, int64_t id0,
+                                                                        int64_t step)
+{
+    const int64_t total = nrb * nkb * 128;
+    for (int64_t id = id0; id < total; id += step) {
+        const int64_t unit = id >> 7;
+        const int w = (int)(id & 127);
+        int r, c;
+        if (TRANS) {
+            r = w & 31;
+            c = w >> 5;
+        } else {
+            r = w >> 2;
+            c = w & 3;
+        }
+        const int64_t rb = unit / nkb, kb = unit - rb * nkb;
+        const int64_t row = rb * 32 + r;
+        const int64_t k0 = kb * 32 + c * 8;
+        float v[8];
+        if (TRANS) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[(k0 + t) * R + row] : 0.0f;
+        } else if (row < R && k0 + 8 <= K && ((K & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
+            const f32x4 *p = reinterpret_cast<const f32x4 *>(X + row * K + k0);
+            const f32x4 a = p[0], b = p[1];
+            v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[row * K + k0 + t] : 0.0f;
+        }
+        u16x8 h, m, l;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            uint16_t a, b, d;
+            split3(v[t], a, b, d);
+            h[t] = a;
+            m[t] = b;
+            l[t] = d;
+        }
+        char *u = out + unit * (3 * PLANE_BYTES) + c * 512 + r * 16;
+        *reinterpret_cast<u16x8 *>(u) = h;
+        *reinterpret_cast<u16x8 *>(u + PLANE_BYTES) = m;
+        *reinterpret_cast<u16x8 *>(u + 2 * PLANE_BYTES) = l;
+    }
+}
+
+// ------------------------------------------------------------------- GEMM --
+
+// 16-byte direct global->LDS load of one wavefront: lane l reads 16 bytes at
+// its own `src` and they land at dst + 16*l (dst is wavefront-uniform).
+// Kept out of the kernel templates: the builtin is device-only, and a kernel
+// template that names it directly loses its host launch stub.
+__device__ inline void dma16(const void *src, void *dst) { __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0); }
+
+template <bool INT8> struct Mma;
+template <> struct Mma<false> {
+    using Frag = bf16x8;
+    using Acc = f32x16;
+    __device__ static inline Acc run(Frag a, Frag b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mma<true> {
+    using Frag = i32x4;
+    using Acc = i32x16;
+    __device__ static inline Acc run(Frag a, Frag b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+    }
+};
+
+// Product list: entry t = (plane of A, plane of B, accumulator) in 6 bits.
+constexpr uint64_t prod(int t, int p, int q, int acc)
+{
+    return (uint64_t)(p | (q << 2) | (acc << 4)) << (6 * t);
+}
+constexpr int prod_p(uint64_t L, int t) { return (int)((L >> (6 * t)) & 3); }
+constexpr int prod_q(uint64_t L, int t) { return (int)((L >> (6 * t + 2)) & 3); }
+constexpr int prod_acc(uint64_t L, int t) { return (int)((L >> (6 * t + 4)) & 3); }
+
+// bf16x3: hi*hi, hi*mid, mid*hi | hi*lo, lo*hi, mid*mid
+constexpr uint64_t PL_CHEAP3 = prod(0, 0, 0, 0) | prod(1, 0, 1, 0) | prod(2, 1, 0, 0);
+constexpr uint64_t PL_FULL6 = PL_CHEAP3 | prod(3, 0, 2, 0) | prod(4, 2, 0, 0) | prod(5, 1, 1, 0);
+constexpr uint64_t PL_CORR3 = prod(0, 0, 2, 0) | prod(1, 2, 0, 0) | prod(2, 1, 1, 0);
+// int8 limbs, accumulator = shift group k+m
+constexpr uint64_t PL_L1 = prod(0, 0, 0, 0);
+constexpr uint64_t PL_L2 = prod(0, 0, 0, 0) | prod(1, 0, 1, 1) | prod(2, 1, 0, 1) | prod(3, 1, 1, 2);
+constexpr uint64_t PL_L3 = prod(0, 0, 0, 0) | prod(1, 0, 1, 1) | prod(2, 1, 0, 1) | prod(3, 0, 2, 2) |
+                           prod(4, 1, 1, 2) | prod(5, 2, 0, 2) | prod(6, 1, 2, 3) | prod(7, 2, 1, 3);
+constexpr uint64_t PL_L4 = PL_L3 | prod(8, 0, 3, 3) | prod(9, 3, 0, 3);
+
+// Planes a product list touches: 1 + the largest plane index on either side.
+constexpr int planes_used(uint64_t L, int nprod)
+{
+    int m = 0;
+    for (int t = 0; t < nprod; ++t) {
+        m = prod_p(L, t) > m ? prod_p(L, t) : m;
+        m = prod_q(L, t) > m ? prod_q(L, t) : m;
+    }
+    return m + 1;
+}
+
+struct GemmArgs {
+    const char *A;  // packed A, P planes
+    const char *B;  // packed B^T, P planes
+    void *C;        // M x N row-major, leading dimension ldc
+    int64_t M, N, ldc;
+    int64_t nkb;     // 64-byte K units per row
+    int64_t nrb_a;   // 32-row blocks present in packed A
+    int64_t nrb_b;   // 32-row blocks present in packed B
+    int tiles_m, tiles_n;
+    int accumulate;  // float: C += result instead of C = result
+    const ProbeRecord *probe;  // non-null: skip tiles whose record says no correction
+};
+
+// Map the linear workgroup id to an output tile.  Workgroups are dealt to
+// the 8 XCDs round-robin; give each XCD a contiguous run of the grouped tile
+// order so that the workgroups sharing an L2 also share A and B tiles.
+__device__ inline void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &tn)
+{
+    const int T = tiles_m * tiles_n;
+    int t = bid;
+    if ((T & 7) == 0) t = (bid & 7) * (T >> 3) + (bid >> 3);
+    constexpr int GM = 8;
+    const int per_group = GM * tiles_n;
+    const int g = t / per_group;
+    const int first = g * GM;
+    const int gsz = min(tiles_m - first, GM);
+    const int w = t - g * per_group;
+    tm = first + w % gsz;
+    tn = w / gsz;
+}
+
+// s_waitcnt immediate that waits until at most N vector-memory operations of
+// this wavefront are outstanding (gfx9 encoding: vmcnt[3:0] and [15:14],
+// expcnt and lgkmcnt left at their maxima).
+template <int N> constexpr int vmcnt_imm() { return (N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14); }
+
+// One workgroup computes the BM x BN tile (tm, tn) of C with WGM x WGN
+// wavefronts, staging operands in `lds` (gemm_lds_bytes bytes, 1 KB aligned).
+// The K loop runs over K-steps of KBK bytes per row per plane, staged in LDS
+// through an NS-deep ring: the direct-to-LDS loads of step s+NS-1 are in
+// flight while step s is computed.  Every wavefront issues the same number
+// of loads per step (row blocks past the operand are clamped to its last
+// block; those rows of C are never stored), so the wait for step s is a
+// fixed count of younger loads.  A raw s_barrier (no memory fence, which
+// would wait for every load) separates the steps: each wavefront waits for
+// its own loads first, and every LDS read of a step is consumed by a matrix
+// instruction before the wavefront reaches the next barrier, so a buffer is
+// only overwritten after all wavefronts are done reading it.
+// LDS bytes the tile needs: NS stages of (BM + BN)/32 units of NPL planes.
+template <int BM, int BN, int KBK, int NS, int NPROD, uint64_t PL>
+constexpr int gemm_lds_bytes()
+{
+    return NS * (BM / 32 + BN / 32) * planes_used(PL, NPROD) * 32 * KBK;
+}
+
+template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC>
+__device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &g, int tm, int tn, char *lds)
+{
+    using M = Mma<INT8>;
+    using Frag = typename M::Frag;
+    using Acc = typename M::Acc;
+    constexpr int WAVES = WGM * WGN;
+    constexpr int NPL = planes_used(PL, NPROD);        // planes staged in LDS (<= P)
+    constexpr int MB = BM / 32, NB = BN / 32;          // 32-row units per tile
+    constexpr int WBM = MB / WGM, WBN = NB / WGN;      // 32x32 blocks per wave
+    constexpr int LUNIT = NPL * 32 * KBK;              // LDS bytes per unit per K-step
+    constexpr int CPU = NPL * KBK / 32;                // 1 KB copies per unit per K-step
+    constexpr int NCOPY = (MB + NB) * CPU;
+    constexpr int LPW = NCOPY / WAVES;                 // loads per wave per K-step
+    constexpr int STAGE = (MB + NB) * LUNIT;
+    constexpr int SUB = KBK / 32;                      // matrix-core K steps per K-step
+    constexpr int HALVES = 64 / KBK;                   // K-steps per 64-byte unit
+    static_assert(MB % WGM == 0 && NB % WGN == 0, "tile/wave mismatch");
+    static_assert(KBK == 32 || KBK == 64, "K step is 32 or 64 bytes");
+    static_assert(NCOPY % WAVES == 0, "loads must divide evenly over the wavefronts");
+    static_assert(NS >= 2 && LPW * (NS - 2) < 64, "vmcnt range");
+    static_assert(NS * STAGE <= 160 * 1024, "LDS");
+    static_assert(NPL <= P, "product list names a plane the operand lacks");
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int64_t ustride = (int64_t)P * PLANE_BYTES;  // bytes per packed unit
+    const int64_t rb0 = (int64_t)tm * MB, cb0 = (int64_t)tn * NB;
+    const int nsteps = (int)(g.nkb * HALVES);
+
+    // Per-wave copy descriptors: global unit-row base and LDS offset.
+    const char *src_base[LPW];
+    int dst_off[LPW];
+#pragma unroll
+    for (int c = 0; c < LPW; ++c) {
+        const int q = c * WAVES + wave;
+        const bool isA = q < MB * CPU;
+        const int qq = isA ? q : q - MB * CPU;
+        const int u = qq / CPU, part = qq % CPU;
+        const int p = part / (KBK / 32), piece = part % (KBK / 32);
+        int64_t rb = (isA ? rb0 : cb0) + u;
+        const int64_t nrb = isA ? g.nrb_a : g.nrb_b;
+        if (rb >= nrb) rb = nrb - 1;
+        src_base[c] = (isA ? g.A : g.B) + rb * g.nkb * ustride + p * PLANE_BYTES + piece * 1024 + lane * 16;
+        dst_off[c] = (isA ? 0 : MB * LUNIT) + u * LUNIT + p * (32 * KBK) + piece * 1024;
+    }
+
+    auto issue = [&](int step) {
+        const int64_t kb = step / HALVES;
+        const int h = step % HALVES;
+        char *sbase = lds + (step % NS) * STAGE;
+#pragma unroll
+        for (int c = 0; c < LPW; ++c)
+            dma16(src_base[c] + kb * ustride + h * (KBK * 32), sbase + dst_off[c]);
+    };
+
+    Acc acc[NACC][WBM][WBN];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int i = 0; i < WBM; ++i)
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) acc[a][i][j] = (Acc)0;
+
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+        if (s < nsteps) issue(s);
+
+    for (int step = 0; step < nsteps; ++step) {
+        // stage `step` has landed once at most (younger stages issued) x LPW loads are outstanding
+        if (step + NS - 2 < nsteps)
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 2)>());
+        else
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (step + NS - 1 < nsteps) issue(step + NS - 1);
+        const char *sA = lds + (step % NS) * STAGE;
+        const char *sB = sA + MB * LUNIT;
+#pragma unroll
+        for (int s = 0; s < SUB; ++s) {
+            const int off = (2 * s + (lane >> 5)) * 512 + (lane & 31) * 16;
+            Frag fa[NPL][WBM], fb[NPL][WBN];
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) {
+#pragma unroll
+                for (int i = 0; i < WBM; ++i)
+                    fa[p][i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + p * 32 * KBK + off);
+#pragma unroll
+                for (int j = 0; j < WBN; ++j)
+                    fb[p][j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + p * 32 * KBK + off);
+            }
+#pragma unroll
+            for (int t = 0; t < NPROD; ++t) {
+#pragma unroll
+                for (int i = 0; i < WBM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WBN; ++j)
+                        acc[prod_acc(PL, t)][i][j] =
+                            M::run(fa[prod_p(PL, t)][i], fb[prod_q(PL, t)][j], acc[prod_acc(PL, t)][i][j]);
+            }
+        }
+    }
+
+    // Epilogue.  32x32 accumulator layout: register r of lane l holds
+    // row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block.
+#pragma unroll
+    for (int i = 0; i < WBM; ++i)
+#pragma unroll
+        for (int j = 0; j < WBN; ++j) {
+            const int64_t col = ((int64_t)tn * NB + wn * WBN + j) * 32 + (lane & 31);
+            const int64_t rowb = ((int64_t)tm * MB + wm * WBM + i) * 32 + (lane >> 5) * 4;
+            if (col >= g.N) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = rowb + (r >> 2) * 8 + (r & 3);
+                if (row >= g.M) continue;
+                if (INT8) {
+                    uint32_t v = 0;
+#pragma unroll
+                    for (int a = 0; a < NACC; ++a) v += (uint32_t)acc[a][i][j][r] << (8 * a);
+                    static_cast<int32_t *>(g.C)[row * g.ldc + col] = (int32_t)v;
+                } else {
+                    float *cp = static_cast<float *>(g.C) + row * g.ldc + col;
+                    const float v = (float)acc[0][i][j][r];
+                    *cp = g.accumulate ? *cp + v : v;
+                }
+            }
+        }
+}
+
+// 32-bit integer hash (timing operands, probe positions).
+__device__ inline uint32_t hash32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+}  // namespace dev
+}  // namespace accx

@@ -89,6 +89,9 @@ namespace {
 
 constexpr int kMaxSlots = 256;
 
+std::set<accx_batch_s *> &batches();  // open batches (defined with the batch code)
+void batch_release(accx_batch_s *b);
+
 struct State {
     std::recursive_mutex mu;
     bool init = false;
@@ -300,9 +303,33 @@ int limbs_for(uint32_t m)
     return 4;
 }
 
+// ACC_PREC_AUTO: relative Frobenius error a tile may show on the probe's
+// samples and still keep the cheap (three-product) result: half the 1e-5
+// bound the float32 path is held to (ACCX_PROBE_TAU overrides).
+double probe_tau()
+{
+    static double tau = [] {
+        const char *e = std::getenv("ACCX_PROBE_TAU");
+        const double v = e ? std::atof(e) : 0.0;
+        return v > 0.0 ? v : 5e-6;
+    }();
+    return tau;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Probe records live after the two packed operands; sized for the smallest
+// tile so that any tile choice fits.
+size_t probe_offset(int64_t len) { return align256(2 * accx::packed_bytes(len, len, 2, 3)); }
+size_t probe_bytes_max(int64_t len)
+{
+    return (size_t)accx::probe_tiles(accx::GEMM_TILE_64, len) * sizeof(accx::ProbeRecord);
+}
+
 size_t matmul_ws_bytes(int t, int64_t len, uint32_t flags)
 {
     if (is_plain(flags)) return 0;
+    if (t == ACC_FLOAT32 && (flags & ACC_PREC_MASK) == ACC_PREC_AUTO) return probe_offset(len) + probe_bytes_max(len);
     if (t == ACC_FLOAT32) return 2 * accx::packed_bytes(len, len, 2, 3);
     const int nl = flag_limbs(flags) ? flag_limbs(flags) : 4;
     return kMaxabsBytes + 2 * accx::packed_bytes(len, len, 1, nl);
@@ -353,6 +380,16 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, int64_t len, 
     if (e == hipSuccess) e = accx::launch_pack_bf16x3(b, len, len, true, pbt, s);
     if (e != hipSuccess) return fail_hip(e, "pack (bf16x3) launch");
     const uint32_t prec = flags & ACC_PREC_MASK;
+    if (prec == ACC_PREC_AUTO) {
+        // cheap pass, float64 probe per tile, then the three missing products
+        // on the tiles the probe marked (the others exit at once)
+        const int tile = resolve_tile(ACC_FLOAT32, len, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
+        auto *rec = reinterpret_cast<accx::ProbeRecord *>(work + probe_offset(len));
+        e = accx::launch_gemm_bf16x3(pa, pbt, c, len, 3, false, tile, s);
+        if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, len, tile, probe_tau(), rec, s);
+        if (e == hipSuccess) e = accx::launch_gemm_bf16x3(pa, pbt, c, len, -3, true, tile, s, rec);
+        return check_launch(e, "gemm (bf16x3, probed) launch");
+    }
     const int products = (prec == ACC_PREC_CHEAP3) ? 3 : 6;
     e = accx::launch_gemm_bf16x3(pa, pbt, c, len, products, false,
                                  resolve_tile(ACC_FLOAT32, len, flags, 0), s);
@@ -553,11 +590,13 @@ void tm_collect(Timing &t)
 
 }  // namespace
 
+thread_local bool t_capturing = false;  // no event records inside a graph capture
+
 namespace accx {
 void tmark(const char *name, hipStream_t s, bool begin)
 {
     Timing &t = TM();
-    if (!t.on) return;
+    if (!t.on || t_capturing) return;
     std::lock_guard<std::mutex> lk(t.mu);
     if (begin) {
         TimingRec r{name, tm_event(t), nullptr};
@@ -646,6 +685,11 @@ acc_status acc_shutdown(void)
         delete r;
     }
     st.regions.clear();
+    for (accx_batch_s *b : batches()) {
+        batch_release(b);
+        delete b;
+    }
+    batches().clear();
     for (auto *m : {&st.mm_ws, &st.red_ws, &st.red_plain_ws}) {
         for (auto &kv : *m) ws_release(kv.second);
         m->clear();
@@ -945,6 +989,21 @@ acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const voi
     return run_reduce(t, dX, n, init, dResult, flags, dWork, stream);
 }
 
+acc_status accx_probe_layout(int64_t len, uint32_t flags, size_t *offset_out, int *count_out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!offset_out || !count_out) return fail(ACC_ERR_INVALID_ARG, "NULL output");
+    acc_status s = validate_matmul(ACC_FLOAT32, len, flags);
+    if (s != ACC_OK) return s;
+    if (is_plain(flags) || (flags & ACC_PREC_MASK) != ACC_PREC_AUTO)
+        return fail(ACC_ERR_INVALID_ARG, "the probe runs only for the tiled kernel with ACC_PREC_AUTO");
+    const int tile = resolve_tile(ACC_FLOAT32, len, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
+    *offset_out = probe_offset(len);
+    *count_out = accx::probe_tiles(tile, len);
+    return ACC_OK;
+}
+
 acc_status accx_packed_size(acc_dtype t, int64_t rows, int64_t k, int planes, size_t *bytes_out)
 {
     if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
@@ -979,13 +1038,15 @@ acc_status accx_pack_dev(acc_dtype t, const void *dX, int64_t rows, int64_t k, i
     return check_launch(e, "pack launch");
 }
 
-acc_status accx_autotune(acc_dtype t, int64_t len, uint32_t flags, uint32_t *best_tile_out, double *ms_out)
+// Time the tile configurations in `mask` (bit i = tile i) and record the
+// fastest in the table of `family` (0: standalone kernels, 1: batch kernel).
+}  // extern "C"
+
+namespace {
+acc_status autotune_impl(int t, int64_t len, uint32_t flags, unsigned mask, int family, int *best_out,
+                         double *ms_out)
 {
-    State &st = S();
-    std::lock_guard<std::recursive_mutex> lk(st.mu);
-    acc_status s = check_ready();
-    if (s != ACC_OK) return s;
-    if ((s = validate_matmul(t, len, flags)) != ACC_OK) return s;
+    acc_status s = ACC_OK;
     const int limbs = (t == ACC_INT32) ? (flag_limbs(flags) ? flag_limbs(flags) : 1) : 0;
     const size_t mat = (size_t)len * (size_t)len * 4;
     const size_t pk = (t == ACC_FLOAT32) ? accx::packed_bytes(len, len, 2, 3) : accx::packed_bytes(len, len, 1, limbs);
@@ -1032,6 +1093,7 @@ acc_status accx_autotune(acc_dtype t, int64_t len, uint32_t flags, uint32_t *bes
         std::vector<double> per(accx::GEMM_TILE_COUNT, 1e300);
         for (int r = 0; r < rounds; ++r) {
             for (int tile = 1; tile < accx::GEMM_TILE_COUNT; ++tile) {
+                if (!(mask & (1u << tile))) continue;
                 if (limbs > 1 && tile != accx::GEMM_TILE_64) continue;  // several limbs: small tile only
                 if ((he = run(tile)) != hipSuccess) goto hip_out;
                 if ((he = hipEventRecord(e0, stream)) != hipSuccess) goto hip_out;
@@ -1050,8 +1112,9 @@ acc_status accx_autotune(acc_dtype t, int64_t len, uint32_t flags, uint32_t *bes
                 best = tile;
             }
     }
-    tune_table()[std::make_tuple((int)t, tune_variant(t, flags, limbs), size_class(len))] = TuneEntry{best, best_ms};
-    if (best_tile_out) *best_tile_out = (uint32_t)best << ACC_TILE_SHIFT;
+    tune_table()[std::make_tuple((int)t, tune_variant(t, flags, limbs) + 100 * family, size_class(len))] =
+        TuneEntry{best, best_ms};
+    if (best_out) *best_out = best;
     if (ms_out) *ms_out = best_ms;
     goto out;
 hip_out:
@@ -1065,6 +1128,23 @@ out:
     dev_free(c, mat);
     dev_free(pk2, 2 * pk);
     return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+acc_status accx_autotune(acc_dtype t, int64_t len, uint32_t flags, uint32_t *best_tile_out, double *ms_out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if ((s = validate_matmul(t, len, flags)) != ACC_OK) return s;
+    int best = 0;
+    if ((s = autotune_impl(t, len, flags, ~0u, 0, &best, ms_out)) != ACC_OK) return s;
+    if (best_tile_out) *best_tile_out = (uint32_t)best << ACC_TILE_SHIFT;
+    return ACC_OK;
 }
 
 acc_status accx_tune_save(const char *path)
@@ -1121,6 +1201,364 @@ const char *acc_status_string(acc_status s)
 const char *acc_last_error_string(void) { return t_last_error.c_str(); }
 
 const char *accx_version(void) { return "libaccx 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+// =========================================================================
+// Batched launch: plan, graph, launch.
+
+struct accx_batch_s {
+    void *dev = nullptr;  // one allocation: descriptors, queue, counters, partials, packed operands
+    size_t dev_bytes = 0;
+    accx::BatchQueue queue{};
+    accx::BatchPackJob *jobs = nullptr;  // device
+    int njobs = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    accx_batch_info_t info{};
+};
+
+namespace {
+
+constexpr int64_t kReduceChunk = 1 << 18;  // elements per reduction work unit
+
+std::set<accx_batch_s *> &batches()
+{
+    static auto *b = new std::set<accx_batch_s *>();
+    return *b;
+}
+
+// Tile policy of a batch: an item's forced tile, else 128 x 128 when its
+// LEN is at least `threshold`, else 64 x 64.
+int batch_tile(const accx_batch_item &it, int64_t threshold)
+{
+    const int forced = (int)((it.flags & ACC_TILE_MASK) >> ACC_TILE_SHIFT);
+    if (forced) return forced;
+    return it.n >= threshold ? accx::GEMM_TILE_128 : accx::GEMM_TILE_64;
+}
+
+constexpr int64_t kBatchDefaultThreshold = 512;
+
+// Work queue for the given tiles: matmul tiles, largest matmul first, with
+// the reduction chunks spread evenly through it by cumulative cost, so that
+// both kinds of work are in flight throughout.
+std::vector<accx::BatchUnit> batch_units(std::vector<accx::BatchMat> &mats, const std::vector<accx::BatchRed> &reds)
+{
+    std::vector<int> order(mats.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return mats[x].len > mats[y].len; });
+    std::vector<std::pair<double, accx::BatchUnit>> mu, ru;
+    double mtot = 0, rtot = 0;
+    for (int k : order) {
+        accx::BatchMat &m = mats[k];
+        const int bm = m.tile == accx::GEMM_TILE_128 ? 128 : 64;
+        m.tiles_m = m.tiles_n = (int32_t)((m.len + bm - 1) / bm);
+        for (int t = 0; t < m.tiles_m * m.tiles_n; ++t) {
+            mu.push_back({mtot, accx::BatchUnit{(uint32_t)k, (uint32_t)t}});
+            mtot += (double)bm * bm * (double)m.len;
+        }
+    }
+    for (size_t k = 0; k < reds.size(); ++k)
+        for (int32_t c = 0; c < reds[k].nchunks; ++c) {
+            ru.push_back({rtot, accx::BatchUnit{(uint32_t)k | 0x80000000u, (uint32_t)c}});
+            rtot += (double)std::min<int64_t>(reds[k].chunk, std::max<int64_t>(0, reds[k].n - c * reds[k].chunk));
+        }
+    std::vector<accx::BatchUnit> units;
+    units.reserve(mu.size() + ru.size());
+    size_t im = 0, ir = 0;
+    while (im < mu.size() || ir < ru.size()) {
+        const double fm = im < mu.size() ? (mtot > 0 ? mu[im].first / mtot : 0) : 2.0;
+        const double fr = ir < ru.size() ? (rtot > 0 ? ru[ir].first / rtot : 0) : 2.0;
+        if (fm <= fr)
+            units.push_back(mu[im++].second);
+        else
+            units.push_back(ru[ir++].second);
+    }
+    return units;
+}
+
+void batch_release(accx_batch_s *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->dev) dev_free(b->dev, b->dev_bytes);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->dev = nullptr;
+}
+
+hipError_t batch_enqueue(accx_batch_s *b, hipStream_t s)
+{
+    hipError_t e = accx::launch_batch_pack(b->jobs, b->njobs, s);
+    if (e == hipSuccess) e = accx::launch_batch_persistent(b->queue, s);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t flags, accx_batch *out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!out) return fail(ACC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if (nitems <= 0 || !items) return fail(ACC_ERR_INVALID_ARG, "empty batch");
+    if (flags & ~ACC_BATCH_AUTOTUNE) return fail(ACC_ERR_INVALID_ARG, "unknown batch flag");
+
+    std::vector<accx::BatchMat> mats;
+    std::vector<accx::BatchRed> reds;
+    std::vector<int> mat_item;
+    std::vector<int64_t> red_chunks;
+    std::vector<size_t> pk_bytes;
+    accx_batch_info_t info{};
+    int64_t max_tiles = 0;  // queue bound over every tile policy (all 64 x 64)
+    for (int i = 0; i < nitems; ++i) {
+        const accx_batch_item &it = items[i];
+        const std::string where = "item " + std::to_string(i) + ": ";
+        if (it.dtype != ACC_FLOAT32) return fail(ACC_ERR_INVALID_ARG, where + "batches hold float32 items");
+        if (it.kind == ACC_BATCH_MATMUL) {
+            if (it.n < 1 || it.n > 65536) return fail(ACC_ERR_INVALID_ARG, where + "LEN must be in [1, 65536]");
+            if (!it.a || !it.b || !it.c) return fail(ACC_ERR_INVALID_ARG, where + "NULL pointer");
+            if (((uintptr_t)it.a | (uintptr_t)it.b | (uintptr_t)it.c) & 3u)
+                return fail(ACC_ERR_INVALID_ARG, where + "pointers must be 4-byte aligned");
+            if (it.flags & ~ACC_TILE_MASK) return fail(ACC_ERR_INVALID_ARG, where + "only tile bits allowed");
+            const int forced = (int)((it.flags & ACC_TILE_MASK) >> ACC_TILE_SHIFT);
+            if (forced && !accx::batch_tile_supported(forced))
+                return fail(ACC_ERR_INVALID_ARG, where + "batches run ACC_TILE_128 or ACC_TILE_64");
+            accx::BatchMat m{};
+            m.c = static_cast<float *>(it.c);
+            m.len = it.n;
+            m.nkb = (it.n * 2 + 63) / 64;
+            m.tile = batch_tile(it, kBatchDefaultThreshold);
+            m.products = 6;
+            mats.push_back(m);
+            mat_item.push_back(i);
+            pk_bytes.push_back(accx::packed_bytes(it.n, it.n, 2, 3));
+            max_tiles += ((it.n + 63) / 64) * ((it.n + 63) / 64);
+            info.flops += 2.0 * (double)it.n * (double)it.n * (double)it.n;
+            info.mfma_flops += 6.0 * 2.0 * (double)it.n * (double)it.n * (double)it.n;
+        } else if (it.kind == ACC_BATCH_REDUCE) {
+            if (it.n < 0) return fail(ACC_ERR_INVALID_ARG, where + "n must be >= 0");
+            if ((it.n > 0 && !it.a) || !it.c) return fail(ACC_ERR_INVALID_ARG, where + "NULL pointer");
+            if (((uintptr_t)it.a | (uintptr_t)it.c) & 3u)
+                return fail(ACC_ERR_INVALID_ARG, where + "pointers must be 4-byte aligned");
+            if (it.flags) return fail(ACC_ERR_INVALID_ARG, where + "reductions take no flags");
+            accx::BatchRed r{};
+            r.x = static_cast<const float *>(it.a);
+            r.result = static_cast<float *>(it.c);
+            r.n = it.n;
+            r.chunk = kReduceChunk;
+            r.nchunks = (int32_t)std::max<int64_t>(1, (it.n + kReduceChunk - 1) / kReduceChunk);
+            r.init = it.init;
+            reds.push_back(r);
+            red_chunks.push_back(r.nchunks);
+            info.chunks += r.nchunks;
+            info.reduce_bytes += 4.0 * (double)it.n;
+        } else {
+            return fail(ACC_ERR_INVALID_ARG, where + "unknown kind");
+        }
+    }
+    if (max_tiles + info.chunks >= (int64_t)0x7fffffff) return fail(ACC_ERR_INVALID_ARG, "batch too large");
+    std::vector<accx::BatchUnit> units = batch_units(mats, reds);
+    const size_t max_units = (size_t)(max_tiles + info.chunks);
+
+    // Device layout.
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_mats = off;
+    off = al(off + sizeof(accx::BatchMat) * std::max<size_t>(1, mats.size()));
+    const size_t o_reds = off;
+    off = al(off + sizeof(accx::BatchRed) * std::max<size_t>(1, reds.size()));
+    const size_t o_units = off;
+    off = al(off + sizeof(accx::BatchUnit) * std::max<size_t>(1, max_units));
+    const size_t o_jobs = off;
+    off = al(off + sizeof(accx::BatchPackJob) * std::max<size_t>(1, 2 * mats.size()));
+    const size_t o_zero = off;  // counters, tickets, partials: zero-filled
+    size_t zbytes = 256;
+    for (size_t k = 0; k < reds.size(); ++k) zbytes += 4 + 4 * (size_t)reds[k].nchunks;
+    off = al(off + zbytes);
+    const size_t o_pack = off;
+    for (size_t k = 0; k < mats.size(); ++k) off = al(off + 2 * pk_bytes[k]);
+
+    accx_batch_s *b = new (std::nothrow) accx_batch_s();
+    if (!b) return fail(ACC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    if ((s = dev_alloc(&b->dev, off)) != ACC_OK) {
+        delete b;
+        return s;
+    }
+    b->dev_bytes = off;
+    char *base = static_cast<char *>(b->dev);
+    std::vector<accx::BatchPackJob> jobs;
+    {
+        size_t p = o_pack;
+        for (size_t k = 0; k < mats.size(); ++k) {
+            const accx_batch_item &it = items[mat_item[k]];
+            char *pa = base + p, *pb = base + p + pk_bytes[k];
+            p = al(p + 2 * pk_bytes[k]);
+            mats[k].pa = pa;
+            mats[k].pb = pb;
+            const int64_t nrb = (it.n + 31) / 32;
+            jobs.push_back(accx::BatchPackJob{static_cast<const float *>(it.a), pa, it.n, it.n, nrb, mats[k].nkb, 0, 0});
+            jobs.push_back(accx::BatchPackJob{static_cast<const float *>(it.b), pb, it.n, it.n, nrb, mats[k].nkb, 1, 0});
+        }
+        uint32_t *z = reinterpret_cast<uint32_t *>(base + o_zero);
+        size_t w = 64;  // counter at word 0, done at word 1
+        for (size_t k = 0; k < reds.size(); ++k) {
+            reds[k].ticket = z + w;
+            reds[k].partials = z + w + 1;
+            w += 1 + (size_t)reds[k].nchunks;
+        }
+        b->queue.counter = z;
+        b->queue.done = z + 1;
+    }
+    b->queue.mats = reinterpret_cast<const accx::BatchMat *>(base + o_mats);
+    b->queue.reds = reinterpret_cast<const accx::BatchRed *>(base + o_reds);
+    b->queue.units = reinterpret_cast<const accx::BatchUnit *>(base + o_units);
+    b->queue.nunits = (uint32_t)units.size();
+    b->jobs = reinterpret_cast<accx::BatchPackJob *>(base + o_jobs);
+    b->njobs = (int)jobs.size();
+
+    hipError_t e = hipSuccess;
+    hipStream_t cs = nullptr;
+    if (!mats.empty()) e = hipMemcpy(base + o_mats, mats.data(), sizeof(accx::BatchMat) * mats.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !reds.empty())
+        e = hipMemcpy(base + o_reds, reds.data(), sizeof(accx::BatchRed) * reds.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !units.empty())
+        e = hipMemcpy(base + o_units, units.data(), sizeof(accx::BatchUnit) * units.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !jobs.empty())
+        e = hipMemcpy(base + o_jobs, jobs.data(), sizeof(accx::BatchPackJob) * jobs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(base + o_zero, 0, zbytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    int64_t threshold = kBatchDefaultThreshold;
+    if (e == hipSuccess && (flags & ACC_BATCH_AUTOTUNE) && !mats.empty()) {
+        // Autotune the tile policy on this batch itself: pack once, then time
+        // the persistent kernel under each LEN threshold between the 64 x 64
+        // and 128 x 128 tiles (best of two runs after a warm-up run each).
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = accx::launch_batch_pack(b->jobs, b->njobs, cs);
+        double best = 1e300;
+        const int64_t cand[] = {0, 192, 320, 448, 576, 768, 65537};
+        for (int64_t th : cand) {
+            if (e != hipSuccess) break;
+            for (size_t k = 0; k < mats.size(); ++k) mats[k].tile = batch_tile(items[mat_item[k]], th);
+            std::vector<accx::BatchUnit> u = batch_units(mats, reds);
+            b->queue.nunits = (uint32_t)u.size();
+            e = hipMemcpy(base + o_mats, mats.data(), sizeof(accx::BatchMat) * mats.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(base + o_units, u.data(), sizeof(accx::BatchUnit) * u.size(), hipMemcpyHostToDevice);
+            double t_best = 1e300;
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+                e = hipEventRecord(e0, cs);
+                if (e == hipSuccess) e = accx::launch_batch_persistent(b->queue, cs);
+                if (e == hipSuccess) e = hipEventRecord(e1, cs);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (r > 0) t_best = std::min(t_best, (double)ms);
+            }
+            if (t_best < best) {
+                best = t_best;
+                threshold = th;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (cs) (void)hipStreamDestroy(cs);
+        cs = nullptr;
+        if (e == hipSuccess) {
+            for (size_t k = 0; k < mats.size(); ++k) mats[k].tile = batch_tile(items[mat_item[k]], threshold);
+            units = batch_units(mats, reds);
+            b->queue.nunits = (uint32_t)units.size();
+            e = hipMemcpy(base + o_mats, mats.data(), sizeof(accx::BatchMat) * mats.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(base + o_units, units.data(), sizeof(accx::BatchUnit) * units.size(),
+                              hipMemcpyHostToDevice);
+        }
+    }
+    for (const accx::BatchMat &m : mats) info.tiles += (int64_t)m.tiles_m * m.tiles_n;
+    // Capture the two kernels into one graph (no memset node: the kernels
+    // leave every counter at zero).
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        t_capturing = true;
+        hipError_t le = batch_enqueue(b, cs);
+        t_capturing = false;
+        e = hipStreamEndCapture(cs, &b->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    size_t nnodes = 0;
+    if (e == hipSuccess) e = hipGraphGetNodes(b->graph, nullptr, &nnodes);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        const acc_status fs = fail_hip(e, "batch setup");
+        batch_release(b);
+        delete b;
+        return fs;
+    }
+    info.units = (int64_t)units.size();
+    info.tile_threshold = threshold;
+    info.workgroups = accx::batch_workgroups();
+    info.matmuls = (int32_t)mats.size();
+    info.reductions = (int32_t)reds.size();
+    info.device_bytes = off;
+    info.pad = (int32_t)nnodes;
+    b->info = info;
+    batches().insert(b);
+    *out = b;
+    return ACC_OK;
+}
+
+acc_status accx_batch_launch(accx_batch b, void *hip_stream)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!b || !batches().count(b)) return fail(ACC_ERR_INVALID_ARG, "unknown batch");
+    acc_status s = launch_fault();
+    if (s != ACC_OK) return s;
+    const hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+    return ACC_OK;
+}
+
+acc_status accx_batch_launch_eager(accx_batch b, void *hip_stream)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!b || !batches().count(b)) return fail(ACC_ERR_INVALID_ARG, "unknown batch");
+    acc_status s = launch_fault();
+    if (s != ACC_OK) return s;
+    return check_launch(batch_enqueue(b, static_cast<hipStream_t>(hip_stream)), "batch launch");
+}
+
+acc_status accx_batch_info(accx_batch b, accx_batch_info_t *out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!b || !batches().count(b) || !out) return fail(ACC_ERR_INVALID_ARG, "unknown batch or NULL output");
+    *out = b->info;
+    return ACC_OK;
+}
+
+acc_status accx_batch_destroy(accx_batch b)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!b || !batches().count(b)) return fail(ACC_ERR_INVALID_ARG, "unknown batch");
+    (void)hipDeviceSynchronize();
+    batch_release(b);
+    batches().erase(b);
+    delete b;
+    return ACC_OK;
+}
 
 }  // extern "C"
 
