@@ -250,6 +250,68 @@ ACCX_API acc_status accx_batch_info(accx_batch b, accx_batch_info_t *out);
 /* Waits for the device, frees the workspace and the graph. */
 ACCX_API acc_status accx_batch_destroy(accx_batch b);
 
+/* ---- serving: continuous batching of offload-region requests -------------
+ * A request is one operation of a data region (the data directive of
+ * section 1.3: inputs copied in at region entry stay on the device for every
+ * kernel of the region; outputs are copied out at its exit).  The server
+ * keeps a FIFO of requests and `slots` HIP streams.  Progress (on submit,
+ * poll and drain) retires finished requests and admits queued ones while a
+ * slot is free: a region's first request is admitted when the region's
+ * device footprint (arrays + workspace) fits in the server's HBM budget
+ * (first requests keep arrival order; requests of open regions pass a first
+ * request that waits for memory).  Requests of different regions run
+ * concurrently; requests of one region keep submission order.  Host arrays
+ * should be pinned (hipHostMalloc) for copies to overlap with compute.
+ * Results are bitwise those of the same calls made one at a time. */
+#define ACC_SERVE_MATMUL 0
+#define ACC_SERVE_REDUCE 1
+typedef struct {
+    int32_t op;     /* ACC_SERVE_MATMUL or ACC_SERVE_REDUCE */
+    int32_t dtype;  /* ACC_FLOAT32 or ACC_INT32 */
+    int64_t region; /* caller's key: requests with one key share a data region */
+    int32_t first;  /* 1: opens the region: device arrays allocated, inputs copied in */
+    int32_t last;   /* 1: closes it: matmul c copied out, arrays freed */
+    const void *a;  /* HOST matmul A (n*n) or reduction x (n); read by the first request */
+    const void *b;  /* HOST matmul B (n*n); unused by reductions */
+    void *c;        /* HOST matmul C (n*n), written by the last request;
+                       reduction: this request's result (one element) */
+    int64_t n;      /* matmul LEN; reduction element count */
+    double init;    /* reduction: result = init + sum (converted to dtype) */
+    uint32_t flags; /* matmul flags (ACC_KERNEL_*, ACC_PREC_*, ...); reduction flags */
+    uint32_t pad;
+    uint64_t tag;   /* returned in the completion */
+} accx_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status; /* acc_status of the request */
+    int32_t pad;
+    double t_submit, t_start, t_done; /* server clock (accx_server_now), seconds */
+} accx_completion;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected;
+    int64_t regions_open, max_inflight, max_regions_open;
+    uint64_t budget_used, budget_peak;
+} accx_server_stats_t;
+
+typedef struct accx_server_s *accx_server; /* opaque */
+
+/* slots in [1, 64]; hbm_budget_bytes = 0: no budget.  Errors: INVALID_ARG,
+ * OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_server_create(int slots, uint64_t hbm_budget_bytes, accx_server *out);
+/* Queue a request (validated now; a rejected request returns an error and
+ * is not queued).  Requests that fail later complete with their status. */
+ACCX_API acc_status accx_server_submit(accx_server s, const accx_request *r);
+/* Make progress without blocking and return up to `cap` completions. */
+ACCX_API acc_status accx_server_poll(accx_server s, accx_completion *out, int cap, int *n_out);
+/* Block until nothing is queued or running (completions stay for poll). */
+ACCX_API acc_status accx_server_drain(accx_server s);
+ACCX_API acc_status accx_server_now(accx_server s, double *t_out);
+ACCX_API acc_status accx_server_stats(accx_server s, accx_server_stats_t *out);
+/* Drains, frees every open region, destroys the streams. */
+ACCX_API acc_status accx_server_destroy(accx_server s);
+
 /* ---- float64 error probe (ACC_PREC_AUTO) ----------------------------------
  * With ACC_PREC_AUTO the float32 tiled matmul runs the three-product split
  * first, then, per output tile of the tile configuration in use, computes 16

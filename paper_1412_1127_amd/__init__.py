@@ -48,6 +48,8 @@ ACC_TILE_256 = 0x10000
 ACC_TILE_256x128 = 0x20000
 ACC_TILE_128 = 0x30000
 ACC_TILE_64 = 0x40000
+ACC_SERVE_MATMUL = 0
+ACC_SERVE_REDUCE = 1
 ACC_BATCH_MATMUL = 0
 ACC_BATCH_REDUCE = 1
 ACC_BATCH_AUTOTUNE = 0x1
@@ -87,6 +89,25 @@ class accx_batch_info_t(ctypes.Structure):
                 ("mfma_flops", ctypes.c_double), ("reduce_bytes", ctypes.c_double)]
 
 
+class accx_request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("dtype", ctypes.c_int32), ("region", ctypes.c_int64),
+                ("first", ctypes.c_int32), ("last", ctypes.c_int32), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("n", ctypes.c_int64), ("init", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("tag", ctypes.c_uint64)]
+
+
+class accx_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class accx_server_stats_t(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("regions_open", ctypes.c_int64), ("max_inflight", ctypes.c_int64),
+                ("max_regions_open", ctypes.c_int64), ("budget_used", ctypes.c_uint64),
+                ("budget_peak", ctypes.c_uint64)]
+
+
 class acc_clause(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("host", ctypes.c_void_p),
                 ("start", ctypes.c_int64), ("n", ctypes.c_int64)]
@@ -123,6 +144,13 @@ _SIGS = {
     "accx_batch_launch_eager": [_vp, _vp],
     "accx_batch_info": [_vp, ctypes.POINTER(accx_batch_info_t)],
     "accx_batch_destroy": [_vp],
+    "accx_server_create": [ctypes.c_int, _u64, ctypes.POINTER(_vp)],
+    "accx_server_submit": [_vp, ctypes.POINTER(accx_request)],
+    "accx_server_poll": [_vp, ctypes.POINTER(accx_completion), ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "accx_server_drain": [_vp],
+    "accx_server_now": [_vp, ctypes.POINTER(ctypes.c_double)],
+    "accx_server_stats": [_vp, ctypes.POINTER(accx_server_stats_t)],
+    "accx_server_destroy": [_vp],
     "accx_probe_layout": [_i64, _u32, ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_int)],
     "accx_autotune": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_double)],
     "accx_tune_save": [ctypes.c_char_p],
@@ -357,3 +385,49 @@ def accx_batch_info(batch: int) -> dict:
 
 def accx_batch_destroy(batch: int) -> None:
     _check(_lib.accx_batch_destroy(batch), "accx_batch_destroy")
+
+
+def accx_server_create(slots: int = 8, hbm_budget_bytes: int = 0) -> int:
+    out = _vp(0)
+    _check(_lib.accx_server_create(int(slots), int(hbm_budget_bytes), ctypes.byref(out)), "accx_server_create")
+    return int(out.value)
+
+
+def accx_server_submit(server: int, req: accx_request) -> None:
+    _check(_lib.accx_server_submit(server, ctypes.byref(req)), "accx_server_submit")
+
+
+_POLL_CAP = 1024
+_poll_buf = (accx_completion * _POLL_CAP)()
+
+
+def accx_server_poll(server: int):
+    """Progress the server; returns the finished requests as
+    (tag, status, t_submit, t_start, t_done) tuples."""
+    n = ctypes.c_int(0)
+    out = []
+    while True:
+        _check(_lib.accx_server_poll(server, _poll_buf, _POLL_CAP, ctypes.byref(n)), "accx_server_poll")
+        out.extend((int(c.tag), int(c.status), c.t_submit, c.t_start, c.t_done) for c in _poll_buf[:n.value])
+        if n.value < _POLL_CAP:
+            return out
+
+
+def accx_server_drain(server: int) -> None:
+    _check(_lib.accx_server_drain(server), "accx_server_drain")
+
+
+def accx_server_now(server: int) -> float:
+    t = ctypes.c_double(0)
+    _check(_lib.accx_server_now(server, ctypes.byref(t)), "accx_server_now")
+    return float(t.value)
+
+
+def accx_server_stats(server: int) -> dict:
+    st = accx_server_stats_t()
+    _check(_lib.accx_server_stats(server, ctypes.byref(st)), "accx_server_stats")
+    return {f: int(getattr(st, f)) for f, _ in accx_server_stats_t._fields_}
+
+
+def accx_server_destroy(server: int) -> None:
+    _check(_lib.accx_server_destroy(server), "accx_server_destroy")

@@ -20,6 +20,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = [
     "runtime.cpp",
+    "serve.cpp",
     "matmul_plain.hip",
     "reduce.hip",
     "gemm_mfma.hip",

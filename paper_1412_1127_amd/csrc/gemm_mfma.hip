@@ -49,11 +49,15 @@ __global__ __launch_bounds__(256) void pack_bf16x3(const float *__restrict__ X, 
 
 // int32 -> P balanced base-256 digit planes (int8), 16 K elements per thread.
 // maxabs (optional): running max of |x| over the operand, as uint32.
+// decide (optional): the two max|x| words of a finished probe pass; the
+// kernel then packs only if limb_gate(decide, expect) holds.
 template <bool TRANS>
 __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K,
                                                char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
-                                               uint32_t *__restrict__ maxabs)
+                                               uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
+                                               int expect)
 {
+    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
     const int64_t total = nrb * nkb * 128;
     uint32_t mx = 0;
     for (int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x; id < total; id += (int64_t)gridDim.x * 256) {
@@ -125,6 +129,7 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
     int tm, tn;
     tile_of(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
     if (g.probe && !g.probe[tm * g.tiles_n + tn].corrected) return;  // whole workgroup: uniform
+    if (g.decide && !limb_gate(g.decide, g.expect)) return;             // the whole grid: uniform
     gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC>(g, tm, tn, lds);
 }
 
@@ -354,17 +359,17 @@ hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, bool tran
 }
 
 hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans, int planes, void *out,
-                          uint32_t *maxabs, hipStream_t s)
+                          uint32_t *maxabs, hipStream_t s, const uint32_t *decide, int expect)
 {
     const int64_t nrb = cdiv(rows, 32), nkb = cdiv(k, 64);
     const unsigned grid = pack_grid(nrb * nkb);
     tmark("pack_i8", s, true);
     if (trans)
         hipLaunchKernelGGL(pack_i8<true>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out), nrb, nkb,
-                           planes, maxabs);
+                           planes, maxabs, decide, expect);
     else
         hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out), nrb,
-                           nkb, planes, maxabs);
+                           nkb, planes, maxabs, decide, expect);
     tmark("pack_i8", s, false);
     return hipGetLastError();
 }
@@ -423,7 +428,8 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t 
     return e;
 }
 
-hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s)
+hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s,
+                          const uint32_t *decide)
 {
     GemmArgs g{};
     g.A = static_cast<const char *>(pa);
@@ -432,6 +438,8 @@ hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t le
     g.M = g.N = g.ldc = len;
     g.nkb = cdiv(len, 64);
     g.nrb_a = g.nrb_b = cdiv(len, 32);
+    g.decide = decide;
+    g.expect = limbs;
     const int t = tile ? tile : default_tile(len);
     hipError_t e;
     tmark("gemm_i8", s, true);

@@ -36,8 +36,10 @@ size_t packed_bytes(int64_t rows, int64_t k_elems, int elem_bytes, int planes);
 hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, bool trans, void *out, hipStream_t s);
 // int32 -> `planes` balanced base-256 digit planes; maxabs (nullable) gets
 // atomicMax of |x| (must hold 0 or a smaller value beforehand).
+// decide (optional): packs only if the digit count decided on the device
+// from the two max|x| words is 1 (expect = 1) or more (expect = 4).
 hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans, int planes, void *out,
-                          uint32_t *maxabs, hipStream_t s);
+                          uint32_t *maxabs, hipStream_t s, const uint32_t *decide = nullptr, int expect = 0);
 // C (len x len) = sum over the product set of A-plane x B-plane.
 // products: 6 = FULL6, 3 = CHEAP3, -3 = the three products FULL6 adds to
 // CHEAP3.  accumulate: C += instead of C =.
@@ -62,7 +64,10 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t 
 hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, int64_t len, int tile, double tau,
                             ProbeRecord *rec, hipStream_t s);
 int probe_tiles(int tile, int64_t len);
-hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s);
+// decide (optional): runs only if the device-side digit count is 1 (limbs =
+// 1) or more than 1 (limbs = 4).
+hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s,
+                          const uint32_t *decide = nullptr);
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
 // n pseudo-random 32-bit words for timing runs: float32 in [-1, 1) or int32 in [-16, 16].
 hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s);

@@ -169,7 +169,25 @@ struct GemmArgs {
     int tiles_m, tiles_n;
     int accumulate;  // float: C += result instead of C = result
     const ProbeRecord *probe;  // non-null: skip tiles whose record says no correction
+    const uint32_t *decide;    // non-null: run only if limb_gate(decide, expect)
+    int expect;
 };
+
+// Digits the int8 path needs for two operands with the given max |x| words:
+// the fewest balanced base-256 digits that hold every value exactly (four
+// hold any int32 modulo 2^32).
+__device__ inline int limbs_needed(const uint32_t *maxabs2)
+{
+    const uint32_t m = maxabs2[0] > maxabs2[1] ? maxabs2[0] : maxabs2[1];
+    return m <= 127u ? 1 : m <= 32639u ? 2 : m <= 8355711u ? 3 : 4;
+}
+
+// The one-digit kernels (expect = 1) run when one digit is enough; the
+// four-digit kernels (expect = 4) serve every other case.
+__device__ inline bool limb_gate(const uint32_t *maxabs2, int expect)
+{
+    return (limbs_needed(maxabs2) == 1) == (expect == 1);
+}
 
 // Map the linear workgroup id to an output tile.  Workgroups are dealt to
 // the 8 XCDs round-robin; give each XCD a contiguous run of the grouped tile

@@ -331,8 +331,9 @@ size_t matmul_ws_bytes(int t, int64_t len, uint32_t flags)
     if (is_plain(flags)) return 0;
     if (t == ACC_FLOAT32 && (flags & ACC_PREC_MASK) == ACC_PREC_AUTO) return probe_offset(len) + probe_bytes_max(len);
     if (t == ACC_FLOAT32) return 2 * accx::packed_bytes(len, len, 2, 3);
-    const int nl = flag_limbs(flags) ? flag_limbs(flags) : 4;
-    return kMaxabsBytes + 2 * accx::packed_bytes(len, len, 1, nl);
+    if (flag_limbs(flags)) return kMaxabsBytes + 2 * accx::packed_bytes(len, len, 1, flag_limbs(flags));
+    // probe: one-digit and four-digit operands side by side
+    return kMaxabsBytes + 2 * accx::packed_bytes(len, len, 1, 1) + 2 * accx::packed_bytes(len, len, 1, 4);
 }
 
 // ---- autotuned tile table -----------------------------------------------
@@ -401,24 +402,27 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, int64_t
 {
     uint32_t *maxabs = reinterpret_cast<uint32_t *>(work);
     char *pa = work + kMaxabsBytes;
-    int nl = flag_limbs(flags);
+    const int nl = flag_limbs(flags);
     hipError_t e;
     if (nl == 0) {
-        // Probe: write digit 0 of both operands and max|x| in one pass; the
-        // digit-0 planes are final when one digit is enough.
+        // Probe on the device, no host round trip: one pass writes digit 0 of
+        // both operands and max|x|; a four-digit pass and the four-digit GEMM
+        // run only if the maxima call for more than one digit, the one-digit
+        // GEMM only if they do not (each kernel reads the decision and exits
+        // at once otherwise).  Two or three digits are served by the
+        // four-digit kernels: the extra digits are zero.
         const size_t pb1 = accx::packed_bytes(len, len, 1, 1);
+        const size_t pb4 = accx::packed_bytes(len, len, 1, 4);
+        char *p4 = pa + 2 * pb1;
         e = accx::launch_zero_u32(maxabs, 2, s);
         if (e == hipSuccess) e = accx::launch_pack_i8(a, len, len, false, 1, pa, maxabs, s);
         if (e == hipSuccess) e = accx::launch_pack_i8(b, len, len, true, 1, pa + pb1, maxabs + 1, s);
+        if (e == hipSuccess) e = accx::launch_pack_i8(a, len, len, false, 4, p4, nullptr, s, maxabs, 4);
+        if (e == hipSuccess) e = accx::launch_pack_i8(b, len, len, true, 4, p4 + pb4, nullptr, s, maxabs, 4);
         if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
-        uint32_t m[2] = {0, 0};
-        e = hipMemcpyAsync(m, maxabs, sizeof m, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return fail_hip(e, "max|x| probe readback");
-        nl = std::max(limbs_for(m[0]), limbs_for(m[1]));
-        if (nl == 1)
-            return check_launch(accx::launch_gemm_i8(pa, pa + pb1, c, len, 1, resolve_tile(ACC_INT32, len, flags, 1), s),
-                                "gemm (int8) launch");
+        e = accx::launch_gemm_i8(pa, pa + pb1, c, len, 1, resolve_tile(ACC_INT32, len, flags, 1), s, maxabs);
+        if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pb4, c, len, 4, 0, s, maxabs);
+        return check_launch(e, "gemm (int8) launch");
     }
     const size_t pbn = accx::packed_bytes(len, len, 1, nl);
     e = accx::launch_pack_i8(a, len, len, false, nl, pa, nullptr, s);
@@ -1203,6 +1207,31 @@ const char *acc_last_error_string(void) { return t_last_error.c_str(); }
 const char *accx_version(void) { return "libaccx 0.1 (gfx950)"; }
 
 }  // extern "C"
+
+// =========================================================================
+// Entry points for the serving engine (serve.cpp); see runtime_internal.h.
+namespace accx {
+namespace rt {
+acc_status fail(acc_status s, const std::string &msg) { return ::fail(s, msg); }
+acc_status fail_hip(hipError_t e, const char *what) { return ::fail_hip(e, what); }
+acc_status ready() { return check_ready(); }
+acc_status check_matmul(int t, int64_t len, uint32_t flags) { return validate_matmul(t, len, flags); }
+acc_status check_reduce(int t, int64_t n, uint32_t flags) { return validate_reduce(t, n, flags); }
+size_t matmul_workspace(int t, int64_t len, uint32_t flags) { return matmul_ws_bytes(t, len, flags); }
+size_t reduce_workspace(int64_t n, uint32_t flags) { return reduce_ws_bytes(n, flags); }
+acc_status matmul(int t, const void *a, const void *b, void *c, int64_t len, uint32_t flags, void *work,
+                  size_t work_bytes, hipStream_t s)
+{
+    return run_matmul(t, a, b, c, len, flags, work, work_bytes, s);
+}
+acc_status reduce(int t, const void *x, int64_t n, const void *init, void *result, uint32_t flags, void *work,
+                  hipStream_t s)
+{
+    return run_reduce(t, x, n, init, result, flags, work, s);
+}
+std::recursive_mutex &lock() { return S().mu; }
+}  // namespace rt
+}  // namespace accx
 
 // =========================================================================
 // Batched launch: plan, graph, launch.

@@ -1,0 +1,137 @@
+"""The serving engine: regions of four requests on device-resident arrays,
+continuous admission under an HBM budget, results identical alone and in the
+mix, and correct against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _util import FP32_REL_FRO_TOL, SEED, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ax():
+    import paper_1412_1127_amd as ax
+    ax.acc_init(0, 0)
+    yield ax
+    ax.acc_shutdown()
+
+
+def _region_inputs(ax, pools, r):
+    a, b = pools.inputs(r)
+    a = a.numpy()
+    if r.op == ax.ACC_SERVE_REDUCE:
+        return a, None
+    return a.reshape(r.n, r.n), b.numpy().reshape(r.n, r.n)
+
+
+def _collect(ax, serve, wl, pools, **kw):
+    outs = {}
+
+    def keep(r, view):
+        outs[r.key] = view.numpy().copy()
+    res = serve.run(wl, pools, on_region_done=keep, **kw)
+    return res, outs
+
+
+def test_mix_equals_alone_and_oracle(ax):
+    from paper_1412_1127_amd import serve
+    wl = serve.make_workload(160, SEED, rate=4000.0, len_hi=512, n_hi=1 << 20)
+    pools = serve.Pools(wl)
+    mix, mix_out = _collect(ax, serve, wl, pools, slots=8)
+    print("mix:", {k: v for k, v in mix.items() if k != "reduce_results"}, flush=True)
+    alone, alone_out = _collect(ax, serve, wl, pools, alone=True)
+    assert mix["completed_ok"] == alone["completed_ok"] == len(wl.requests)
+    assert mix["server"]["max_inflight"] > 1          # work really overlapped
+    assert set(mix_out) == set(alone_out)
+    for k in mix_out:
+        assert np.array_equal(mix_out[k], alone_out[k]), k
+    assert mix["reduce_results"] == alone["reduce_results"]
+    # against the oracle
+    g = synth.rng(SEED, 3)
+    for k, c in mix_out.items():
+        r = wl.regions[k]
+        a, b = _region_inputs(ax, pools, r)
+        c = c.reshape(r.n, r.n)
+        ii, jj = g.integers(0, r.n, 64), g.integers(0, r.n, 64)
+        ref = oracle.matmul_at(a, b, ii, jj)
+        if r.dtype == ax.ACC_INT32:
+            assert np.array_equal(c[ii, jj], ref), k
+        else:
+            assert rel_fro(c[ii, jj], ref) <= FP32_REL_FRO_TOL, k
+    for q in wl.requests:
+        r = wl.regions[q.region]
+        if r.op != ax.ACC_SERVE_REDUCE:
+            continue
+        x, _ = _region_inputs(ax, pools, r)
+        ref = oracle.sum_f32(x, q.init)
+        assert abs(mix["reduce_results"][q.tag] - ref) <= 1e-5 * abs(ref), q.tag
+
+
+def test_small_budget_admission(ax):
+    from paper_1412_1127_amd import serve
+    wl = serve.make_workload(60, SEED + 1, rate=4000.0, len_lo=128, len_hi=256, n_lo=1 << 16, n_hi=1 << 18)
+    pools = serve.Pools(wl)
+    # room for about two regions at a time
+    budget = 4 << 20
+    res, outs = _collect(ax, serve, wl, pools, slots=8, budget=budget)
+    print({k: v for k, v in res.items() if k != "reduce_results"})
+    assert res["completed_ok"] == len(wl.requests)
+    assert res["server"]["budget_peak"] <= budget
+    ref, ref_out = _collect(ax, serve, wl, pools, alone=True)
+    for k in outs:
+        assert np.array_equal(outs[k], ref_out[k])
+    assert res["reduce_results"] == ref["reduce_results"]
+
+
+def test_protocol_errors(ax):
+    import torch
+    srv = ax.accx_server_create(2, 1 << 20)
+    try:
+        x = torch.ones(1000).pin_memory()
+        out = torch.zeros(2).pin_memory()
+        # a request of a region that never opened
+        ax.accx_server_submit(srv, ax.accx_request(ax.ACC_SERVE_REDUCE, ax.ACC_FLOAT32, 7, 0, 1, x.data_ptr(), None,
+                                                   out.data_ptr(), 1000, 0.0, 0, 0, 1))
+        # a region bigger than the budget
+        big = torch.ones(1 << 19).pin_memory()
+        ax.accx_server_submit(srv, ax.accx_request(ax.ACC_SERVE_REDUCE, ax.ACC_FLOAT32, 8, 1, 1, big.data_ptr(),
+                                                   None, out.data_ptr(), 1 << 19, 0.0, 0, 0, 2))
+        # a well-formed one
+        ax.accx_server_submit(srv, ax.accx_request(ax.ACC_SERVE_REDUCE, ax.ACC_FLOAT32, 9, 1, 1, x.data_ptr(), None,
+                                                   out[1:].data_ptr(), 1000, 0.5, 0, 0, 3))
+        ax.accx_server_drain(srv)
+        got = {t: st for t, st, *_ in ax.accx_server_poll(srv)}
+        assert got == {1: ax.ACC_ERR_NOT_PRESENT, 2: ax.ACC_ERR_OUT_OF_MEMORY, 3: ax.ACC_OK}
+        assert float(out[1]) == 1000.5
+        with pytest.raises(ax.AccxError):   # invalid requests are refused at submit
+            ax.accx_server_submit(srv, ax.accx_request(5, ax.ACC_FLOAT32, 1, 1, 1, x.data_ptr(), None,
+                                                       out.data_ptr(), 10, 0.0, 0, 0, 4))
+    finally:
+        ax.accx_server_destroy(srv)
+
+
+def test_serving_workload(ax):
+    # The serving workload: Poisson 2000 requests/s, 70% matmuls (LEN
+    # log-uniform in [128, 2048], float32 and int32), 30% reductions (n
+    # log-uniform in [2^16, 2^26]), 4 requests per region, 64 GB budget.
+    from paper_1412_1127_amd import serve
+    wl = serve.make_workload(1200, SEED)
+    pools = serve.Pools(wl)
+    g = synth.rng(SEED, 4)
+    bad = []
+
+    def check(r, view):
+        a, b = _region_inputs(ax, pools, r)
+        c = view.numpy().reshape(r.n, r.n)
+        ii, jj = g.integers(0, r.n, 16), g.integers(0, r.n, 16)
+        ref = oracle.matmul_at(a, b, ii, jj)
+        ok = np.array_equal(c[ii, jj], ref) if r.dtype == ax.ACC_INT32 else rel_fro(c[ii, jj], ref) <= 1e-5
+        if not ok:
+            bad.append(r.key)
+    res = serve.run(wl, pools, slots=8, budget=64 << 30, on_region_done=check)
+    print({k: v for k, v in res.items() if k != "reduce_results"}, flush=True)
+    assert res["completed_ok"] == len(wl.requests) and not bad
+    assert res["latency_ms"]["p99"] > 0
