@@ -42,13 +42,18 @@ def _args():
     p.add_argument("--n-reduce", type=int, default=1 << 28)
     p.add_argument("--prec", choices=["full6", "auto", "cheap3"], default="full6")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-rows", type=int, default=1024,
-                   help="rows of C the CPU baseline computes per matmul (scaled to the whole step)")
+    p.add_argument("--cpu-rows", type=int, default=0,
+                   help="rows of C the CPU baseline computes per matmul, scaled to the whole step "
+                        "(0: all LEN rows, the whole step)")
     p.add_argument("--no-verify", action="store_true")
     p.add_argument("--tile", choices=["256", "256x128", "128", "64"], default=None,
                    help="force the float32 tile configuration (implies --no-autotune)")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the tile autotuner before the timed region (size heuristic instead)")
+    p.add_argument("--workload", choices=["scale", "small", "precision", "batch", "serve"], default="scale",
+                   help="scale (default): the step described above; the others measure the remaining "
+                        "configurations (LEN=256 plain method, LEN=8192 precision, batching, serving)")
+    p.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     return p.parse_args()
@@ -69,7 +74,7 @@ def _traffic(kernel: str, workload: str):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
         e = t[kernel][workload]
-        if e.get("source_hash") != _source_hash("gemm_mfma.hip"):
+        if e.get("source_hash") != _source_hash("gemm_mfma.hip", "mfma_tile.h"):
             return None
         return float(e["fetch_bytes"]) + float(e["write_bytes"])
     except (OSError, KeyError, ValueError):
@@ -81,14 +86,7 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q)) if len(v) else None
 
 
-def main() -> int:
-    args = _args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the offload path here has no multi-GPU form "
-              "(how it would shard is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
-        return 2
-
+def run_scale(args) -> int:
     import numpy as np
     import torch
 
@@ -223,7 +221,7 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        rows = min(args.cpu_rows, n)
+        rows = min(args.cpu_rows, n) if args.cpu_rows > 0 else n
         t = time.perf_counter()
         oracle.matmul_rows(a, b, 0, rows)
         tf = time.perf_counter() - t
@@ -235,9 +233,10 @@ def main() -> int:
         tr = time.perf_counter() - t
         cpu_step_s = (tf + ti) * (n / rows) + tr
         cpu = {"value": ops / cpu_step_s / 1e12, "unit": "TFLOP/s", "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": "float64 and uint64 oracle on rows 0..%d of both LEN=%d matmuls (scaled by %d/%d) plus the "
-                         "serial float64 sum of all %d values; measured %.1f s" % (rows - 1, n, n, rows, nred,
-                                                                                   tf + ti + tr),
+               "sample": ("the whole step: " if rows == n else "rows 0..%d of both matmuls, scaled by %d/%d; " %
+                          (rows - 1, n, rows)) +
+                         "float64 (float32 inputs) and uint64-wrapping (int32) LEN=%d matmul oracles with OpenMP, "
+                         "serial float64 sum of %d values; measured %.1f s" % (n, nred, tf + ti + tr),
                "step_s_scaled": cpu_step_s}
 
     line = {
@@ -262,6 +261,241 @@ def main() -> int:
     ax.acc_shutdown()
     print(json.dumps(line))
     return 0
+
+
+def _common(args, metric, value, unit, ms, config, higher=True, dtype="f32", **extra):
+    line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    line.update(extra)
+    return line
+
+
+def _event_times(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return ts
+
+
+def run_small(args) -> int:
+    """LEN=256 float32, uniform[-1,1]: the plain one-thread-per-(i,j) kernel
+    (and the tiled kernel beside it), per-call latency and error vs the
+    float64 oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1412_1127_amd as ax
+    import synth
+    n = 256
+    a = synth.uniform_pm1_f32((n, n), synth.DEFAULT_SEED, synth.STREAM_A)
+    b = synth.uniform_pm1_f32((n, n), synth.DEFAULT_SEED, synth.STREAM_B)
+    ax.acc_init(0, 0)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    dc = torch.empty((n, n), device="cuda")
+    ref = oracle.matmul_f32(a, b)
+    out = {}
+    for name, flags in [("plain", ax.ACC_KERNEL_PLAIN), ("listing1b", ax.ACC_KERNEL_PLAIN_LISTING1B),
+                        ("tiled_full6", ax.ACC_KERNEL_TILED | ax.ACC_PREC_FULL6)]:
+        ts = _event_times(lambda: ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, flags), args.steps, args.warmup)
+        c = dc.cpu().numpy()
+        out[name] = {"p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99)),
+                     "tflops_p50": 2.0 * n ** 3 / (np.percentile(ts, 50) * 1e-3) / 1e12,
+                     "rel_fro_vs_oracle": float(np.linalg.norm(c - ref) / np.linalg.norm(ref))}
+    ax.acc_shutdown()
+    p = out["plain"]
+    print(json.dumps(_common(args, "matmul TFLOP/s (plain kernel, LEN=256) and p50/p99 latency", p["tflops_p50"],
+                             "TFLOP/s", p["p50_ms"],
+                             {"workload": "plain method, smallest: LEN=256 float32 uniform[-1,1]", "len": n},
+                             latency_ms={"p50": p["p50_ms"], "p99": p["p99_ms"]}, kernels=out)))
+    return 0
+
+
+def run_precision(args) -> int:
+    """LEN=8192 float32, N(0,1) x 2^U(-8,8) per row: bf16x3 on matrix cores
+    (six products, and the probed AUTO mode) beside the float32 plain kernel;
+    relative Frobenius error vs the float64 oracle on sampled entries."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1412_1127_amd as ax
+    import synth
+    n = 8192
+    a = synth.normal_rowscaled_f32(n, n, synth.DEFAULT_SEED, synth.STREAM_A)
+    b = synth.normal_rowscaled_f32(n, n, synth.DEFAULT_SEED, synth.STREAM_B)
+    ax.acc_init(0, 0)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    dc = torch.empty((n, n), device="cuda")
+    g = synth.rng(synth.DEFAULT_SEED, 98)
+    ii, jj = g.integers(0, n, 2048), g.integers(0, n, 2048)
+    ref = oracle.matmul_at(a, b, ii, jj)
+    ax.accx_autotune(ax.ACC_FLOAT32, n, ax.ACC_PREC_FULL6)
+    ax.accx_timing_enable(True)
+    out = {}
+    for name, flags, reps in [("bf16x3_full6", ax.ACC_KERNEL_TILED | ax.ACC_PREC_FULL6, args.steps),
+                              ("bf16x3_auto", ax.ACC_KERNEL_TILED | ax.ACC_PREC_AUTO, args.steps),
+                              ("plain_f32", ax.ACC_KERNEL_PLAIN, 1)]:
+        ax.accx_timing_read(reset=True)
+        ts = _event_times(lambda: ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, flags), reps,
+                          1 if reps > 1 else 0)
+        kt = ax.accx_timing_read(reset=True)
+        c = dc.cpu().numpy()
+        ms = float(np.median(ts))
+        out[name] = {"ms": ms, "tflops_fp32_equiv": 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
+                     "rel_fro_vs_oracle_sampled": float(np.linalg.norm(c[ii, jj] - ref) / np.linalg.norm(ref)),
+                     "kernels": {k: v[1] / v[0] for k, v in kt.items()}}
+    ax.accx_timing_enable(False)
+    ax.acc_shutdown()
+    f = out["bf16x3_full6"]
+    gm = f["kernels"].get("gemm_bf16x3")
+    achieved = 6 * 2.0 * n ** 3 / (gm * 1e-3) / 1e12 if gm else None
+    print(json.dumps(_common(
+        args, "matmul TFLOP/s (bf16x3, LEN=8192) at <=1e-5 rel err", f["tflops_fp32_equiv"], "TFLOP/s", f["ms"],
+        {"workload": "precision: LEN=8192 float32 N(0,1) x 2^U(-8,8) per row", "len": n},
+        roofline={"kernel": "gemm_bf16x3", "bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                  "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS if achieved else None},
+        paths=out)))
+    return 0
+
+
+def run_batch(args) -> int:
+    """512 float32 matmuls (LEN uniform over {64, ..., 1024}) + 256 float32
+    reductions (n log-uniform in [2^16, 2^24]) as one graph launch."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1412_1127_amd as ax
+    import synth
+    seed = synth.DEFAULT_SEED
+    lens = synth.lens_uniform(512, [64 * k for k in range(1, 17)], seed)
+    ns = synth.log_uniform_int(256, 1 << 16, 1 << 24, seed, synth.STREAM_X)
+    ax.acc_init(0, 0)
+    items, mats, reds = [], [], []
+    for k, n in enumerate(lens):
+        a = synth.uniform_pm1_f32((n, n), seed, 1000 + 2 * k)
+        b = synth.uniform_pm1_f32((n, n), seed, 1001 + 2 * k)
+        da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        dc = torch.empty((n, n), device="cuda")
+        mats.append((a, b, da, db, dc, int(n)))
+        items.append(ax.batch_matmul(da, db, dc, int(n)))
+    for k, n in enumerate(ns):
+        x = synth.uniform01_f32(int(n), seed, 5000 + k)
+        dx = torch.from_numpy(x).cuda()
+        r = torch.empty(1, device="cuda")
+        reds.append((x, dx, r))
+        items.append(ax.batch_reduce(dx, int(n), r))
+    t0 = time.time()
+    bh = ax.accx_batch_create(items, ax.ACC_BATCH_AUTOTUNE)
+    create_s = time.time() - t0
+    info = ax.accx_batch_info(bh)
+    ts = _event_times(lambda: ax.accx_batch_launch(bh), args.steps, args.warmup)
+    ms = float(np.median(ts))
+    ax.accx_timing_enable(True)
+    ax.accx_timing_read(reset=True)
+    for _ in range(3):
+        ax.accx_batch_launch_eager(bh)
+    kt = {k: v[1] / v[0] for k, v in ax.accx_timing_read(reset=True).items()}
+    ax.accx_timing_enable(False)
+    # one call per item, no graph, for comparison
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (_a, _b, da, db, dc, n) in mats:
+        ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, ax.ACC_KERNEL_TILED | ax.ACC_PREC_FULL6)
+    for (x, dx, r) in reds:
+        ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, x.size, 0.0, r)
+    torch.cuda.synchronize()
+    per_item_ms = (time.perf_counter() - t0) * 1e3
+    ax.accx_batch_launch(bh)
+    torch.cuda.synchronize()
+    g = synth.rng(seed, 77)
+    got, ref = [], []
+    for (a, b, _da, _db, dc, n) in mats:
+        ii, jj = g.integers(0, n, 8), g.integers(0, n, 8)
+        got.append(dc.cpu().numpy()[ii, jj])
+        ref.append(oracle.matmul_at(a, b, ii, jj))
+    got, ref = np.concatenate(got), np.concatenate(ref)
+    red_err = max(abs(float(r.item()) - oracle.sum_f32(x)) / oracle.sum_f32(x) for (x, _dx, r) in reds)
+    ax.accx_batch_destroy(bh)
+    ax.acc_shutdown()
+    tf = info["flops"] / (ms * 1e-3) / 1e12
+    mfma = info["mfma_flops"] / (ms * 1e-3) / 1e12
+    print(json.dumps(_common(
+        args, "batched matmul TFLOP/s (one graph launch: 512 matmuls + 256 reductions)", tf, "TFLOP/s", ms,
+        {"workload": "batching: 512 float32 matmuls LEN in {64..1024} + 256 float32 reductions n in [2^16, 2^24]",
+         "tile_threshold": info["tile_threshold"]},
+        batch=info, create_s=create_s, mfma_tflops=mfma, mfma_frac=mfma / PEAK_BF16_TFLOPS,
+        reduce_gbs_if_alone=info["reduce_bytes"] / (ms * 1e-3) / 1e9, eager_kernels_ms=kt,
+        one_call_per_item_ms=per_item_ms,
+        accuracy={"matmul_rel_fro_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                  "reduce_max_rel_err": red_err})))
+    return 0
+
+
+def run_serve(args) -> int:
+    """Poisson 2000 requests/s of offload-region requests through the
+    serving engine; latency from scheduled arrival to completion."""
+    import numpy as np
+
+    import oracle
+    import paper_1412_1127_amd as ax
+    from paper_1412_1127_amd import serve
+    import synth
+    ax.acc_init(0, 0)
+    wl = serve.make_workload(args.requests, synth.DEFAULT_SEED)
+    pools = serve.Pools(wl)
+    g = synth.rng(synth.DEFAULT_SEED, 4)
+    errs, exact = [], []
+
+    def check(r, view):
+        a, b = pools.inputs(r)
+        a, b = a.numpy().reshape(r.n, r.n), b.numpy().reshape(r.n, r.n)
+        c = view.numpy().reshape(r.n, r.n)
+        ii, jj = g.integers(0, r.n, 8), g.integers(0, r.n, 8)
+        ref = oracle.matmul_at(a, b, ii, jj)
+        if r.dtype == ax.ACC_INT32:
+            exact.append(bool(np.array_equal(c[ii, jj], ref)))
+        else:
+            errs.append(float(np.linalg.norm(c[ii, jj] - ref) / np.linalg.norm(ref)))
+    serve.run(wl, pools, slots=8, budget=64 << 30)  # warm-up pass (kernels, block cache)
+    res = serve.run(wl, pools, slots=8, budget=64 << 30, on_region_done=check)
+    ax.acc_shutdown()
+    rr = res.pop("reduce_results")
+    red = [abs(rr[q.tag] - oracle.sum_f32(pools.inputs(wl.regions[q.region])[0].numpy(), q.init)) /
+           oracle.sum_f32(pools.inputs(wl.regions[q.region])[0].numpy(), q.init)
+           for q in wl.requests[:400] if q.tag in rr]
+    print(json.dumps(_common(
+        args, "serving p50 latency (ms) at 2000 requests/s; p99 and throughput alongside", res["latency_ms"]["p50"],
+        "ms", res["latency_ms"]["p50"],
+        {"workload": "serving: Poisson 2000 req/s, 70% matmuls (LEN log-uniform [128, 2048], float32/int32), "
+                     "30% reductions (n log-uniform [2^16, 2^26]), 4 requests per region, 64 GB budget",
+         "requests": args.requests, "slots": 8},
+        higher=False, latency_ms=res["latency_ms"], serving=res,
+        accuracy={"matmul_f32_max_rel_fro_sampled": max(errs) if errs else None,
+                  "matmul_i32_bit_exact_sampled": all(exact), "reduce_max_rel_err": max(red) if red else None})))
+    return 0
+
+
+def main() -> int:
+    args = _args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: every step of this offload path runs on a single device, "
+              "and no multi-GPU form is built; run with --gpus 1.", file=sys.stderr)
+        return 2
+    return {"scale": run_scale, "small": run_small, "precision": run_precision, "batch": run_batch,
+            "serve": run_serve}[args.workload](args)
 
 
 if __name__ == "__main__":
