@@ -46,7 +46,7 @@ def _args():
                    help="rows of C the CPU baseline computes per matmul, scaled to the whole step "
                         "(0: all LEN rows, the whole step)")
     p.add_argument("--no-verify", action="store_true")
-    p.add_argument("--tile", choices=["256", "256x128", "128", "64"], default=None,
+    p.add_argument("--tile", choices=["256", "256x128", "128", "64", "256w4"], default=None,
                    help="force the float32 tile configuration (implies --no-autotune)")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the tile autotuner before the timed region (size heuristic instead)")

@@ -106,6 +106,7 @@ typedef struct acc_region_s *acc_region; /* opaque */
 #define ACC_TILE_256x128 0x20000u /* 256 x 128, 4 wavefronts, 2 workgroups/CU */
 #define ACC_TILE_128 0x30000u     /* 128 x 128, 4 wavefronts */
 #define ACC_TILE_64 0x40000u      /* 64 x 64, 4 wavefronts */
+#define ACC_TILE_256W4 0x50000u   /* 256 x 256 output tile, 4 wavefronts */
 
 /* ---- flags for acc_reduce_sum / accx_reduce_sum_dev --------------------- */
 #define ACC_REDUCE_FAST 0x0u  /* single pass, last-block-done final stage */

@@ -53,7 +53,9 @@ ACC_SERVE_REDUCE = 1
 ACC_BATCH_MATMUL = 0
 ACC_BATCH_REDUCE = 1
 ACC_BATCH_AUTOTUNE = 0x1
-TILES = {"256": ACC_TILE_256, "256x128": ACC_TILE_256x128, "128": ACC_TILE_128, "64": ACC_TILE_64}
+ACC_TILE_256W4 = 0x50000
+TILES = {"256": ACC_TILE_256, "256x128": ACC_TILE_256x128, "128": ACC_TILE_128, "64": ACC_TILE_64,
+         "256w4": ACC_TILE_256W4}
 
 
 def ACC_LIMBS(n: int) -> int:

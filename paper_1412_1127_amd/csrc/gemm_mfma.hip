@@ -252,6 +252,9 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
 //           two workgroups per CU that do not share barriers.
 //  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3).
 //  T64       64 x 64,  4 waves (2x2), 64 B, 2 stages (several int8 planes).
+//  T256W4   256 x 256, 4 waves (2x2, 128 x 128 each), 32 B / 64 B, 3 stages:
+//           a third less LDS read traffic per matrix instruction than T256,
+//           one wavefront per SIMD, accumulators in AGPRs.
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC>
 hipError_t launch_tile(GemmArgs g, hipStream_t s)
 {
@@ -274,6 +277,8 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
     case GEMM_TILE_256:
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, multi ? 2 : 4, multi ? 2 : 3, NPROD, PL,
                            NACC>(g, s);
+    case GEMM_TILE_256W4:
+        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, 2, multi ? 2 : 3, NPROD, PL, NACC>(g, s);
     case GEMM_TILE_256x128:
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 128, KS, 2, 2, 2, NPROD, PL, NACC>(g, s);
     case GEMM_TILE_128:
@@ -377,8 +382,8 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans,
 void tile_dims(int tile, int64_t len, int &bm, int &bn)
 {
     const int t = tile ? tile : default_tile(len);
-    bm = t == GEMM_TILE_256 || t == GEMM_TILE_256x128 ? 256 : t == GEMM_TILE_128 ? 128 : 64;
-    bn = t == GEMM_TILE_256 ? 256 : t == GEMM_TILE_256x128 ? 128 : bm;
+    bm = (t == GEMM_TILE_256 || t == GEMM_TILE_256W4 || t == GEMM_TILE_256x128) ? 256 : t == GEMM_TILE_128 ? 128 : 64;
+    bn = (t == GEMM_TILE_256 || t == GEMM_TILE_256W4) ? 256 : t == GEMM_TILE_256x128 ? 128 : bm;
 }
 
 hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, int64_t len, int tile, double tau,

@@ -45,7 +45,7 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans,
 // CHEAP3.  accumulate: C += instead of C =.
 // tile: one of GEMM_TILE_* (0 = size heuristic).
 enum { GEMM_TILE_DEFAULT = 0, GEMM_TILE_256 = 1, GEMM_TILE_256x128 = 2, GEMM_TILE_128 = 3, GEMM_TILE_64 = 4,
-       GEMM_TILE_COUNT = 5 };
+       GEMM_TILE_256W4 = 5, GEMM_TILE_COUNT = 6 };
 // Per-tile record of the float64 error probe (layout documented in accx.h).
 struct ProbeRecord {
     int32_t rows[4], cols[4];  // sampled rows and columns of the tile

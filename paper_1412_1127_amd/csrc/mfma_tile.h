@@ -255,7 +255,9 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     static_assert(NS * STAGE <= 160 * 1024, "LDS");
     static_assert(NPL <= P, "product list names a plane the operand lacks");
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wavefront index in a scalar register: everything derived from it
+    // (copy descriptors, fragment offsets) stays out of vector registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wm = wave / WGN, wn = wave % WGN;
     const int64_t ustride = (int64_t)P * PLANE_BYTES;  // bytes per packed unit
     const int64_t rb0 = (int64_t)tm * MB, cb0 = (int64_t)tn * NB;
@@ -274,7 +276,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
         int64_t rb = (isA ? rb0 : cb0) + u;
         const int64_t nrb = isA ? g.nrb_a : g.nrb_b;
         if (rb >= nrb) rb = nrb - 1;
-        src_base[c] = (isA ? g.A : g.B) + rb * g.nkb * ustride + p * PLANE_BYTES + piece * 1024 + lane * 16;
+        src_base[c] = (isA ? g.A : g.B) + rb * g.nkb * ustride + p * PLANE_BYTES + piece * 1024;
         dst_off[c] = (isA ? 0 : MB * LUNIT) + u * LUNIT + p * (32 * KBK) + piece * 1024;
     }
 
@@ -284,7 +286,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
         char *sbase = lds + (step % NS) * STAGE;
 #pragma unroll
         for (int c = 0; c < LPW; ++c)
-            dma16(src_base[c] + kb * ustride + h * (KBK * 32), sbase + dst_off[c]);
+            dma16(src_base[c] + kb * ustride + h * (KBK * 32) + lane * 16, sbase + dst_off[c]);
     };
 
     Acc acc[NACC][WBM][WBN];

@@ -151,7 +151,7 @@ def test_precision_8192_rowscaled(ax):
     assert err <= FP32_REL_FRO_TOL
 
 
-@pytest.mark.parametrize("tile", ["256", "256x128", "128", "64"])
+@pytest.mark.parametrize("tile", ["256", "256x128", "128", "64", "256w4"])
 @pytest.mark.parametrize("n", [100, 257, 1000])
 def test_every_tile_config(ax, tile, n):
     t = ax.TILES[tile]
