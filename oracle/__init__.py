@@ -51,6 +51,8 @@ def lib():
             "oracle_matmul_i32": (None, [i64, vp, vp, vp]),
             "oracle_matmul_f32_rows": (None, [i64, i64, i64, vp, vp, vp]),
             "oracle_matmul_i32_rows": (None, [i64, i64, i64, vp, vp, vp]),
+            "oracle_gemm_f32": (None, [i64, i64, i64, vp, i64, vp, i64, vp, i64]),
+            "oracle_gemm_i32": (None, [i64, i64, i64, vp, i64, vp, i64, vp, i64]),
             "oracle_matmul_f32_at": (None, [i64, vp, vp, i64, vp, vp, vp]),
             "oracle_matmul_i32_at": (None, [i64, vp, vp, i64, vp, vp, vp]),
             "oracle_sum_f32": (f64, [i64, vp, f64]),
@@ -105,6 +107,33 @@ def matmul_i32(a: np.ndarray, b: np.ndarray, literal_order: bool = False) -> np.
     c = np.empty((n, n), dtype=np.int32)
     fn = lib().oracle_matmul_i32_ijl if literal_order else lib().oracle_matmul_i32
     fn(n, _p(a), _p(b), _p(c))
+    return c
+
+
+def _rowmajor_ld(x: np.ndarray) -> int:
+    """Leading dimension (elements) of a 2-D row-major view; rows may be padded."""
+    if x.ndim != 2 or x.strides[1] != x.itemsize or x.strides[0] % x.itemsize or x.strides[0] < x.shape[1] * x.itemsize:
+        raise ValueError("2-D row-major array (unit column stride) expected")
+    return x.strides[0] // x.itemsize
+
+
+def gemm(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Listing 1a's loop nest on rectangular operands: C (m x n) = A (m x k) B (k x n),
+    float64 accumulation for float32 inputs, wraparound mod 2**32 for int32.
+    A and B may be row-major views with padded rows (leading dimensions)."""
+    if a.ndim != 2 or b.ndim != 2 or a.shape[1] != b.shape[0] or a.dtype != b.dtype:
+        raise ValueError("A (m x k) and B (k x n) of one dtype expected")
+    m, k = a.shape
+    n = b.shape[1]
+    lda, ldb = _rowmajor_ld(a), _rowmajor_ld(b)
+    if a.dtype == np.float32:
+        c = np.empty((m, n), dtype=np.float64)
+        lib().oracle_gemm_f32(m, n, k, _p(a), lda, _p(b), ldb, _p(c), n)
+    elif a.dtype == np.int32:
+        c = np.empty((m, n), dtype=np.int32)
+        lib().oracle_gemm_i32(m, n, k, _p(a), lda, _p(b), ldb, _p(c), n)
+    else:
+        raise ValueError("float32 or int32 operands expected")
     return c
 
 

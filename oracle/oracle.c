@@ -141,6 +141,45 @@ void oracle_matmul_i32_rows(int64_t len, int64_t row0, int64_t nrows, const int3
     }
 }
 
+/* The same loop nest on rectangular operands with leading dimensions:
+ * C (m x n) = A (m x k) B (k x n), row-major, element (i, j) of X at
+ * x[i*ldx + j]; c[i*ldc + j] = sum over l ascending of a[i*lda+l]*b[l*ldb+j].
+ * Listing 1a is the case m = n = k = LEN, lda = ldb = ldc = LEN. */
+void oracle_gemm_f32(int64_t m, int64_t n, int64_t k, const float *a, int64_t lda, const float *b, int64_t ldb,
+                     double *c, int64_t ldc)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        double *crow = c + i * ldc;
+        for (int64_t j = 0; j < n; ++j) crow[j] = 0.0;
+        for (int64_t l = 0; l < k; ++l) {
+            const double ail = (double)a[i * lda + l];
+            const float *brow = b + l * ldb;
+            for (int64_t j = 0; j < n; ++j) crow[j] += ail * (double)brow[j];
+        }
+    }
+}
+
+void oracle_gemm_i32(int64_t m, int64_t n, int64_t k, const int32_t *a, int64_t lda, const int32_t *b, int64_t ldb,
+                     int32_t *c, int64_t ldc)
+{
+#pragma omp parallel
+    {
+        uint64_t *acc = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < m; ++i) {
+            for (int64_t j = 0; j < n; ++j) acc[j] = 0;
+            for (int64_t l = 0; l < k; ++l) {
+                const uint64_t ail = (uint64_t)(int64_t)a[i * lda + l];
+                const int32_t *brow = b + l * ldb;
+                for (int64_t j = 0; j < n; ++j) acc[j] += ail * (uint64_t)(int64_t)brow[j];
+            }
+            for (int64_t j = 0; j < n; ++j) c[i * ldc + j] = (int32_t)(uint32_t)acc[j];
+        }
+        free(acc);
+    }
+}
+
 /* Selected entries only, each by the literal l-ascending loop: for sizes
  * where the full product would take too long on the host. */
 void oracle_matmul_f32_at(int64_t len, const float *a, const float *b, int64_t m,

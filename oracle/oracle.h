@@ -13,6 +13,10 @@ void oracle_matmul_i32(int64_t len, const int32_t *a, const int32_t *b, int32_t 
 void oracle_matmul_f32_rows(int64_t len, int64_t row0, int64_t nrows, const float *a, const float *b, double *c);
 void oracle_matmul_i32_rows(int64_t len, int64_t row0, int64_t nrows, const int32_t *a, const int32_t *b,
                             int32_t *c);
+void oracle_gemm_f32(int64_t m, int64_t n, int64_t k, const float *a, int64_t lda, const float *b, int64_t ldb,
+                     double *c, int64_t ldc);
+void oracle_gemm_i32(int64_t m, int64_t n, int64_t k, const int32_t *a, int64_t lda, const int32_t *b, int64_t ldb,
+                     int32_t *c, int64_t ldc);
 void oracle_matmul_f32_at(int64_t len, const float *a, const float *b, int64_t m,
                           const int64_t *ii, const int64_t *jj, double *out);
 void oracle_matmul_i32_at(int64_t len, const int32_t *a, const int32_t *b, int64_t m,

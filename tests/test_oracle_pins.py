@@ -178,6 +178,61 @@ def test_row_slices_match_full():
         oracle.matmul_rows(a, b, 50, 20)
 
 
+# ------------------------------------------------------- rectangular gemm --
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (3, 5, 2), (7, 2, 9), (4, 8, 1)])
+def test_gemm_rational_brute_force(m, n, k):
+    # grid-valued inputs: the float64 accumulation is exact at these sizes
+    a = synth.uniform_pm1_f32((m, k), SEED, 131)
+    b = synth.uniform_pm1_f32((k, n), SEED, 132)
+    c = oracle.gemm(a, b)
+    for i in range(m):
+        for j in range(n):
+            ex = sum((Fraction(float(a[i, l])) * Fraction(float(b[l, j])) for l in range(k)), Fraction(0))
+            assert Fraction(float(c[i, j])) == ex
+
+
+def test_gemm_square_equals_matmul():
+    n = 33
+    a, b = _rand_f32(n, 133), _rand_f32(n, 134)
+    assert np.array_equal(oracle.gemm(a, b), oracle.matmul_f32(a, b))
+    ai, bi = synth.full_range_i32((n, n), SEED, 135), synth.full_range_i32((n, n), SEED, 136)
+    assert np.array_equal(oracle.gemm(ai, bi), oracle.matmul_i32(ai, bi))
+
+
+def test_gemm_leading_dimensions():
+    # views with padded rows give the result of their contiguous copies
+    big_a = synth.uniform_pm1_f32((20, 37), SEED, 137)
+    big_b = synth.uniform_pm1_f32((30, 41), SEED, 138)
+    a, b = big_a[3:15, 5:29], big_b[2:26, 7:40]          # 12 x 24 and 24 x 33
+    assert np.array_equal(oracle.gemm(a, b), oracle.gemm(np.ascontiguousarray(a), np.ascontiguousarray(b)))
+    bia = synth.full_range_i32((20, 37), SEED, 139)
+    bib = synth.full_range_i32((30, 41), SEED, 140)
+    ai, bi = bia[3:15, 5:29], bib[2:26, 7:40]
+    assert np.array_equal(oracle.gemm(ai, bi), oracle.gemm(np.ascontiguousarray(ai), np.ascontiguousarray(bi)))
+
+
+def test_gemm_outer_product_and_transpose():
+    # k = 1: C is the outer product, every entry one exact product
+    a = synth.uniform_pm1_f32((9, 1), SEED, 141)
+    b = synth.uniform_pm1_f32((1, 13), SEED, 142)
+    assert np.array_equal(oracle.gemm(a, b), a.astype(np.float64) @ b.astype(np.float64))
+    # (AB)^T == B^T A^T bitwise on rectangular shapes
+    g = synth.rng(SEED, 143)
+    a = g.standard_normal((6, 11)).astype(np.float32)
+    b = g.standard_normal((11, 4)).astype(np.float32)
+    lhs = oracle.gemm(a, b).T
+    rhs = oracle.gemm(np.ascontiguousarray(b.T), np.ascontiguousarray(a.T))
+    assert np.array_equal(lhs, rhs)
+
+
+def test_gemm_int_associativity_rectangular():
+    a = synth.full_range_i32((3, 5), SEED, 144)
+    b = synth.full_range_i32((5, 2), SEED, 145)
+    c = synth.full_range_i32((2, 4), SEED, 146)
+    assert np.array_equal(oracle.gemm(oracle.gemm(a, b), c), oracle.gemm(a, oracle.gemm(b, c)))
+
+
 # --------------------------------------------------------------- matmul i32 --
 
 @pytest.mark.parametrize("n", [1, 2, 4, 8])
