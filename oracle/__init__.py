@@ -57,6 +57,7 @@ def lib():
             "oracle_matmul_i32_at": (None, [i64, vp, vp, i64, vp, vp, vp]),
             "oracle_sum_f32": (f64, [i64, vp, f64]),
             "oracle_sum_i32": (i32, [i64, vp, i32]),
+            "oracle_reduce": (None, [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, i64, vp, vp]),
             "oracle_round_bf16": (ctypes.c_uint16, [ctypes.c_float]),
             "oracle_bf16_value": (f64, [ctypes.c_uint16]),
             "oracle_split_bf16x3": (None, [i64, vp, vp, vp, vp]),
@@ -183,6 +184,44 @@ def sum_i32(x: np.ndarray, init: int = 0) -> int:
     """reduction(+) over int32 with wraparound: (init + sum x) mod 2**32 as int32."""
     x = np.ascontiguousarray(x, dtype=np.int32)
     return int(lib().oracle_sum_i32(x.size, _p(x), int(np.int32(init))))
+
+
+REDUCE_OPS = {"sum": 0, "max": 1, "min": 2, "or": 3}
+_RED_DTYPES = {np.dtype(np.float32): (0, np.float64), np.dtype(np.int32): (1, np.int32),
+               np.dtype(np.float64): (2, np.float64), np.dtype(np.int64): (3, np.int64)}
+
+
+def identity(op: str, dtype) -> float | int:
+    """The value that leaves a reduction unchanged: 0 for + and logical or,
+    the lowest value for max, the highest for min."""
+    dt = np.dtype(dtype)
+    if op in ("sum", "or"):
+        return 0
+    if dt.kind == "f":
+        return -np.inf if op == "max" else np.inf
+    info = np.iinfo(dt)
+    return int(info.min) if op == "max" else int(info.max)
+
+
+def reduce(x: np.ndarray, op: str, init=None, square: bool = False):
+    """One reduction variable (section 2.3's reduction lowering with the
+    operators +, max, min and logical or): init (op) f(x[0]) (op) f(x[1]) ...
+    in index order, f(x) = x or x*x in the element type.  float32: + in
+    float64; float64: + in long double; int32/int64: + and * wrap around;
+    max/min ignore NaN operands; 'or' gives 1 if init or any element is
+    nonzero, else 0.  Returns a Python float (float types) or int."""
+    x = np.ascontiguousarray(x)
+    if x.dtype not in _RED_DTYPES:
+        raise ValueError("float32, int32, float64 or int64 elements expected")
+    if op not in REDUCE_OPS:
+        raise ValueError("op must be one of %s" % sorted(REDUCE_OPS))
+    if op == "or" and square:
+        raise ValueError("logical or takes the elements themselves")
+    code, out_t = _RED_DTYPES[x.dtype]
+    iv = np.array([identity(op, x.dtype) if init is None else init], dtype=x.dtype)
+    out = np.zeros(1, dtype=out_t)
+    lib().oracle_reduce(code, REDUCE_OPS[op], int(bool(square)), _p(x), x.size, _p(iv), _p(out))
+    return float(out[0]) if out_t == np.float64 else int(out[0])
 
 
 def round_bf16(x: float) -> int:

@@ -224,6 +224,88 @@ int32_t oracle_sum_i32(int64_t n, const int32_t *x, int32_t init)
     return (int32_t)(uint32_t)(uint64_t)s;
 }
 
+/* --------------------------------------- reduction operators and types -- */
+/* The reduction clause with the operators +, max, min and logical or
+ * (section 2.3's reduction lowering; the BFS paragraph of section 4.2 names
+ * a boolean "more nodes" flag, the SRAD paragraph a loop with two sum
+ * variables).  One variable: out = init (op) f(x[0]) (op) f(x[1]) ... in
+ * index order, where f(x) = x, or f(x) = x*x evaluated in the element type
+ * (as the loop body `v += t * t` does in C).
+ *   dtype 0 float32: + accumulates in double; max/min exact (fmax/fmin: a
+ *                    NaN operand is ignored); out: double.
+ *   dtype 1 int32:   + and * modulo 2^32; max/min signed; out: int32.
+ *   dtype 2 float64: + accumulates in long double; out: double.
+ *   dtype 3 int64:   + and * modulo 2^64; out: int64.
+ *   op 3 (logical or): out = 1 if init or any x[k] compares unequal to zero,
+ *                    else 0 (f must be the identity).
+ * init points to one value of the element type. */
+void oracle_reduce(int dtype, int op, int square, const void *x, int64_t n, const void *init, void *out)
+{
+    if (op == 3) {
+        int any = 0;
+        for (int64_t k = -1; k < n && !any; ++k) {
+            const void *p = k < 0 ? init : x;
+            const int64_t i = k < 0 ? 0 : k;
+            switch (dtype) {
+            case 0: any = ((const float *)p)[i] != 0.0f; break;
+            case 1: any = ((const int32_t *)p)[i] != 0; break;
+            case 2: any = ((const double *)p)[i] != 0.0; break;
+            default: any = ((const int64_t *)p)[i] != 0; break;
+            }
+        }
+        switch (dtype) {
+        case 0: *(double *)out = any; break;
+        case 1: *(int32_t *)out = any; break;
+        case 2: *(double *)out = any; break;
+        default: *(int64_t *)out = any; break;
+        }
+        return;
+    }
+    if (dtype == 0) {
+        const float *v = (const float *)x;
+        double acc = *(const float *)init;
+        for (int64_t k = 0; k < n; ++k) {
+            const float t = square ? v[k] * v[k] : v[k];
+            acc = op == 0 ? acc + (double)t : op == 1 ? fmax(acc, (double)t) : fmin(acc, (double)t);
+        }
+        *(double *)out = acc;
+    } else if (dtype == 2) {
+        const double *v = (const double *)x;
+        long double acc = *(const double *)init;
+        for (int64_t k = 0; k < n; ++k) {
+            const double t = square ? v[k] * v[k] : v[k];
+            acc = op == 0 ? acc + (long double)t : op == 1 ? fmaxl(acc, (long double)t) : fminl(acc, (long double)t);
+        }
+        *(double *)out = (double)acc;
+    } else if (dtype == 1) {
+        const int32_t *v = (const int32_t *)x;
+        uint32_t acc = (uint32_t) * (const int32_t *)init;
+        for (int64_t k = 0; k < n; ++k) {
+            const uint32_t t = square ? (uint32_t)v[k] * (uint32_t)v[k] : (uint32_t)v[k];
+            if (op == 0)
+                acc += t;
+            else if (op == 1)
+                acc = (int32_t)t > (int32_t)acc ? t : acc;
+            else
+                acc = (int32_t)t < (int32_t)acc ? t : acc;
+        }
+        *(int32_t *)out = (int32_t)acc;
+    } else {
+        const int64_t *v = (const int64_t *)x;
+        uint64_t acc = (uint64_t) * (const int64_t *)init;
+        for (int64_t k = 0; k < n; ++k) {
+            const uint64_t t = square ? (uint64_t)v[k] * (uint64_t)v[k] : (uint64_t)v[k];
+            if (op == 0)
+                acc += t;
+            else if (op == 1)
+                acc = (int64_t)t > (int64_t)acc ? t : acc;
+            else
+                acc = (int64_t)t < (int64_t)acc ? t : acc;
+        }
+        *(int64_t *)out = (int64_t)acc;
+    }
+}
+
 /* ------------------------------------------------------ bf16 3-term split -- */
 
 static float bits_to_float(uint32_t u)

@@ -23,6 +23,7 @@ void oracle_matmul_i32_at(int64_t len, const int32_t *a, const int32_t *b, int64
                           const int64_t *ii, const int64_t *jj, int32_t *out);
 
 double oracle_sum_f32(int64_t n, const float *x, double init);
+void oracle_reduce(int dtype, int op, int square, const void *x, int64_t n, const void *init, void *out);
 int32_t oracle_sum_i32(int64_t n, const int32_t *x, int32_t init);
 
 uint16_t oracle_round_bf16(float x);

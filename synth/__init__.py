@@ -74,6 +74,26 @@ def full_range_i32(shape, seed: int, stream: int) -> np.ndarray:
     return g.integers(-(1 << 31), 1 << 31, size=shape, dtype=np.int64).astype(np.int32)
 
 
+def uniform_pm1_f64(n: int, seed: int, stream: int) -> np.ndarray:
+    """uniform[-1, 1) as float64; every value is k * 2**-52 for an integer k."""
+    g = rng(seed, stream)
+    k = g.integers(-(1 << 52), 1 << 52, size=int(n), dtype=np.int64)
+    return k.astype(np.float64) * 2.0 ** -52
+
+
+def full_range_i64(n: int, seed: int, stream: int) -> np.ndarray:
+    """Integers uniform over all of int64."""
+    g = rng(seed, stream)
+    return g.integers(-(1 << 63), (1 << 63) - 1, size=int(n), dtype=np.int64, endpoint=True)
+
+
+def sparse_flags_i32(n: int, density: float, seed: int, stream: int) -> np.ndarray:
+    """0/1 int32 flags, each 1 with probability `density` (a BFS frontier's
+    "visit next" marks)."""
+    g = rng(seed, stream)
+    return (g.random(int(n)) < density).astype(np.int32)
+
+
 def normal_rowscaled_f32(rows: int, cols: int, seed: int, stream: int,
                          umin: float = -8.0, umax: float = 8.0) -> np.ndarray:
     """N(0,1) * 2**U per row, U ~ Uniform[umin, umax), rounded once to float32."""

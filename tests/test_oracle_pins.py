@@ -411,3 +411,102 @@ def test_maxabs():
     assert oracle.maxabs_i32(np.array([-(2 ** 31), 5], np.int32)) == 2 ** 31
     assert oracle.maxabs_i32(np.array([3, -4, 2], np.int32)) == 4
     assert oracle.maxabs_i32(np.zeros(0, np.int32)) == 0
+
+
+# ------------------------------------------- reduction operators and types --
+
+def test_reduce_int_closed_forms():
+    n = 100_000
+    k = np.arange(1, n + 1, dtype=np.int64)
+    assert oracle.reduce(k, "sum") == n * (n + 1) // 2
+    assert oracle.reduce(k, "sum", square=True) == n * (n + 1) * (2 * n + 1) // 6
+    assert oracle.reduce(k, "sum", init=-5) == n * (n + 1) // 2 - 5
+    assert oracle.reduce(k, "max") == n and oracle.reduce(k, "min") == 1
+    assert oracle.reduce(k, "max", init=n + 7) == n + 7 and oracle.reduce(k, "min", init=-3) == -3
+    k32 = k[:1000].astype(np.int32)
+    assert oracle.reduce(k32, "sum", square=True) == 1000 * 1001 * 2001 // 6
+
+
+def test_reduce_int_wraparound():
+    # 5 * 2^30 = 2^32 + 2^30; 65536^2 = 2^32; int64: 2^62 * 4 = 2^64
+    assert oracle.reduce(np.full(5, 1 << 30, np.int32), "sum") == 1 << 30
+    assert oracle.reduce(np.array([65536, 3], np.int32), "sum", square=True) == 9
+    assert oracle.reduce(np.full(4, 1 << 62, np.int64), "sum", init=7) == 7
+    assert oracle.reduce(np.array([1 << 32], np.int64), "sum", square=True) == 0
+    # bignum brute force on full-range values
+    for dt, bits, stream in ((np.int32, 32, 201), (np.int64, 64, 202)):
+        x = (synth.full_range_i32(500, SEED, stream) if dt == np.int32 else synth.full_range_i64(500, SEED, stream))
+        for sq in (False, True):
+            exact = sum(int(v) * int(v) if sq else int(v) for v in x) % (1 << bits)
+            if exact >= 1 << (bits - 1):
+                exact -= 1 << bits
+            assert oracle.reduce(x, "sum", square=sq) == exact
+
+
+def test_reduce_extremes_and_signed_order():
+    x = np.array([-(1 << 63), (1 << 63) - 1, 0, -1], np.int64)
+    assert oracle.reduce(x, "max") == (1 << 63) - 1 and oracle.reduce(x, "min") == -(1 << 63)
+    y = synth.full_range_i32(4001, SEED, 203)
+    assert oracle.reduce(y, "max") == int(max(y.tolist())) and oracle.reduce(y, "min") == int(min(y.tolist()))
+    z = synth.full_range_i64(4001, SEED, 204)
+    assert oracle.reduce(z, "max") == max(z.tolist()) and oracle.reduce(z, "min") == min(z.tolist())
+
+
+def test_reduce_f64_sum_against_exact_sum():
+    # grid values: the long-double sum of 4096 multiples of 2^-52 in [-1, 1) is exact
+    x = synth.uniform_pm1_f64(4096, SEED, 205)
+    assert oracle.reduce(x, "sum") == math.fsum(x.tolist())
+    # arbitrary doubles: within a few units of the last place of the exact sum
+    g = synth.rng(SEED, 206)
+    y = g.random(100_000)
+    ex = math.fsum(y.tolist())
+    assert abs(oracle.reduce(y, "sum") - ex) <= 4 * 2.0 ** -52 * ex
+    # squares are rounded to double first (the loop body's own arithmetic)
+    ex2 = math.fsum((np.float64(v) * np.float64(v)) for v in y[:20_000])
+    assert abs(oracle.reduce(y[:20_000], "sum", square=True) - ex2) <= 4 * 2.0 ** -52 * ex2
+
+
+def test_reduce_f32_sum_and_squares():
+    x = synth.uniform_pm1_f32((3000,), SEED, 207)
+    assert oracle.reduce(x, "sum") == math.fsum(float(v) for v in x)          # grid values: exact
+    sq = [float(np.float32(v) * np.float32(v)) for v in x]                       # rounded to float32
+    assert oracle.reduce(x, "sum", square=True) == pytest.approx(math.fsum(sq), rel=1e-14)
+    assert oracle.reduce(x, "sum", init=2.5) == 2.5 + math.fsum(float(v) for v in x)
+    assert oracle.reduce(x, "max", square=True) == max(sq) and oracle.reduce(x, "min", square=True) == min(sq)
+    # agrees with the pinned float32 sum
+    u = synth.uniform01_f32(5000, SEED, 208)
+    assert oracle.reduce(u, "sum", init=1.0) == oracle.sum_f32(u, 1.0)
+
+
+def test_reduce_max_min_ignore_nan():
+    x = synth.uniform_pm1_f32((1000,), SEED, 209).astype(np.float64)
+    x[[0, 17, 999]] = np.nan
+    assert oracle.reduce(x, "max") == np.nanmax(x) and oracle.reduce(x, "min") == np.nanmin(x)
+    assert oracle.reduce(x.astype(np.float32), "max") == float(np.nanmax(x))
+    allnan = np.full(5, np.nan)
+    assert oracle.reduce(allnan, "max") == -np.inf           # the identity init survives
+    assert math.isnan(oracle.reduce(allnan, "max", init=np.nan))
+    assert oracle.reduce(allnan, "max", init=3.0) == 3.0
+    assert oracle.reduce(np.array([np.nan, 2.0]), "min", init=np.nan) == 2.0
+
+
+def test_reduce_logical_or():
+    z = np.zeros(1000, np.int32)
+    assert oracle.reduce(z, "or") == 0 and oracle.reduce(z, "or", init=5) == 1
+    z[-1] = 1
+    assert oracle.reduce(z, "or") == 1
+    assert oracle.reduce(np.array([0, 1 << 40], np.int64), "or") == 1    # high bits only
+    assert oracle.reduce(np.array([-0.0, 0.0], np.float32), "or") == 0   # -0 equals zero
+    assert oracle.reduce(np.array([0.0, np.nan]), "or") == 1             # NaN is unequal to zero
+    f = synth.sparse_flags_i32(100_000, 1e-4, SEED, 210)
+    assert oracle.reduce(f, "or") == int(f.any())
+    assert oracle.reduce(np.zeros(0, np.float64), "or", init=0.0) == 0
+    with pytest.raises(ValueError):
+        oracle.reduce(f, "or", square=True)
+
+
+def test_reduce_empty_returns_init():
+    for dt in (np.float32, np.int32, np.float64, np.int64):
+        e = np.zeros(0, dt)
+        for op in ("sum", "max", "min"):
+            assert oracle.reduce(e, op, init=3) == 3
