@@ -50,9 +50,11 @@ def _args():
                    help="force the float32 tile configuration (implies --no-autotune)")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the tile autotuner before the timed region (size heuristic instead)")
-    p.add_argument("--workload", choices=["scale", "small", "precision", "batch", "serve"], default="scale",
+    p.add_argument("--workload", choices=["scale", "small", "precision", "batch", "serve", "rowblock"],
+                   default="scale",
                    help="scale (default): the step described above; the others measure the remaining "
-                        "configurations (LEN=256 plain method, LEN=8192 precision, batching, serving)")
+                        "configurations (LEN=256 plain method, LEN=8192 precision, batching, serving) and "
+                        "one GPU's 512-row block of the LEN=4096 product (rowblock)")
     p.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
@@ -443,6 +445,81 @@ def run_batch(args) -> int:
     return 0
 
 
+def run_rowblock(args) -> int:
+    """One GPU's share of the LEN=4096 product split by row blocks over eight
+    GPUs: C (512 x 4096) = A (512 x 4096) B (4096 x 4096), float32 on the
+    bf16x3 path (six products) and int32 on the int8-limb path, through the
+    rectangular entry point; error on sampled rows vs the float64 oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1412_1127_amd as ax
+    import synth
+    m, n, k = 512, 4096, 4096
+    seed = synth.DEFAULT_SEED
+    a = synth.uniform_pm1_f32((m, k), seed, synth.STREAM_A)
+    b = synth.uniform_pm1_f32((k, n), seed, synth.STREAM_B)
+    ai = synth.int_uniform_i32((m, k), -16, 16, seed, synth.STREAM_A)
+    bi = synth.int_uniform_i32((k, n), -16, 16, seed, synth.STREAM_B)
+    ax.acc_init(0, 0)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    dai, dbi = torch.from_numpy(ai).cuda(), torch.from_numpy(bi).cuda()
+    dc = torch.empty((m, n), device="cuda")
+    dci = torch.empty((m, n), dtype=torch.int32, device="cuda")
+    ff = ax.ACC_KERNEL_TILED | ax.ACC_PREC_FULL6
+    fi = ax.ACC_KERNEL_TILED
+    tuned = {}
+    if not args.no_autotune:
+        tuned["f32"] = ax.accx_autotune_gemm(ax.ACC_FLOAT32, m, n, k, ff)
+        tuned["i32"] = ax.accx_autotune_gemm(ax.ACC_INT32, m, n, k, ax.ACC_LIMBS(1))
+    wf = torch.empty(ax.accx_gemm_workspace_size(ax.ACC_FLOAT32, m, n, k, ff), dtype=torch.uint8, device="cuda")
+    wi = torch.empty(ax.accx_gemm_workspace_size(ax.ACC_INT32, m, n, k, fi), dtype=torch.uint8, device="cuda")
+
+    def step():
+        ax.accx_gemm_dev(ax.ACC_FLOAT32, m, n, k, da, k, db, n, dc, n, ff, wf, wf.numel())
+        ax.accx_gemm_dev(ax.ACC_INT32, m, n, k, dai, k, dbi, n, dci, n, fi, wi, wi.numel())
+
+    ax.accx_timing_enable(True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ax.accx_timing_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kt = {kk: v[1] / v[0] for kk, v in ax.accx_timing_read(reset=True).items()}
+    ax.accx_timing_enable(False)
+    g = synth.rng(seed, 97)
+    rows = np.unique(np.concatenate([[0, m - 1], g.integers(0, m, 30)]))
+    ref = oracle.gemm(np.ascontiguousarray(a[rows]), b)
+    refi = oracle.gemm(np.ascontiguousarray(ai[rows]), bi)
+    c, ci = dc.cpu().numpy()[rows], dci.cpu().numpy()[rows]
+    ax.acc_shutdown()
+    ops = 2.0 * 2.0 * m * n * k
+    gm = kt.get("gemm_bf16x3")
+    achieved = 6 * 2.0 * m * n * k / (gm * 1e-3) / 1e12 if gm else None
+    gi = kt.get("gemm_i8")
+    print(json.dumps(_common(
+        args, "matmul TFLOP/s on one GPU's 512-row block of the LEN=4096 product", ops / (ms * 1e-3) / 1e12,
+        "TFLOP/s", ms,
+        {"workload": "row block: C (512 x 4096) = A (512 x 4096) B (4096 x 4096), float32 uniform[-1,1] and "
+                     "int32 uniform [-16,16]", "m": m, "n": n, "k": k,
+         "tiles": {kk: {"tile": [t for t, v in ax.TILES.items() if v == tv][0], "tune_ms": tms}
+                   for kk, (tv, tms) in tuned.items()}},
+        dtype="f32 (bf16x3 matrix cores) + int32 (int8-limb matrix cores)",
+        roofline={"kernel": "gemm_bf16x3", "bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
+                  "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS if achieved else None},
+        components={"f32_gemm_tflops_fp32_equiv": 2.0 * m * n * k / (gm * 1e-3) / 1e12 if gm else None,
+                    "i32_gemm_tops": 2.0 * m * n * k / (gi * 1e-3) / 1e12 if gi else None,
+                    "kernels_ms": kt},
+        accuracy={"f32_rel_fro_vs_oracle_sampled_rows": float(np.linalg.norm(c - ref) / np.linalg.norm(ref)),
+                  "i32_bit_exact_sampled_rows": bool(np.array_equal(ci, refi)), "rows_checked": int(rows.size)})))
+    return 0
+
+
 def run_serve(args) -> int:
     """Poisson 2000 requests/s of offload-region requests through the
     serving engine; latency from scheduled arrival to completion."""
@@ -495,7 +572,7 @@ def main() -> int:
               "and no multi-GPU form is built; run with --gpus 1.", file=sys.stderr)
         return 2
     return {"scale": run_scale, "small": run_small, "precision": run_precision, "batch": run_batch,
-            "serve": run_serve}[args.workload](args)
+            "serve": run_serve, "rowblock": run_rowblock}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -59,10 +59,32 @@ typedef enum {
 } acc_status;
 
 /* Data clauses (section 1.3): copy = copy in at region entry and out at exit;
- * copyin = in only; copyout = out only; create = device allocation only. */
-typedef enum { ACC_COPY = 0, ACC_COPYIN = 1, ACC_COPYOUT = 2, ACC_CREATE = 3 } acc_clause_kind;
+ * copyin = in only; copyout = out only; create = device allocation only.
+ * present = the range must already be mapped (by an enclosing region): the
+ * region uses that mapping.  present_or_X = present if the range is already
+ * mapped, else X.  Mappings are reference counted: every clause of every
+ * region that uses a mapping holds one reference, and the mapping is copied
+ * out (if its creating clause was copy or copyout) and freed when the last
+ * region holding a reference ends, whichever region that is. */
+typedef enum {
+    ACC_COPY = 0,
+    ACC_COPYIN = 1,
+    ACC_COPYOUT = 2,
+    ACC_CREATE = 3,
+    ACC_PRESENT = 4,
+    ACC_PRESENT_OR_COPY = 5,
+    ACC_PRESENT_OR_COPYIN = 6,
+    ACC_PRESENT_OR_COPYOUT = 7,
+    ACC_PRESENT_OR_CREATE = 8
+} acc_clause_kind;
 
-typedef enum { ACC_FLOAT32 = 0, ACC_INT32 = 1 } acc_dtype;
+/* directions of acc_update */
+#define ACC_UPDATE_HOST 0   /* device copy -> host (update host / self) */
+#define ACC_UPDATE_DEVICE 1 /* host -> device copy (update device) */
+
+/* Element types.  The matmul takes ACC_FLOAT32 and ACC_INT32; data clauses
+ * and reductions take all four. */
+typedef enum { ACC_FLOAT32 = 0, ACC_INT32 = 1, ACC_FLOAT64 = 2, ACC_INT64 = 3 } acc_dtype;
 
 /* One data clause: host[start : start+n) in elements of `dtype` ("[start:n]
  * means n elements from element start", section 1.3).  `host` is the base of
@@ -147,6 +169,25 @@ ACCX_API acc_status acc_data_end(acc_region region);
 /* Block until all work enqueued on the region has finished. */
 ACCX_API acc_status acc_wait(acc_region region);
 
+/* The update directive: copy host[start : start+n) (elements of dtype t)
+ * between the host and its device copy, which must lie in one mapped range
+ * of dtype t.  Enqueued on the region's stream, in order with its kernels
+ * (the region's stream is its async queue); synchronous unless ACC_ASYNC,
+ * then complete by acc_wait / acc_data_end.
+ * Errors: INVALID_ARG, NOT_PRESENT, DEVICE. */
+ACCX_API acc_status acc_update(acc_region region, int direction, acc_dtype t, void *host, int64_t start, int64_t n,
+                               uint32_t flags);
+
+/* *present_out = 1 if host[0 : bytes) lies inside one mapped range, else 0. */
+ACCX_API acc_status acc_is_present(const void *host, size_t bytes, int *present_out);
+
+/* Page-locked host memory (hipHostMalloc) for region arrays: copies from and
+ * to it run asynchronously on the region's stream, so the transfers of one
+ * region overlap the kernels of another.  Free with accx_host_free.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, NO_DEVICE. */
+ACCX_API acc_status accx_host_alloc(size_t bytes, void **host_out);
+ACCX_API acc_status accx_host_free(void *host);
+
 /* Host-accelerator pointer exchange (section 2.3): the device address of the
  * mapped host address `host`.  Errors: NOT_PRESENT. */
 ACCX_API acc_status acc_deviceptr(const void *host, void **device_out);
@@ -162,15 +203,61 @@ ACCX_API acc_status acc_deviceptr(const void *host, void **device_out);
 ACCX_API acc_status acc_loopnest_matmul(acc_region region, acc_dtype t, const void *a, const void *b,
                                void *c, int64_t len, uint32_t flags);
 
+/* The same nest on rectangular operands with leading dimensions (section
+ * 1.3's loop nest with the trip counts and row strides as parameters; the
+ * output-parallel form of section 4.2's Matrix Multiplication paragraph):
+ *   c[i*ldc + j] = sum over l < k of a[i*lda + l] * b[l*ldb + j],
+ *   0 <= i < m, 0 <= j < n.
+ * Row-major A (m x k), B (k x n), C (m x n); a, b, c are HOST addresses and
+ * the span of each view (from its first to its last element) must lie in one
+ * mapped range of dtype `t`; c's span must not overlap a's or b's.
+ * 0 <= m, n <= 131072; 0 <= k <= 65536; lda >= max(1, k), ldb >= max(1, n),
+ * ldc >= max(1, n), each at most 2^31.  m = 0 or n = 0 does nothing; k = 0
+ * sets C to zero.  Same flags and results as acc_loopnest_matmul, which is
+ * the case m = n = k = lda = ldb = ldc = len.
+ * Errors: INVALID_ARG, NOT_PRESENT, OUT_OF_MEMORY (workspace), DEVICE. */
+ACCX_API acc_status acc_loopnest_gemm(acc_region region, acc_dtype t, int64_t m, int64_t n, int64_t k, const void *a,
+                                      int64_t lda, const void *b, int64_t ldb, void *c, int64_t ldc, uint32_t flags);
+
 /* ---- reduction(+) (section 2.3; SRAD paragraph of section 4.2) ---------- */
 
 /* *inout = *inout + sum of x[0..n), x a HOST address whose n elements lie in
- * one mapped range of dtype `t`; *inout is a host float or int32.  n = 0
- * leaves *inout unchanged.  Synchronous unless ACC_ASYNC, then *inout is
+ * one mapped range of dtype `t`; *inout is a host value of type t (float32
+ * and int32 run the dedicated sum kernels; float64 and int64 the general
+ * ones of acc_reduce).  n = 0 leaves *inout unchanged.  Synchronous unless ACC_ASYNC, then *inout is
  * written by the time acc_wait / acc_data_end returns.
  * Errors: INVALID_ARG, NOT_PRESENT, DEVICE. */
 ACCX_API acc_status acc_reduce_sum(acc_region region, acc_dtype t, const void *x, int64_t n,
                           void *inout_result, uint32_t flags);
+
+/* ---- reduction variables: operators, types, several per loop ------------
+ * The reduction clause with the operators +, max, min and logical or
+ * (section 2.3's reduction lowering; the BFS paragraph of section 4.2 names a
+ * boolean "more nodes" flag, the SRAD paragraph a loop with two sum
+ * variables).  Variable v of a loop over x[0..n):
+ *   result_v = init_v (op) f(x[0]) (op) f(x[1]) ... , f(x) = x, or x*x when
+ *   `square` is 1 (the square in the element type, as `v += t*t` computes it).
+ * +: float32 and float64 add in their own type (any order: the result is
+ * within rounding of the exact sum, and bitwise the same on every run);
+ * int32 and int64 wrap around.  max / min: exact; a NaN element is ignored
+ * (fmax / fmin).  Logical or: result = 1 if init or any element is nonzero,
+ * else 0 (a variable of its own, not squared), computed as a guarded write
+ * (every thread that sees a nonzero element stores 1) instead of a tree.
+ * Up to ACC_MAX_REDUCE_VARS variables over the same array share one pass. */
+typedef enum { ACC_RED_SUM = 0, ACC_RED_MAX = 1, ACC_RED_MIN = 2, ACC_RED_OR = 3 } acc_reduce_op;
+#define ACC_MAX_REDUCE_VARS 4
+typedef struct {
+    int32_t op;     /* acc_reduce_op */
+    int32_t square; /* 0: fold x; 1: fold x*x */
+} acc_reduce_var;
+
+/* inout: nvars HOST values of type t (initial values in, results out), x a
+ * HOST address whose n elements lie in one mapped range of dtype t.  n = 0
+ * leaves every value unchanged (logical or: normalised to 0 or 1).
+ * Synchronous unless ACC_ASYNC, as acc_reduce_sum; ACC_REDUCE_PLAIN only for
+ * one float32 / int32 sum.  Errors: INVALID_ARG, NOT_PRESENT, DEVICE. */
+ACCX_API acc_status acc_reduce(acc_region region, acc_dtype t, const void *x, int64_t n, const acc_reduce_var *vars,
+                               int nvars, void *inout, uint32_t flags);
 
 /* ---- device-pointer entries (memory owned by the caller, e.g. torch) ----- */
 
@@ -186,16 +273,45 @@ ACCX_API acc_status accx_matmul_workspace_size(acc_dtype t, int64_t len, uint32_
 ACCX_API acc_status accx_matmul_dev(acc_dtype t, const void *dA, const void *dB, void *dC, int64_t len,
                            uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
 
+/* Workspace bytes accx_gemm_dev needs for (t, m, n, k, flags); does not
+ * depend on the leading dimensions.  0 for the plain kernels and for m = 0
+ * or n = 0.  Errors: INVALID_ARG. */
+ACCX_API acc_status accx_gemm_workspace_size(acc_dtype t, int64_t m, int64_t n, int64_t k, uint32_t flags,
+                                             size_t *bytes_out);
+
+/* acc_loopnest_gemm's nest on device pointers (4-byte aligned; dA and dB may
+ * be NULL when k = 0; dC's span must not overlap dA's or dB's), enqueued on
+ * `hip_stream` (NULL = the null stream); dWork as for accx_matmul_dev.
+ * Shape limits and results as acc_loopnest_gemm.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_gemm_dev(acc_dtype t, int64_t m, int64_t n, int64_t k, const void *dA, int64_t lda,
+                                  const void *dB, int64_t ldb, void *dC, int64_t ldc, uint32_t flags, void *dWork,
+                                  size_t work_bytes, void *hip_stream);
+
 /* Workspace bytes accx_reduce_sum_dev needs for (t, n, flags). */
 ACCX_API acc_status accx_reduce_workspace_size(acc_dtype t, int64_t n, uint32_t flags, size_t *bytes_out);
 
 /* dResult (device scalar of type t) = init + sum of dX[0..n), enqueued on
- * `hip_stream`.  `init` points to a HOST float or int32.  dWork as above
+ * `hip_stream`.  `init` points to a HOST value of type t.  dWork as above
  * (NULL: library-owned per-stream workspace); a workspace passed in must be
  * zero-filled before its first use, and the kernel leaves it so.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
 ACCX_API acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const void *init, void *dResult,
                                uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
+
+/* Workspace bytes accx_reduce_dev needs for (t, n, vars, flags). */
+ACCX_API acc_status accx_reduce_vars_workspace_size(acc_dtype t, int64_t n, const acc_reduce_var *vars, int nvars,
+                                                    uint32_t flags, size_t *bytes_out);
+
+/* acc_reduce on device memory: dResult[v] (nvars device elements of type t)
+ * = the variable's result; init: nvars HOST values of type t.  dX and
+ * dResult aligned to the element size.  dWork as for accx_reduce_sum_dev
+ * (zero-filled before first use, left so; NULL: library-owned per stream).
+ * accx_reduce_sum_dev is the case of one sum variable.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars,
+                                    const void *init, void *dResult, uint32_t flags, void *dWork, size_t work_bytes,
+                                    void *hip_stream);
 
 /* ---- batched launch --------------------------------------------------------
  * Many independent float32 loop-nest matmuls and reductions on device
@@ -334,18 +450,27 @@ typedef struct {
  * their count, for a float32 tiled call with (len, flags), flags carrying
  * ACC_PREC_AUTO.  Errors: INVALID_ARG. */
 ACCX_API acc_status accx_probe_layout(int64_t len, uint32_t flags, size_t *offset_out, int *count_out);
+/* The same for accx_gemm_dev with (m, n, k, flags); m, n >= 1. */
+ACCX_API acc_status accx_gemm_probe_layout(int64_t m, int64_t n, int64_t k, uint32_t flags, size_t *offset_out,
+                                           int *count_out);
 
 /* ---- autotuner ------------------------------------------------------------
- * Times every tile configuration of the tiled kernel for (t, len, and the
+ * Times every tile configuration of the tiled kernel for (t, m, n, k, and the
  * precision / limb bits of flags) on the current device, on scratch operands
- * of len x len, and records the fastest for len's size class (len rounded up
- * to a power of two).  Later tiled calls with ACC_TILE_AUTO in that class use
- * it.  Allocates and frees its scratch (charged to the budget while held).
+ * of that shape, and records the fastest for the shape's size class (m, n
+ * and k each rounded up to a power of two).  Later tiled calls with
+ * ACC_TILE_AUTO in that class use it; untuned classes take a size heuristic.
+ * Allocates and frees its scratch (charged to the budget while held).
  * best_tile_out: the ACC_TILE_* value chosen; ms_out: its kernel time (both
- * nullable).  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ * nullable).  accx_autotune(t, len, ...) is the square case.
+ * Errors: INVALID_ARG (also m, n or k = 0), OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
 ACCX_API acc_status accx_autotune(acc_dtype t, int64_t len, uint32_t flags, uint32_t *best_tile_out, double *ms_out);
+ACCX_API acc_status accx_autotune_gemm(acc_dtype t, int64_t m, int64_t n, int64_t k, uint32_t flags,
+                                       uint32_t *best_tile_out, double *ms_out);
 /* Write / read the tuned table as text, one line per entry:
- * "dtype variant size_class tile ms".  Errors: INVALID_ARG (I/O, format). */
+ * "dtype variant class_m class_n class_k tile ms"; loading also takes
+ * "dtype variant class tile ms" for a square class.
+ * Errors: INVALID_ARG (I/O, format). */
 ACCX_API acc_status accx_tune_save(const char *path);
 ACCX_API acc_status accx_tune_load(const char *path);
 

@@ -29,7 +29,11 @@ ACC_ERR_DEVICE = -5
 ACC_ERR_NO_DEVICE = -6
 
 ACC_COPY, ACC_COPYIN, ACC_COPYOUT, ACC_CREATE = 0, 1, 2, 3
-ACC_FLOAT32, ACC_INT32 = 0, 1
+ACC_PRESENT, ACC_PRESENT_OR_COPY, ACC_PRESENT_OR_COPYIN, ACC_PRESENT_OR_COPYOUT, ACC_PRESENT_OR_CREATE = 4, 5, 6, 7, 8
+ACC_UPDATE_HOST, ACC_UPDATE_DEVICE = 0, 1
+ACC_FLOAT32, ACC_INT32, ACC_FLOAT64, ACC_INT64 = 0, 1, 2, 3
+ACC_RED_SUM, ACC_RED_MAX, ACC_RED_MIN, ACC_RED_OR = 0, 1, 2, 3
+ACC_MAX_REDUCE_VARS = 4
 
 ACC_KERNEL_AUTO = 0x0
 ACC_KERNEL_PLAIN = 0x1
@@ -110,6 +114,10 @@ class accx_server_stats_t(ctypes.Structure):
                 ("budget_peak", ctypes.c_uint64)]
 
 
+class acc_reduce_var(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("square", ctypes.c_int32)]
+
+
 class acc_clause(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("host", ctypes.c_void_p),
                 ("start", ctypes.c_int64), ("n", ctypes.c_int64)]
@@ -133,12 +141,24 @@ _SIGS = {
     "acc_data_end": [_vp],
     "acc_wait": [_vp],
     "acc_deviceptr": [_vp, ctypes.POINTER(_vp)],
+    "acc_update": [_vp, ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _u32],
+    "acc_is_present": [_vp, _sz, ctypes.POINTER(ctypes.c_int)],
+    "accx_host_alloc": [_sz, ctypes.POINTER(_vp)],
+    "accx_host_free": [_vp],
     "acc_loopnest_matmul": [_vp, ctypes.c_int, _vp, _vp, _vp, _i64, _u32],
+    "acc_loopnest_gemm": [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _u32],
     "acc_reduce_sum": [_vp, ctypes.c_int, _vp, _i64, _vp, _u32],
+    "acc_reduce": [_vp, ctypes.c_int, _vp, _i64, ctypes.POINTER(acc_reduce_var), ctypes.c_int, _vp, _u32],
     "accx_matmul_workspace_size": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_sz)],
     "accx_matmul_dev": [ctypes.c_int, _vp, _vp, _vp, _i64, _u32, _vp, _sz, _vp],
+    "accx_gemm_workspace_size": [ctypes.c_int, _i64, _i64, _i64, _u32, ctypes.POINTER(_sz)],
+    "accx_gemm_dev": [ctypes.c_int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _u32, _vp, _sz, _vp],
     "accx_reduce_workspace_size": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_sz)],
     "accx_reduce_sum_dev": [ctypes.c_int, _vp, _i64, _vp, _vp, _u32, _vp, _sz, _vp],
+    "accx_reduce_vars_workspace_size": [ctypes.c_int, _i64, ctypes.POINTER(acc_reduce_var), ctypes.c_int, _u32,
+                                        ctypes.POINTER(_sz)],
+    "accx_reduce_dev": [ctypes.c_int, _vp, _i64, ctypes.POINTER(acc_reduce_var), ctypes.c_int, _vp, _vp, _u32, _vp,
+                        _sz, _vp],
     "accx_packed_size": [ctypes.c_int, _i64, _i64, ctypes.c_int, ctypes.POINTER(_sz)],
     "accx_pack_dev": [ctypes.c_int, _vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _sz, _vp],
     "accx_batch_create": [ctypes.POINTER(accx_batch_item), ctypes.c_int, _u32, ctypes.POINTER(_vp)],
@@ -154,7 +174,10 @@ _SIGS = {
     "accx_server_stats": [_vp, ctypes.POINTER(accx_server_stats_t)],
     "accx_server_destroy": [_vp],
     "accx_probe_layout": [_i64, _u32, ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_int)],
+    "accx_gemm_probe_layout": [_i64, _i64, _i64, _u32, ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_int)],
     "accx_autotune": [ctypes.c_int, _i64, _u32, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_double)],
+    "accx_autotune_gemm": [ctypes.c_int, _i64, _i64, _i64, _u32, ctypes.POINTER(_u32),
+                           ctypes.POINTER(ctypes.c_double)],
     "accx_tune_save": [ctypes.c_char_p],
     "accx_tune_load": [ctypes.c_char_p],
     "accx_timing_enable": [ctypes.c_int],
@@ -257,9 +280,43 @@ def acc_deviceptr(host) -> int:
     return int(out.value or 0)
 
 
+def acc_update(region: int, direction: int, dtype: int, host, start: int = 0, n: int | None = None,
+               flags: int = 0) -> None:
+    """host: numpy array (n defaults to its size - start) or an address."""
+    if n is None:
+        n = int(host.size) - int(start)
+    _check(_lib.acc_update(region, int(direction), int(dtype), _addr(host), int(start), int(n), int(flags)),
+           "acc_update")
+
+
+def acc_is_present(host, nbytes: int | None = None) -> bool:
+    if nbytes is None:
+        nbytes = int(host.nbytes)
+    out = ctypes.c_int(0)
+    _check(_lib.acc_is_present(_addr(host), int(nbytes), ctypes.byref(out)), "acc_is_present")
+    return bool(out.value)
+
+
+def accx_host_alloc(nbytes: int) -> int:
+    """Address of `nbytes` of page-locked host memory (free with accx_host_free)."""
+    out = _vp(0)
+    _check(_lib.accx_host_alloc(int(nbytes), ctypes.byref(out)), "accx_host_alloc")
+    return int(out.value)
+
+
+def accx_host_free(addr: int) -> None:
+    _check(_lib.accx_host_free(addr), "accx_host_free")
+
+
 def acc_loopnest_matmul(region: int, dtype: int, a, b, c, length: int, flags: int = 0) -> None:
     _check(_lib.acc_loopnest_matmul(region, int(dtype), _addr(a), _addr(b), _addr(c), int(length), int(flags)),
            "acc_loopnest_matmul")
+
+
+def acc_loopnest_gemm(region: int, dtype: int, m: int, n: int, k: int, a, lda: int, b, ldb: int, c, ldc: int,
+                      flags: int = 0) -> None:
+    _check(_lib.acc_loopnest_gemm(region, int(dtype), int(m), int(n), int(k), _addr(a), int(lda), _addr(b), int(ldb),
+                                  _addr(c), int(ldc), int(flags)), "acc_loopnest_gemm")
 
 
 def acc_reduce_sum(region: int, dtype: int, x, n: int, inout, flags: int = 0) -> None:
@@ -280,6 +337,20 @@ def accx_matmul_dev(dtype: int, dA, dB, dC, length: int, flags: int = 0, work=No
                                 _addr(work), int(work_bytes), _stream(stream)), "accx_matmul_dev")
 
 
+def accx_gemm_workspace_size(dtype: int, m: int, n: int, k: int, flags: int = 0) -> int:
+    v = _sz(0)
+    _check(_lib.accx_gemm_workspace_size(int(dtype), int(m), int(n), int(k), int(flags), ctypes.byref(v)),
+           "accx_gemm_workspace_size")
+    return int(v.value)
+
+
+def accx_gemm_dev(dtype: int, m: int, n: int, k: int, dA, lda: int, dB, ldb: int, dC, ldc: int, flags: int = 0,
+                  work=None, work_bytes: int = 0, stream=None) -> None:
+    _check(_lib.accx_gemm_dev(int(dtype), int(m), int(n), int(k), _addr(dA), int(lda), _addr(dB), int(ldb),
+                              _addr(dC), int(ldc), int(flags), _addr(work), int(work_bytes), _stream(stream)),
+           "accx_gemm_dev")
+
+
 def accx_reduce_workspace_size(dtype: int, n: int, flags: int = 0) -> int:
     v = _sz(0)
     _check(_lib.accx_reduce_workspace_size(int(dtype), int(n), int(flags), ctypes.byref(v)),
@@ -287,10 +358,52 @@ def accx_reduce_workspace_size(dtype: int, n: int, flags: int = 0) -> int:
     return int(v.value)
 
 
+_CTYPE = {ACC_FLOAT32: ctypes.c_float, ACC_INT32: ctypes.c_int32, ACC_FLOAT64: ctypes.c_double,
+          ACC_INT64: ctypes.c_int64}
+
+
+def _values(dtype: int, vals):
+    """A host array of the element type holding `vals`."""
+    ct = _CTYPE[int(dtype)]
+    conv = float if dtype in (ACC_FLOAT32, ACC_FLOAT64) else int
+    return (ct * len(vals))(*[conv(v) for v in vals])
+
+
+def _vars(vars_):
+    """[(op, square), ...] or acc_reduce_var instances -> ctypes array."""
+    out = (acc_reduce_var * len(vars_))()
+    for i, v in enumerate(vars_):
+        out[i] = v if isinstance(v, acc_reduce_var) else acc_reduce_var(int(v[0]), int(v[1]))
+    return out
+
+
+def acc_reduce(region: int, dtype: int, x, n: int, vars_, inout, flags: int = 0) -> None:
+    """vars_: [(op, square), ...]; inout: a numpy array of len(vars_) elements of the dtype, updated in place."""
+    v = _vars(vars_)
+    _check(_lib.acc_reduce(region, int(dtype), _addr(x), int(n), v, len(v), _addr(inout), int(flags)), "acc_reduce")
+
+
+def accx_reduce_vars_workspace_size(dtype: int, n: int, vars_, flags: int = 0) -> int:
+    v = _vars(vars_)
+    out = _sz(0)
+    _check(_lib.accx_reduce_vars_workspace_size(int(dtype), int(n), v, len(v), int(flags), ctypes.byref(out)),
+           "accx_reduce_vars_workspace_size")
+    return int(out.value)
+
+
+def accx_reduce_dev(dtype: int, dX, n: int, vars_, init, dResult, flags: int = 0, work=None, work_bytes: int = 0,
+                    stream=None) -> None:
+    """init: Python numbers, one per variable; dResult: len(vars_) device elements of the dtype."""
+    v = _vars(vars_)
+    iv = _values(dtype, init)
+    _check(_lib.accx_reduce_dev(int(dtype), _addr(dX), int(n), v, len(v), iv, _addr(dResult), int(flags),
+                                _addr(work), int(work_bytes), _stream(stream)), "accx_reduce_dev")
+
+
 def accx_reduce_sum_dev(dtype: int, dX, n: int, init, dResult, flags: int = 0, work=None, work_bytes: int = 0,
                         stream=None) -> None:
-    """init: a Python number (marshalled to a host float / int32)."""
-    iv = ctypes.c_float(float(init)) if dtype == ACC_FLOAT32 else ctypes.c_int32(int(init))
+    """init: a Python number (marshalled to a host value of the dtype)."""
+    iv = _CTYPE[int(dtype)](float(init) if dtype in (ACC_FLOAT32, ACC_FLOAT64) else int(init))
     _check(_lib.accx_reduce_sum_dev(int(dtype), _addr(dX), int(n), ctypes.byref(iv), _addr(dResult), int(flags),
                                     _addr(work), int(work_bytes), _stream(stream)), "accx_reduce_sum_dev")
 
@@ -330,6 +443,15 @@ def accx_autotune(dtype: int, length: int, flags: int = 0):
     return int(tile.value), float(ms.value)
 
 
+def accx_autotune_gemm(dtype: int, m: int, n: int, k: int, flags: int = 0):
+    """Time every tile configuration for (dtype, m, n, k, flags); returns (ACC_TILE_* chosen, ms)."""
+    tile = _u32(0)
+    ms = ctypes.c_double(0)
+    _check(_lib.accx_autotune_gemm(int(dtype), int(m), int(n), int(k), int(flags), ctypes.byref(tile),
+                                   ctypes.byref(ms)), "accx_autotune_gemm")
+    return int(tile.value), float(ms.value)
+
+
 def accx_tune_save(path: str) -> None:
     _check(_lib.accx_tune_save(os.fsencode(path)), "accx_tune_save")
 
@@ -343,6 +465,15 @@ def accx_probe_layout(length: int, flags: int):
     off = _sz(0)
     cnt = ctypes.c_int(0)
     _check(_lib.accx_probe_layout(int(length), int(flags), ctypes.byref(off), ctypes.byref(cnt)), "accx_probe_layout")
+    return int(off.value), int(cnt.value)
+
+
+def accx_gemm_probe_layout(m: int, n: int, k: int, flags: int):
+    """(byte offset of the probe records in the accx_gemm_dev workspace, record count)."""
+    off = _sz(0)
+    cnt = ctypes.c_int(0)
+    _check(_lib.accx_gemm_probe_layout(int(m), int(n), int(k), int(flags), ctypes.byref(off), ctypes.byref(cnt)),
+           "accx_gemm_probe_layout")
     return int(off.value), int(cnt.value)
 
 

@@ -48,9 +48,9 @@ __global__ __launch_bounds__(BT) void batch_pack(const BatchPackJob *__restrict_
     const BatchPackJob j = jobs[blockIdx.y];
     const int64_t id0 = (int64_t)blockIdx.x * BT + threadIdx.x, step = (int64_t)gridDim.x * BT;
     if (j.trans)
-        pack_bf16x3_range<true>(j.x, j.rows, j.k, j.out, j.nrb, j.nkb, id0, step);
+        pack_bf16x3_range<true>(j.x, j.rows, j.k, j.ld, j.out, j.nrb, j.nkb, id0, step);
     else
-        pack_bf16x3_range<false>(j.x, j.rows, j.k, j.out, j.nrb, j.nkb, id0, step);
+        pack_bf16x3_range<false>(j.x, j.rows, j.k, j.ld, j.out, j.nrb, j.nkb, id0, step);
 }
 
 __device__ inline float wave_sum_f(float v)

@@ -39,20 +39,21 @@ using namespace dev;
 
 // One thread per (unit, row, chunk): 8 consecutive K elements of one row.
 template <bool TRANS>
-__global__ __launch_bounds__(256) void pack_bf16x3(const float *__restrict__ X, int64_t R, int64_t K,
+__global__ __launch_bounds__(256) void pack_bf16x3(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
                                                    char *__restrict__ out, int64_t nrb, int64_t nkb)
 {
-    pack_bf16x3_range<TRANS>(X, R, K, out, nrb, nkb, (int64_t)blockIdx.x * 256 + threadIdx.x,
+    pack_bf16x3_range<TRANS>(X, R, K, ld, out, nrb, nkb, (int64_t)blockIdx.x * 256 + threadIdx.x,
                              (int64_t)gridDim.x * 256);
 }
 
 
 // int32 -> P balanced base-256 digit planes (int8), 16 K elements per thread.
+// Element addressing as for the bf16x3 pack (leading dimension ld).
 // maxabs (optional): running max of |x| over the operand, as uint32.
 // decide (optional): the two max|x| words of a finished probe pass; the
 // kernel then packs only if limb_gate(decide, expect) holds.
 template <bool TRANS>
-__global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K,
+__global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
                                                char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
                                                uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
                                                int expect)
@@ -75,8 +76,8 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
         const int64_t row = rb * 32 + r;
         const int64_t k0 = kb * 64 + c * 16;
         int32_t v[16];
-        if (!TRANS && row < R && k0 + 16 <= K && ((K & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
-            const i32x4 *p = reinterpret_cast<const i32x4 *>(X + row * K + k0);
+        if (!TRANS && row < R && k0 + 16 <= K && ((ld & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
+            const i32x4 *p = reinterpret_cast<const i32x4 *>(X + row * ld + k0);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const i32x4 w4 = p[q];
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
                 const bool in = row < R && k0 + t < K;
-                v[t] = in ? (TRANS ? X[(k0 + t) * R + row] : X[row * K + k0 + t]) : 0;
+                v[t] = in ? (TRANS ? X[(k0 + t) * ld + row] : X[row * ld + k0 + t]) : 0;
             }
         }
         int64_t rem[16];
@@ -180,14 +181,14 @@ __device__ inline int probe_pick(int64_t tile, int k, int extent)
 // relative Frobenius error exceeds tau (or the samples are all zero but C is
 // not).
 __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, const char *__restrict__ pb,
-                                                 const float *__restrict__ C, int64_t len, int bm, int bn,
+                                                 const float *__restrict__ C, GemmShape sh, int bm, int bn,
                                                  int tiles_n, int64_t nkb, double tau2, ProbeRecord *__restrict__ rec)
 {
     __shared__ double part[4][16];
     const int64_t tile = blockIdx.x;
     const int tm = (int)(tile / tiles_n), tn = (int)(tile % tiles_n);
     const int64_t row0 = (int64_t)tm * bm, col0 = (int64_t)tn * bn;
-    const int rext = (int)min<int64_t>(bm, len - row0), cext = (int)min<int64_t>(bn, len - col0);
+    const int rext = (int)min<int64_t>(bm, sh.m - row0), cext = (int)min<int64_t>(bn, sh.n - col0);
     int64_t rows[4], cols[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -198,8 +199,8 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
     // one 16-byte chunk (8 consecutive k) per plane and vector per step;
-    // elements past len are zero in the packed operands
-    for (int64_t k8 = (int64_t)threadIdx.x * 8; k8 < len; k8 += 256 * 8) {
+    // elements past k are zero in the packed operands
+    for (int64_t k8 = (int64_t)threadIdx.x * 8; k8 < sh.k; k8 += 256 * 8) {
         double av[4][8], bv[4][8];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const double ref = (part[0][q] + part[1][q]) + (part[2][q] + part[3][q]);
-            const double c = (double)C[rows[q / 4] * len + cols[q % 4]];
+            const double c = (double)C[rows[q / 4] * sh.ldc + cols[q % 4]];
             r.ref[q] = ref;
             e2 += (c - ref) * (c - ref);
             r2 += ref * ref;
@@ -289,13 +290,6 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
     return launch_tile<INT8, P, 64, 64, 64, 2, 2, 2, NPROD, PL, NACC>(g, s);
 }
 
-int default_tile(int64_t len)
-{
-    if (len <= 512) return GEMM_TILE_64;
-    if (len <= 2048) return GEMM_TILE_128;
-    return GEMM_TILE_256;
-}
-
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Pseudo-random operands for timing runs (not part of any result): a
@@ -341,6 +335,16 @@ hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s)
     return hipGetLastError();
 }
 
+// The largest square tile that still gives every CU a workgroup; the
+// smallest tile when none does.
+int default_tile(int64_t m, int64_t n)
+{
+    const int64_t cus = device_cu_count();
+    if (cdiv(m, 256) * cdiv(n, 256) >= cus) return GEMM_TILE_256;
+    if (cdiv(m, 128) * cdiv(n, 128) >= cus) return GEMM_TILE_128;
+    return GEMM_TILE_64;
+}
+
 size_t packed_bytes(int64_t rows, int64_t k_elems, int elem_bytes, int planes)
 {
     const int64_t nrb = cdiv(rows, 32);
@@ -348,77 +352,85 @@ size_t packed_bytes(int64_t rows, int64_t k_elems, int elem_bytes, int planes)
     return (size_t)(nrb * nkb * planes * PLANE_BYTES);
 }
 
-hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, bool trans, void *out, hipStream_t s)
+hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, int64_t ld, bool trans, void *out,
+                              hipStream_t s)
 {
     const int64_t nrb = cdiv(rows, 32), nkb = cdiv(k, 32);
+    if (nrb * nkb == 0) return hipSuccess;
     const unsigned grid = pack_grid(nrb * nkb);
     tmark("pack_bf16x3", s, true);
     if (trans)
-        hipLaunchKernelGGL(pack_bf16x3<true>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out), nrb,
-                           nkb);
+        hipLaunchKernelGGL(pack_bf16x3<true>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out),
+                           nrb, nkb);
     else
-        hipLaunchKernelGGL(pack_bf16x3<false>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out),
+        hipLaunchKernelGGL(pack_bf16x3<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out),
                            nrb, nkb);
     tmark("pack_bf16x3", s, false);
     return hipGetLastError();
 }
 
-hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans, int planes, void *out,
+hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld, bool trans, int planes, void *out,
                           uint32_t *maxabs, hipStream_t s, const uint32_t *decide, int expect)
 {
     const int64_t nrb = cdiv(rows, 32), nkb = cdiv(k, 64);
+    if (nrb * nkb == 0) return hipSuccess;
     const unsigned grid = pack_grid(nrb * nkb);
     tmark("pack_i8", s, true);
     if (trans)
-        hipLaunchKernelGGL(pack_i8<true>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out), nrb, nkb,
-                           planes, maxabs, decide, expect);
+        hipLaunchKernelGGL(pack_i8<true>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out), nrb,
+                           nkb, planes, maxabs, decide, expect);
     else
-        hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, static_cast<char *>(out), nrb,
+        hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out), nrb,
                            nkb, planes, maxabs, decide, expect);
     tmark("pack_i8", s, false);
     return hipGetLastError();
 }
 
-void tile_dims(int tile, int64_t len, int &bm, int &bn)
+void tile_dims(int tile, int64_t m, int64_t n, int &bm, int &bn)
 {
-    const int t = tile ? tile : default_tile(len);
+    const int t = tile ? tile : default_tile(m, n);
     bm = (t == GEMM_TILE_256 || t == GEMM_TILE_256W4 || t == GEMM_TILE_256x128) ? 256 : t == GEMM_TILE_128 ? 128 : 64;
     bn = (t == GEMM_TILE_256 || t == GEMM_TILE_256W4) ? 256 : t == GEMM_TILE_256x128 ? 128 : bm;
 }
 
-hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, int64_t len, int tile, double tau,
+hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, const GemmShape &sh, int tile, double tau,
                             ProbeRecord *rec, hipStream_t s)
 {
     int bm, bn;
-    tile_dims(tile, len, bm, bn);
-    const int tiles_m = (int)cdiv(len, bm), tiles_n = (int)cdiv(len, bn);
+    tile_dims(tile, sh.m, sh.n, bm, bn);
+    const int tiles_m = (int)cdiv(sh.m, bm), tiles_n = (int)cdiv(sh.n, bn);
+    if (tiles_m * tiles_n == 0) return hipSuccess;
     tmark("probe_f64", s, true);
     hipLaunchKernelGGL(probe_f64, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s, static_cast<const char *>(pa),
-                       static_cast<const char *>(pb), c, len, bm, bn, tiles_n, cdiv(len * 2, 64), tau * tau, rec);
+                       static_cast<const char *>(pb), c, sh, bm, bn, tiles_n, cdiv(sh.k * 2, 64), tau * tau, rec);
     tmark("probe_f64", s, false);
     return hipGetLastError();
 }
 
-int probe_tiles(int tile, int64_t len)
+int probe_tiles(int tile, int64_t m, int64_t n)
 {
     int bm, bn;
-    tile_dims(tile, len, bm, bn);
-    return (int)(cdiv(len, bm) * cdiv(len, bn));
+    tile_dims(tile, m, n, bm, bn);
+    return (int)(cdiv(m, bm) * cdiv(n, bn));
 }
 
-hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t len, int products, bool accumulate,
-                              int tile, hipStream_t s, const ProbeRecord *probe)
+hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const GemmShape &sh, int products,
+                              bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe)
 {
+    if (sh.m <= 0 || sh.n <= 0) return hipSuccess;
     GemmArgs g{};
     g.A = static_cast<const char *>(pa);
     g.B = static_cast<const char *>(pb);
     g.C = c;
-    g.M = g.N = g.ldc = len;
-    g.nkb = cdiv(len * 2, 64);
-    g.nrb_a = g.nrb_b = cdiv(len, 32);
+    g.M = sh.m;
+    g.N = sh.n;
+    g.ldc = sh.ldc;
+    g.nkb = cdiv(sh.k * 2, 64);
+    g.nrb_a = cdiv(sh.m, 32);
+    g.nrb_b = cdiv(sh.n, 32);
     g.accumulate = accumulate ? 1 : 0;
     g.probe = probe;
-    const int t = tile ? tile : default_tile(len);
+    const int t = tile ? tile : default_tile(sh.m, sh.n);
     hipError_t e;
     tmark("gemm_bf16x3", s, true);
     if (products == 6)
@@ -433,19 +445,23 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t 
     return e;
 }
 
-hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s,
-                          const uint32_t *decide)
+hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,
+                          hipStream_t s, const uint32_t *decide)
 {
+    if (sh.m <= 0 || sh.n <= 0) return hipSuccess;
     GemmArgs g{};
     g.A = static_cast<const char *>(pa);
     g.B = static_cast<const char *>(pb);
     g.C = c;
-    g.M = g.N = g.ldc = len;
-    g.nkb = cdiv(len, 64);
-    g.nrb_a = g.nrb_b = cdiv(len, 32);
+    g.M = sh.m;
+    g.N = sh.n;
+    g.ldc = sh.ldc;
+    g.nkb = cdiv(sh.k, 64);
+    g.nrb_a = cdiv(sh.m, 32);
+    g.nrb_b = cdiv(sh.n, 32);
     g.decide = decide;
     g.expect = limbs;
-    const int t = tile ? tile : default_tile(len);
+    const int t = tile ? tile : default_tile(sh.m, sh.n);
     hipError_t e;
     tmark("gemm_i8", s, true);
     switch (limbs) {

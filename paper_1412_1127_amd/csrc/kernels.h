@@ -8,10 +8,18 @@
 
 namespace accx {
 
+// Shape of one loop nest C (m x n) = A (m x k) B (k x n), row-major, with
+// leading dimensions (elements between rows): Listing 1a is
+// m = n = k = lda = ldb = ldc = LEN.
+struct GemmShape {
+    int64_t m, n, k, lda, ldb, ldc;
+};
+inline GemmShape square_shape(int64_t len) { return GemmShape{len, len, len, len, len, len}; }
+
 // ---- plain loop nest (Listing 1a/1b): one thread per output element -------
-hipError_t launch_matmul_plain_f32(const float *a, const float *b, float *c, int64_t len,
+hipError_t launch_matmul_plain_f32(const float *a, const float *b, float *c, const GemmShape &sh,
                                    bool listing1b_mapping, hipStream_t s);
-hipError_t launch_matmul_plain_i32(const int32_t *a, const int32_t *b, int32_t *c, int64_t len,
+hipError_t launch_matmul_plain_i32(const int32_t *a, const int32_t *b, int32_t *c, const GemmShape &sh,
                                    bool listing1b_mapping, hipStream_t s);
 
 // ---- reduction(+) ----------------------------------------------------------
@@ -27,20 +35,38 @@ hipError_t launch_reduce_f32(const float *x, int64_t n, float init, float *resul
 hipError_t launch_reduce_i32(const int32_t *x, int64_t n, int32_t init, int32_t *result, void *work,
                              bool plain, hipStream_t s);
 
+// Reduction variables over one array (any operator, element type).
+enum { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2, RED_OR = 3, RED_MAX_VARS = 4 };
+struct RedVars {
+    int32_t nvars;                 // 1..4 (logical or: 1)
+    int32_t op[RED_MAX_VARS];      // RED_*
+    int32_t square[RED_MAX_VARS];  // 1: the variable folds x*x
+    uint64_t init[RED_MAX_VARS];   // initial values as element bit patterns
+};
+// Workspace: [0,256) ticket word (zero before the first call, left at zero),
+// then RED_MAX_VARS x 4096 partial words of 8 bytes.
+size_t reduce_vars_workspace_bytes();
+// dtype: 0 float32, 1 int32, 2 float64, 3 int64; result: nvars elements.
+hipError_t launch_reduce_vars(int dtype, const void *x, int64_t n, const RedVars &vars, void *result, void *work,
+                              hipStream_t s);
+
 // ---- tiled matrix-core path (gemm_mfma.hip) --------------------------------
 // Bytes of a packed operand: `rows` rows of `k_elems` elements of
 // `elem_bytes` bytes, `planes` planes (units of 32 rows x 64 bytes per plane).
 size_t packed_bytes(int64_t rows, int64_t k_elems, int elem_bytes, int planes);
-// float32 -> hi/mid/lo bf16 planes.  trans = false: x is rows x k row-major;
-// trans = true: x is k x rows row-major (packs the columns, i.e. B^T).
-hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, bool trans, void *out, hipStream_t s);
+// float32 -> hi/mid/lo bf16 planes.  trans = false: x is rows x k row-major
+// (element (r, e) at x[r*ld + e]); trans = true: x is k x rows row-major
+// (element (e, r) at x[e*ld + r]; packs the columns, i.e. B^T).
+hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, int64_t ld, bool trans, void *out,
+                              hipStream_t s);
 // int32 -> `planes` balanced base-256 digit planes; maxabs (nullable) gets
 // atomicMax of |x| (must hold 0 or a smaller value beforehand).
 // decide (optional): packs only if the digit count decided on the device
 // from the two max|x| words is 1 (expect = 1) or more (expect = 4).
-hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, bool trans, int planes, void *out,
+hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld, bool trans, int planes, void *out,
                           uint32_t *maxabs, hipStream_t s, const uint32_t *decide = nullptr, int expect = 0);
-// C (len x len) = sum over the product set of A-plane x B-plane.
+// C (m x n, leading dimension ldc) = sum over the product set of A-plane x
+// B-plane, A and B packed with k elements per row.
 // products: 6 = FULL6, 3 = CHEAP3, -3 = the three products FULL6 adds to
 // CHEAP3.  accumulate: C += instead of C =.
 // tile: one of GEMM_TILE_* (0 = size heuristic).
@@ -57,17 +83,20 @@ struct ProbeRecord {
 static_assert(sizeof(ProbeRecord) == 192, "probe record layout");
 
 // probe: non-null = skip the tiles whose record has corrected == 0.
-hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, int64_t len, int products, bool accumulate,
-                              int tile, hipStream_t s, const ProbeRecord *probe = nullptr);
-// Float64 probe of C (len x len) per output tile of `tile`; tau: relative
-// Frobenius threshold above which a tile is marked for correction.
-hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, int64_t len, int tile, double tau,
+hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const GemmShape &sh, int products,
+                              bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe = nullptr);
+// Float64 probe of C per output tile of `tile`; tau: relative Frobenius
+// threshold above which a tile is marked for correction.
+hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, const GemmShape &sh, int tile, double tau,
                             ProbeRecord *rec, hipStream_t s);
-int probe_tiles(int tile, int64_t len);
+// Output tiles of `tile` (0 = the heuristic's choice) over an m x n result.
+int probe_tiles(int tile, int64_t m, int64_t n);
+// The configuration the size heuristic picks for an m x n result.
+int default_tile(int64_t m, int64_t n);
 // decide (optional): runs only if the device-side digit count is 1 (limbs =
 // 1) or more than 1 (limbs = 4).
-hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, int64_t len, int limbs, int tile, hipStream_t s,
-                          const uint32_t *decide = nullptr);
+hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,
+                          hipStream_t s, const uint32_t *decide = nullptr);
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
 // n pseudo-random 32-bit words for timing runs: float32 in [-1, 1) or int32 in [-16, 16].
 hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s);
@@ -76,7 +105,7 @@ hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s);
 struct BatchPackJob {   // one bf16x3 operand to pack
     const float *x;
     char *out;
-    int64_t rows, k, nrb, nkb;
+    int64_t rows, k, ld, nrb, nkb;
     int32_t trans, pad;
 };
 struct BatchMat {       // one matmul: packed operands, output, tiling

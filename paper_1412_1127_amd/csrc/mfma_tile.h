@@ -49,14 +49,16 @@ __device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l)
 }
 
 // One thread per (unit, row, chunk): 8 consecutive K elements of one row.
-// TRANS = false: X is R x K row-major (operand row r = X row r).
-// TRANS = true:  X is K x R row-major (operand row r = X column r).
+// TRANS = false: X is R x K row-major (operand row r = X row r), element
+//                (r, e) at X[r*ld + e].
+// TRANS = true:  X is K x R row-major (operand row r = X column r), element
+//                (e, r) at X[e*ld + r].
 // Work items id0, id0 + step, ... of one operand (128 items per unit).
 template <bool TRANS>
 __device__ __attribute__((always_inline)) inline void pack_bf16x3_range(const float *__restrict__ X, int64_t R,
-                                                                        int64_t K, char *__restrict__ out,
-                                                                        int64_t nrb, int64_t nkb, int64_t id0,
-                                                                        int64_t step)
+                                                                        int64_t K, int64_t ld,
+                                                                        char *__restrict__ out, int64_t nrb,
+                                                                        int64_t nkb, int64_t id0, int64_t step)
 {
     const int64_t total = nrb * nkb * 128;
     for (int64_t id = id0; id < total; id += step) {
@@ -76,14 +78,14 @@ __device__ __attribute__((always_inline)) inline void pack_bf16x3_range(const fl
         float v[8];
         if (TRANS) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[(k0 + t) * R + row] : 0.0f;
-        } else if (row < R && k0 + 8 <= K && ((K & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
-            const f32x4 *p = reinterpret_cast<const f32x4 *>(X + row * K + k0);
+            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[(k0 + t) * ld + row] : 0.0f;
+        } else if (row < R && k0 + 8 <= K && ((ld & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
+            const f32x4 *p = reinterpret_cast<const f32x4 *>(X + row * ld + k0);
             const f32x4 a = p[0], b = p[1];
             v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
         } else {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[row * K + k0 + t] : 0.0f;
+            for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[row * ld + k0 + t] : 0.0f;
         }
         u16x8 h, m, l;
 #pragma unroll

@@ -20,7 +20,9 @@
 // change the order in which anything is added.
 //
 // float: float32 arithmetic throughout.  int32: unsigned 32-bit adds
-// (wraparound modulo 2^32).
+// (wraparound modulo 2^32).  The other operators and element types (max,
+// min, logical or; float64, int64; several variables per pass) follow the
+// sum kernels below.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -160,6 +162,230 @@ __global__ __launch_bounds__(RT) void reduce_plain_final(const L *__restrict__ p
     if (threadIdx.x == 0) result[0] = init + s[0];
 }
 
+// ---- reduction variables of any operator and type --------------------------
+//
+// Up to four reduction variables over one array in one pass (the SRAD loop
+// keeps a sum and a sum of squares of the same image): variable v combines
+// f_v(x[k]) with operator op_v, where f_v(x) = x or x*x in the element type.
+// Operators: + (integers wrap around), max, min (floats: a NaN operand is
+// ignored, as fmax/fmin do).  Each thread folds its grid-stride slice into
+// one accumulator per variable in a fixed order, the workgroup combines its
+// threads in a fixed tree, and the last workgroup to finish (atomic ticket)
+// folds the per-workgroup partials in index order and then the initial value:
+// result_v = init_v (op_v) (partial_0 (op_v) partial_1 ...).
+
+template <typename E> struct Red;
+template <> struct Red<float> {
+    using V = f4;
+    using Bits = uint32_t;
+    static constexpr int W = 4;
+    __device__ static float lowest() { return -__builtin_inff(); }
+    __device__ static float highest() { return __builtin_inff(); }
+    __device__ static float add(float a, float b) { return a + b; }
+    __device__ static float mul(float a, float b) { return a * b; }
+    __device__ static float max(float a, float b) { return __builtin_fmaxf(a, b); }
+    __device__ static float min(float a, float b) { return __builtin_fminf(a, b); }
+    __device__ static bool nonzero(float a) { return a != 0.0f; }
+};
+typedef double d2 __attribute__((ext_vector_type(2)));
+template <> struct Red<double> {
+    using V = d2;
+    using Bits = uint64_t;
+    static constexpr int W = 2;
+    __device__ static double lowest() { return -__builtin_inf(); }
+    __device__ static double highest() { return __builtin_inf(); }
+    __device__ static double add(double a, double b) { return a + b; }
+    __device__ static double mul(double a, double b) { return a * b; }
+    __device__ static double max(double a, double b) { return __builtin_fmax(a, b); }
+    __device__ static double min(double a, double b) { return __builtin_fmin(a, b); }
+    __device__ static bool nonzero(double a) { return a != 0.0; }
+};
+typedef int32_t i4 __attribute__((ext_vector_type(4)));
+template <> struct Red<int32_t> {
+    using V = i4;
+    using Bits = uint32_t;
+    static constexpr int W = 4;
+    __device__ static int32_t lowest() { return INT32_MIN; }
+    __device__ static int32_t highest() { return INT32_MAX; }
+    __device__ static int32_t add(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
+    __device__ static int32_t mul(int32_t a, int32_t b) { return (int32_t)((uint32_t)a * (uint32_t)b); }
+    __device__ static int32_t max(int32_t a, int32_t b) { return a > b ? a : b; }
+    __device__ static int32_t min(int32_t a, int32_t b) { return a < b ? a : b; }
+    __device__ static bool nonzero(int32_t a) { return a != 0; }
+};
+typedef int64_t l2 __attribute__((ext_vector_type(2)));
+template <> struct Red<int64_t> {
+    using V = l2;
+    using Bits = uint64_t;
+    static constexpr int W = 2;
+    __device__ static int64_t lowest() { return INT64_MIN; }
+    __device__ static int64_t highest() { return INT64_MAX; }
+    __device__ static int64_t add(int64_t a, int64_t b) { return (int64_t)((uint64_t)a + (uint64_t)b); }
+    __device__ static int64_t mul(int64_t a, int64_t b) { return (int64_t)((uint64_t)a * (uint64_t)b); }
+    __device__ static int64_t max(int64_t a, int64_t b) { return a > b ? a : b; }
+    __device__ static int64_t min(int64_t a, int64_t b) { return a < b ? a : b; }
+    __device__ static bool nonzero(int64_t a) { return a != 0; }
+};
+
+template <typename E> __device__ inline E red_identity(int op)
+{
+    return op == RED_SUM ? (E)0 : op == RED_MAX ? Red<E>::lowest() : Red<E>::highest();
+}
+
+template <typename E> __device__ inline E red_apply(int op, E a, E b)
+{
+    return op == RED_SUM ? Red<E>::add(a, b) : op == RED_MAX ? Red<E>::max(a, b) : Red<E>::min(a, b);
+}
+
+template <typename E> __device__ inline E bits_as(uint64_t b)
+{
+    typename Red<E>::Bits t = (typename Red<E>::Bits)b;
+    return __builtin_bit_cast(E, t);
+}
+template <typename E> __device__ inline uint64_t as_bits(E v)
+{
+    return (uint64_t)__builtin_bit_cast(typename Red<E>::Bits, v);
+}
+
+// Combine v over the workgroup in a fixed order; valid in thread 0.
+template <typename E> __device__ inline E block_apply(int op, E v, E *lds4)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = red_apply<E>(op, v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    E r = v;
+    if (threadIdx.x == 0) r = red_apply<E>(op, red_apply<E>(op, lds4[0], lds4[1]), red_apply<E>(op, lds4[2], lds4[3]));
+    __syncthreads();
+    return r;
+}
+
+template <typename E, int NV>
+__global__ __launch_bounds__(RT) void reduce_vars(const E *__restrict__ x, int64_t n, RedVars vars,
+                                                  E *__restrict__ result, uint32_t *__restrict__ ticket,
+                                                  uint64_t *__restrict__ partials)
+{
+    using R = Red<E>;
+    using V = typename R::V;
+    constexpr int W = R::W;
+    __shared__ E lds4[4];
+    __shared__ int is_last;
+
+    int op[NV], sq[NV];
+    E acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        op[v] = vars.op[v];
+        sq[v] = vars.square[v];
+        acc[v] = red_identity<E>(op[v]);
+    }
+    auto fold = [&](E t) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = red_apply<E>(op[v], acc[v], sq[v] ? R::mul(t, t) : t);
+    };
+
+    // Aligned body of 16-byte vectors, up to W-1 leading and trailing scalars.
+    const uintptr_t addr = (uintptr_t)x;
+    int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) / sizeof(E));
+    if (head > n) head = n;
+    const int64_t nvec = (n - head) / W;
+    const int64_t tail0 = head + nvec * W;
+    const V *__restrict__ xv = reinterpret_cast<const V *>(x + head);
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x;
+    for (; i + (RU - 1) * stride < nvec; i += RU * stride) {
+        V t[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) t[u] = __builtin_nontemporal_load(xv + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int e = 0; e < W; ++e) fold(t[u][e]);
+    }
+    for (; i < nvec; i += stride) {
+        const V t = __builtin_nontemporal_load(xv + i);
+#pragma unroll
+        for (int e = 0; e < W; ++e) fold(t[e]);
+    }
+    if (blockIdx.x == 0) {
+        if ((int64_t)threadIdx.x < head) fold(x[threadIdx.x]);
+        if ((int64_t)threadIdx.x < n - tail0) fold(x[tail0 + threadIdx.x]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const E b = block_apply<E>(op[v], acc[v], lds4);
+        if (threadIdx.x == 0)
+            __hip_atomic_store(partials + (size_t)v * gridDim.x + blockIdx.x, as_bits<E>(b), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        is_last = (atomicAdd(ticket, 1u) == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        E t = red_identity<E>(op[v]);
+        for (unsigned k = threadIdx.x; k < gridDim.x; k += RT)
+            t = red_apply<E>(op[v], t,
+                             bits_as<E>(__hip_atomic_load(partials + (size_t)v * gridDim.x + k, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT)));
+        t = block_apply<E>(op[v], t, lds4);
+        if (threadIdx.x == 0) result[v] = red_apply<E>(op[v], bits_as<E>(vars.init[v]), t);
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Logical or as a guarded write (the flag idiom hand-written code uses in
+// place of a reduction): result = (init != 0) is stored first; then every
+// thread that finds a nonzero element stores 1 (all writers store the same
+// value).  A wavefront stops scanning once it sees the flag set.
+template <typename E> __global__ void red_flag_init(E *result, uint64_t init_bits)
+{
+    if (threadIdx.x == 0) result[0] = Red<E>::nonzero(bits_as<E>(init_bits)) ? (E)1 : (E)0;
+}
+
+template <typename E>
+__global__ __launch_bounds__(RT) void reduce_or_flag(const E *__restrict__ x, int64_t n, E *result)
+{
+    using R = Red<E>;
+    using V = typename R::V;
+    constexpr int W = R::W;
+    using B = typename R::Bits;
+    B *flag = reinterpret_cast<B *>(result);
+    const B one = __builtin_bit_cast(B, (E)1);
+    const uintptr_t addr = (uintptr_t)x;
+    int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) / sizeof(E));
+    if (head > n) head = n;
+    const int64_t nvec = (n - head) / W;
+    const int64_t tail0 = head + nvec * W;
+    const V *__restrict__ xv = reinterpret_cast<const V *>(x + head);
+    const int64_t stride = (int64_t)gridDim.x * RT;
+    bool found = false;
+    if (blockIdx.x == 0) {
+        if ((int64_t)threadIdx.x < head) found |= R::nonzero(x[threadIdx.x]);
+        if ((int64_t)threadIdx.x < n - tail0) found |= R::nonzero(x[tail0 + threadIdx.x]);
+    }
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i - threadIdx.x < nvec; i += RU * stride) {
+        // wave-uniform early exit once any thread has stored the flag
+        const B seen = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane((int)(seen == one))) return;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t j = i + u * stride;
+            if (j < nvec) {
+                const V t = __builtin_nontemporal_load(xv + j);
+#pragma unroll
+                for (int e = 0; e < W; ++e) found |= R::nonzero(t[e]);
+            }
+        }
+        if (found) __hip_atomic_store(flag, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (found) __hip_atomic_store(flag, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 int64_t fast_blocks(int64_t n)
 {
     const int64_t nvec = n / 4;
@@ -199,7 +425,51 @@ hipError_t launch_reduce(const L *x, int64_t n, L init, L *result, void *work, b
     return hipGetLastError();
 }
 
+template <typename E>
+hipError_t launch_vars(const E *x, int64_t n, const RedVars &vars, E *result, void *work, hipStream_t s)
+{
+    if (vars.op[0] == RED_OR) {
+        hipLaunchKernelGGL(red_flag_init<E>, dim3(1), dim3(64), 0, s, result, vars.init[0]);
+        if (n > 0) {
+            const int64_t g = fast_blocks(n * (int64_t)sizeof(E) / 4);
+            tmark("reduce_or_flag", s, true);
+            hipLaunchKernelGGL(reduce_or_flag<E>, dim3((unsigned)g), dim3(RT), 0, s, x, n, result);
+            tmark("reduce_or_flag", s, false);
+        }
+        return hipGetLastError();
+    }
+    const int64_t g = fast_blocks(n * (int64_t)sizeof(E) / 4);
+    uint32_t *ticket = static_cast<uint32_t *>(work);
+    uint64_t *partials = reinterpret_cast<uint64_t *>(static_cast<char *>(work) + TICKET_BYTES);
+    tmark("reduce_vars", s, true);
+    switch (vars.nvars) {
+    case 1: hipLaunchKernelGGL((reduce_vars<E, 1>), dim3((unsigned)g), dim3(RT), 0, s, x, n, vars, result, ticket, partials); break;
+    case 2: hipLaunchKernelGGL((reduce_vars<E, 2>), dim3((unsigned)g), dim3(RT), 0, s, x, n, vars, result, ticket, partials); break;
+    case 3: hipLaunchKernelGGL((reduce_vars<E, 3>), dim3((unsigned)g), dim3(RT), 0, s, x, n, vars, result, ticket, partials); break;
+    case 4: hipLaunchKernelGGL((reduce_vars<E, 4>), dim3((unsigned)g), dim3(RT), 0, s, x, n, vars, result, ticket, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    tmark("reduce_vars", s, false);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+size_t reduce_vars_workspace_bytes() { return TICKET_BYTES + sizeof(uint64_t) * RED_MAX_VARS * MAX_BLOCKS; }
+
+hipError_t launch_reduce_vars(int dtype, const void *x, int64_t n, const RedVars &vars, void *result, void *work,
+                              hipStream_t s)
+{
+    switch (dtype) {
+    case 0: return launch_vars<float>(static_cast<const float *>(x), n, vars, static_cast<float *>(result), work, s);
+    case 1:
+        return launch_vars<int32_t>(static_cast<const int32_t *>(x), n, vars, static_cast<int32_t *>(result), work, s);
+    case 2: return launch_vars<double>(static_cast<const double *>(x), n, vars, static_cast<double *>(result), work, s);
+    case 3:
+        return launch_vars<int64_t>(static_cast<const int64_t *>(x), n, vars, static_cast<int64_t *>(result), work, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 size_t reduce_fast_workspace_bytes(int64_t) { return TICKET_BYTES + sizeof(uint32_t) * MAX_BLOCKS; }
 

@@ -54,13 +54,14 @@ struct Fault {
 struct Entry {
     uintptr_t hbeg = 0, hend = 0;  // host byte range [hbeg, hend)
     void *dev = nullptr;
-    int kind = 0, dtype = 0;
-    acc_region_s *owner = nullptr;
+    int kind = 0, dtype = 0;       // kind: the creating clause's data movement (ACC_COPY..ACC_CREATE)
+    int refs = 0;                  // region references (creating clause + present clauses)
 };
 
 struct Pending {  // an asynchronous reduction result waiting for acc_wait
     void *host_dst;
-    int slot;
+    int slot;       // first result slot
+    size_t bytes;   // bytes to copy from the slots
 };
 
 struct Workspace {
@@ -73,14 +74,15 @@ struct Workspace {
 struct acc_region_s {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    std::vector<uintptr_t> keys;  // present-table keys owned by this region
+    std::vector<uintptr_t> keys;  // present-table keys this region holds a reference to (one per clause)
     acc_status err = ACC_OK;
     std::string err_msg;
     Workspace mm_work;            // matmul workspace
     Workspace red_work;           // reduction workspace (zero-filled ticket)
     Workspace red_plain_work;     // plain reduction partials
-    void *dres = nullptr;         // device result slots (4 bytes each)
-    uint32_t *hres = nullptr;     // pinned host staging for the slots
+    Workspace red_vars_work;      // reduction variables (zero-filled ticket)
+    void *dres = nullptr;         // device result slots (8 bytes each)
+    uint64_t *hres = nullptr;     // pinned host staging for the slots
     int nslots = 0, used_slots = 0;
     std::vector<Pending> pending;
 };
@@ -100,7 +102,7 @@ struct State {
     uint64_t used = 0;
     std::map<uintptr_t, Entry> present;  // key = hbeg
     std::set<acc_region_s *> regions;
-    std::map<hipStream_t, Workspace> mm_ws, red_ws, red_plain_ws;  // device-pointer entries
+    std::map<hipStream_t, Workspace> mm_ws, red_ws, red_plain_ws, red_vars_ws;  // device-pointer entries
     Fault fault;
 };
 
@@ -131,9 +133,11 @@ void parse_fault(Fault &f)
     if (kind == "launch") f.launch_at = n;
 }
 
-size_t elem_bytes(int) { return 4; }
+size_t elem_bytes(int t) { return (t == ACC_FLOAT64 || t == ACC_INT64) ? 8 : 4; }
 
-bool valid_dtype(int t) { return t == ACC_FLOAT32 || t == ACC_INT32; }
+// Element types of data clauses and reductions; the matmul takes the 4-byte ones.
+bool valid_dtype(int t) { return t == ACC_FLOAT32 || t == ACC_INT32 || t == ACC_FLOAT64 || t == ACC_INT64; }
+bool matmul_dtype(int t) { return t == ACC_FLOAT32 || t == ACC_INT32; }
 
 // Device allocation charged against the budget.
 acc_status dev_alloc(void **p, size_t bytes)
@@ -266,10 +270,10 @@ acc_status check_launch(hipError_t e, const char *what)
 
 // ---- matmul dispatch ------------------------------------------------------
 
-acc_status validate_matmul(int t, int64_t len, uint32_t flags)
+using accx::GemmShape;
+
+acc_status validate_flags(uint32_t flags)
 {
-    if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
-    if (len < 1 || len > 65536) return fail(ACC_ERR_INVALID_ARG, "len must be in [1, 65536]");
     const uint32_t known = ACC_KERNEL_MASK | ACC_PREC_MASK | ACC_LIMBS_MASK | ACC_ASYNC | ACC_TILE_MASK;
     if (flags & ~known) return fail(ACC_ERR_INVALID_ARG, "unknown flag bits");
     const uint32_t k = flags & ACC_KERNEL_MASK;
@@ -284,6 +288,34 @@ acc_status validate_matmul(int t, int64_t len, uint32_t flags)
     return ACC_OK;
 }
 
+acc_status validate_matmul(int t, int64_t len, uint32_t flags)
+{
+    if (!matmul_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
+    if (len < 1 || len > 65536) return fail(ACC_ERR_INVALID_ARG, "len must be in [1, 65536]");
+    return validate_flags(flags);
+}
+
+constexpr int64_t kMaxMN = 131072;  // rows of A, columns of B
+constexpr int64_t kMaxK = 65536;    // int8 digit products summed over k stay below 2^31
+constexpr int64_t kMaxLd = (int64_t)1 << 31;
+
+acc_status validate_gemm(int t, const GemmShape &sh, uint32_t flags)
+{
+    if (!matmul_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
+    if (sh.m < 0 || sh.n < 0 || sh.m > kMaxMN || sh.n > kMaxMN)
+        return fail(ACC_ERR_INVALID_ARG, "m and n must be in [0, 131072]");
+    if (sh.k < 0 || sh.k > kMaxK) return fail(ACC_ERR_INVALID_ARG, "k must be in [0, 65536]");
+    if (sh.lda < std::max<int64_t>(1, sh.k) || sh.ldb < std::max<int64_t>(1, sh.n) ||
+        sh.ldc < std::max<int64_t>(1, sh.n))
+        return fail(ACC_ERR_INVALID_ARG, "leading dimensions must satisfy lda >= k, ldb >= n, ldc >= n (and >= 1)");
+    if (sh.lda > kMaxLd || sh.ldb > kMaxLd || sh.ldc > kMaxLd)
+        return fail(ACC_ERR_INVALID_ARG, "leading dimensions must be at most 2^31");
+    return validate_flags(flags);
+}
+
+// Elements spanned by a rows x cols row-major view with leading dimension ld.
+int64_t span_elems(int64_t rows, int64_t cols, int64_t ld) { return rows && cols ? (rows - 1) * ld + cols : 0; }
+
 bool is_plain(uint32_t flags)
 {
     const uint32_t k = flags & ACC_KERNEL_MASK;
@@ -293,15 +325,6 @@ bool is_plain(uint32_t flags)
 constexpr size_t kMaxabsBytes = 256;  // int path: two max|x| words, padded
 
 int flag_limbs(uint32_t flags) { return (int)((flags & ACC_LIMBS_MASK) >> ACC_LIMBS_SHIFT); }
-
-// Fewest balanced base-256 digits that represent every |x| <= m exactly.
-int limbs_for(uint32_t m)
-{
-    if (m <= 127u) return 1;
-    if (m <= 32639u) return 2;
-    if (m <= 8355711u) return 3;
-    return 4;
-}
 
 // ACC_PREC_AUTO: relative Frobenius error a tile may show on the probe's
 // samples and still keep the cheap (three-product) result: half the 1e-5
@@ -318,22 +341,28 @@ double probe_tau()
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Probe records live after the two packed operands; sized for the smallest
-// tile so that any tile choice fits.
-size_t probe_offset(int64_t len) { return align256(2 * accx::packed_bytes(len, len, 2, 3)); }
-size_t probe_bytes_max(int64_t len)
+// Packed A (m rows of k) and packed B^T (n rows of k).
+size_t packed_pair(const GemmShape &sh, int elem_bytes, int planes)
 {
-    return (size_t)accx::probe_tiles(accx::GEMM_TILE_64, len) * sizeof(accx::ProbeRecord);
+    return accx::packed_bytes(sh.m, sh.k, elem_bytes, planes) + accx::packed_bytes(sh.n, sh.k, elem_bytes, planes);
 }
 
-size_t matmul_ws_bytes(int t, int64_t len, uint32_t flags)
+// Probe records live after the two packed operands; sized for the smallest
+// tile so that any tile choice fits.
+size_t probe_offset(const GemmShape &sh) { return align256(packed_pair(sh, 2, 3)); }
+size_t probe_bytes_max(const GemmShape &sh)
 {
-    if (is_plain(flags)) return 0;
-    if (t == ACC_FLOAT32 && (flags & ACC_PREC_MASK) == ACC_PREC_AUTO) return probe_offset(len) + probe_bytes_max(len);
-    if (t == ACC_FLOAT32) return 2 * accx::packed_bytes(len, len, 2, 3);
-    if (flag_limbs(flags)) return kMaxabsBytes + 2 * accx::packed_bytes(len, len, 1, flag_limbs(flags));
+    return (size_t)accx::probe_tiles(accx::GEMM_TILE_64, sh.m, sh.n) * sizeof(accx::ProbeRecord);
+}
+
+size_t matmul_ws_bytes(int t, const GemmShape &sh, uint32_t flags)
+{
+    if (is_plain(flags) || sh.m == 0 || sh.n == 0) return 0;
+    if (t == ACC_FLOAT32 && (flags & ACC_PREC_MASK) == ACC_PREC_AUTO) return probe_offset(sh) + probe_bytes_max(sh);
+    if (t == ACC_FLOAT32) return packed_pair(sh, 2, 3);
+    if (flag_limbs(flags)) return kMaxabsBytes + packed_pair(sh, 1, flag_limbs(flags));
     // probe: one-digit and four-digit operands side by side
-    return kMaxabsBytes + 2 * accx::packed_bytes(len, len, 1, 1) + 2 * accx::packed_bytes(len, len, 1, 4);
+    return kMaxabsBytes + packed_pair(sh, 1, 1) + packed_pair(sh, 1, 4);
 }
 
 // ---- autotuned tile table -----------------------------------------------
@@ -357,48 +386,56 @@ struct TuneEntry {
     double ms;
 };
 
-std::map<std::tuple<int, int, int>, TuneEntry> &tune_table()
+// Key: dtype, variant (+100 per kernel family), and the size classes of m,
+// n and k (each rounded up to a power of two).
+using TuneKey = std::tuple<int, int, int, int, int>;
+
+TuneKey tune_key(int t, int variant, const GemmShape &sh)
 {
-    static auto *t = new std::map<std::tuple<int, int, int>, TuneEntry>();
+    return TuneKey{t, variant, size_class(sh.m), size_class(sh.n), size_class(sh.k)};
+}
+
+std::map<TuneKey, TuneEntry> &tune_table()
+{
+    static auto *t = new std::map<TuneKey, TuneEntry>();
     return *t;
 }
 
-int resolve_tile(int t, int64_t len, uint32_t flags, int limbs)
+int resolve_tile(int t, const GemmShape &sh, uint32_t flags, int limbs)
 {
     const int forced = (int)((flags & ACC_TILE_MASK) >> ACC_TILE_SHIFT);
     if (forced) return forced;
     auto &tab = tune_table();
-    auto it = tab.find(std::make_tuple(t, tune_variant(t, flags, limbs), size_class(len)));
+    auto it = tab.find(tune_key(t, tune_variant(t, flags, limbs), sh));
     return it == tab.end() ? 0 : it->second.tile;
 }
 
-acc_status run_tiled_f32(const float *a, const float *b, float *c, int64_t len, uint32_t flags, char *work,
+acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmShape &sh, uint32_t flags, char *work,
                          hipStream_t s)
 {
-    const size_t pb = accx::packed_bytes(len, len, 2, 3);
+    const size_t pb = accx::packed_bytes(sh.m, sh.k, 2, 3);
     char *pa = work, *pbt = work + pb;
-    hipError_t e = accx::launch_pack_bf16x3(a, len, len, false, pa, s);
-    if (e == hipSuccess) e = accx::launch_pack_bf16x3(b, len, len, true, pbt, s);
+    hipError_t e = accx::launch_pack_bf16x3(a, sh.m, sh.k, sh.lda, false, pa, s);
+    if (e == hipSuccess) e = accx::launch_pack_bf16x3(b, sh.n, sh.k, sh.ldb, true, pbt, s);
     if (e != hipSuccess) return fail_hip(e, "pack (bf16x3) launch");
     const uint32_t prec = flags & ACC_PREC_MASK;
     if (prec == ACC_PREC_AUTO) {
         // cheap pass, float64 probe per tile, then the three missing products
         // on the tiles the probe marked (the others exit at once)
-        const int tile = resolve_tile(ACC_FLOAT32, len, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
-        auto *rec = reinterpret_cast<accx::ProbeRecord *>(work + probe_offset(len));
-        e = accx::launch_gemm_bf16x3(pa, pbt, c, len, 3, false, tile, s);
-        if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, len, tile, probe_tau(), rec, s);
-        if (e == hipSuccess) e = accx::launch_gemm_bf16x3(pa, pbt, c, len, -3, true, tile, s, rec);
+        const int tile = resolve_tile(ACC_FLOAT32, sh, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
+        auto *rec = reinterpret_cast<accx::ProbeRecord *>(work + probe_offset(sh));
+        e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, 3, false, tile, s);
+        if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, sh, tile, probe_tau(), rec, s);
+        if (e == hipSuccess) e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, -3, true, tile, s, rec);
         return check_launch(e, "gemm (bf16x3, probed) launch");
     }
     const int products = (prec == ACC_PREC_CHEAP3) ? 3 : 6;
-    e = accx::launch_gemm_bf16x3(pa, pbt, c, len, products, false,
-                                 resolve_tile(ACC_FLOAT32, len, flags, 0), s);
+    e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, products, false, resolve_tile(ACC_FLOAT32, sh, flags, 0), s);
     return check_launch(e, "gemm (bf16x3) launch");
 }
 
-acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, int64_t len, uint32_t flags, char *work,
-                         hipStream_t s)
+acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const GemmShape &sh, uint32_t flags,
+                         char *work, hipStream_t s)
 {
     uint32_t *maxabs = reinterpret_cast<uint32_t *>(work);
     char *pa = work + kMaxabsBytes;
@@ -411,65 +448,98 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, int64_t
         // GEMM only if they do not (each kernel reads the decision and exits
         // at once otherwise).  Two or three digits are served by the
         // four-digit kernels: the extra digits are zero.
-        const size_t pb1 = accx::packed_bytes(len, len, 1, 1);
-        const size_t pb4 = accx::packed_bytes(len, len, 1, 4);
-        char *p4 = pa + 2 * pb1;
+        const size_t pa1 = accx::packed_bytes(sh.m, sh.k, 1, 1), pa4 = accx::packed_bytes(sh.m, sh.k, 1, 4);
+        char *p4 = pa + packed_pair(sh, 1, 1);
         e = accx::launch_zero_u32(maxabs, 2, s);
-        if (e == hipSuccess) e = accx::launch_pack_i8(a, len, len, false, 1, pa, maxabs, s);
-        if (e == hipSuccess) e = accx::launch_pack_i8(b, len, len, true, 1, pa + pb1, maxabs + 1, s);
-        if (e == hipSuccess) e = accx::launch_pack_i8(a, len, len, false, 4, p4, nullptr, s, maxabs, 4);
-        if (e == hipSuccess) e = accx::launch_pack_i8(b, len, len, true, 4, p4 + pb4, nullptr, s, maxabs, 4);
+        if (e == hipSuccess) e = accx::launch_pack_i8(a, sh.m, sh.k, sh.lda, false, 1, pa, maxabs, s);
+        if (e == hipSuccess) e = accx::launch_pack_i8(b, sh.n, sh.k, sh.ldb, true, 1, pa + pa1, maxabs + 1, s);
+        if (e == hipSuccess) e = accx::launch_pack_i8(a, sh.m, sh.k, sh.lda, false, 4, p4, nullptr, s, maxabs, 4);
+        if (e == hipSuccess)
+            e = accx::launch_pack_i8(b, sh.n, sh.k, sh.ldb, true, 4, p4 + pa4, nullptr, s, maxabs, 4);
         if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
-        e = accx::launch_gemm_i8(pa, pa + pb1, c, len, 1, resolve_tile(ACC_INT32, len, flags, 1), s, maxabs);
-        if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pb4, c, len, 4, 0, s, maxabs);
+        e = accx::launch_gemm_i8(pa, pa + pa1, c, sh, 1, resolve_tile(ACC_INT32, sh, flags, 1), s, maxabs);
+        if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pa4, c, sh, 4, 0, s, maxabs);
         return check_launch(e, "gemm (int8) launch");
     }
-    const size_t pbn = accx::packed_bytes(len, len, 1, nl);
-    e = accx::launch_pack_i8(a, len, len, false, nl, pa, nullptr, s);
-    if (e == hipSuccess) e = accx::launch_pack_i8(b, len, len, true, nl, pa + pbn, nullptr, s);
+    const size_t pan = accx::packed_bytes(sh.m, sh.k, 1, nl);
+    e = accx::launch_pack_i8(a, sh.m, sh.k, sh.lda, false, nl, pa, nullptr, s);
+    if (e == hipSuccess) e = accx::launch_pack_i8(b, sh.n, sh.k, sh.ldb, true, nl, pa + pan, nullptr, s);
     if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
-    return check_launch(accx::launch_gemm_i8(pa, pa + pbn, c, len, nl, resolve_tile(ACC_INT32, len, flags, nl), s),
+    return check_launch(accx::launch_gemm_i8(pa, pa + pan, c, sh, nl, resolve_tile(ACC_INT32, sh, flags, nl), s),
                         "gemm (int8) launch");
 }
 
-acc_status run_matmul(int t, const void *a, const void *b, void *c, int64_t len, uint32_t flags, void *work,
+acc_status run_matmul(int t, const void *a, const void *b, void *c, const GemmShape &sh, uint32_t flags, void *work,
                       size_t work_bytes, hipStream_t s)
 {
     acc_status st = launch_fault();
     if (st != ACC_OK) return st;
+    if (sh.m == 0 || sh.n == 0) return ACC_OK;  // empty result
     const uint32_t k = flags & ACC_KERNEL_MASK;
     if (k == ACC_KERNEL_PLAIN || k == ACC_KERNEL_PLAIN_LISTING1B) {
         const bool l1b = (k == ACC_KERNEL_PLAIN_LISTING1B);
         hipError_t e = (t == ACC_FLOAT32)
                            ? accx::launch_matmul_plain_f32(static_cast<const float *>(a),
-                                                           static_cast<const float *>(b), static_cast<float *>(c),
-                                                           len, l1b, s)
+                                                           static_cast<const float *>(b), static_cast<float *>(c), sh,
+                                                           l1b, s)
                            : accx::launch_matmul_plain_i32(static_cast<const int32_t *>(a),
                                                            static_cast<const int32_t *>(b),
-                                                           static_cast<int32_t *>(c), len, l1b, s);
+                                                           static_cast<int32_t *>(c), sh, l1b, s);
         return check_launch(e, "matmul (plain) launch");
     }
-    if (work_bytes < matmul_ws_bytes(t, len, flags)) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
+    if (work_bytes < matmul_ws_bytes(t, sh, flags)) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
     if (t == ACC_FLOAT32)
-        return run_tiled_f32(static_cast<const float *>(a), static_cast<const float *>(b), static_cast<float *>(c),
-                             len, flags, static_cast<char *>(work), s);
+        return run_tiled_f32(static_cast<const float *>(a), static_cast<const float *>(b), static_cast<float *>(c), sh,
+                             flags, static_cast<char *>(work), s);
     return run_tiled_i32(static_cast<const int32_t *>(a), static_cast<const int32_t *>(b), static_cast<int32_t *>(c),
-                         len, flags, static_cast<char *>(work), s);
+                         sh, flags, static_cast<char *>(work), s);
 }
 
 // ---- reduction dispatch ---------------------------------------------------
 
 acc_status validate_reduce(int t, int64_t n, uint32_t flags)
 {
-    if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
+    if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "unknown dtype");
     if (n < 0) return fail(ACC_ERR_INVALID_ARG, "n must be >= 0");
     if (flags & ~(ACC_REDUCE_PLAIN | ACC_ASYNC)) return fail(ACC_ERR_INVALID_ARG, "unknown flag bits");
+    if ((flags & ACC_REDUCE_PLAIN) && !matmul_dtype(t))
+        return fail(ACC_ERR_INVALID_ARG, "ACC_REDUCE_PLAIN takes float32 and int32 sums only");
+    return ACC_OK;
+}
+
+// The one-variable float32/int32 sum runs on the dedicated sum kernels (fast
+// or plain); every other variable set on the general kernels.
+bool legacy_sum(int t, const acc_reduce_var *vars, int nvars)
+{
+    return matmul_dtype(t) && nvars == 1 && vars[0].op == ACC_RED_SUM && !vars[0].square;
+}
+
+acc_status validate_vars(int t, int64_t n, const acc_reduce_var *vars, int nvars, uint32_t flags)
+{
+    acc_status s = validate_reduce(t, n, flags & ~ACC_REDUCE_PLAIN);
+    if (s != ACC_OK) return s;
+    if (!vars || nvars < 1 || nvars > ACC_MAX_REDUCE_VARS)
+        return fail(ACC_ERR_INVALID_ARG, "1 to 4 reduction variables expected");
+    for (int v = 0; v < nvars; ++v) {
+        if (vars[v].op < ACC_RED_SUM || vars[v].op > ACC_RED_OR) return fail(ACC_ERR_INVALID_ARG, "unknown operator");
+        if (vars[v].square != 0 && vars[v].square != 1) return fail(ACC_ERR_INVALID_ARG, "square must be 0 or 1");
+        if (vars[v].op == ACC_RED_OR && (nvars != 1 || vars[v].square))
+            return fail(ACC_ERR_INVALID_ARG, "logical or is a variable of its own, over the elements themselves");
+    }
+    if ((flags & ACC_REDUCE_PLAIN) && !legacy_sum(t, vars, nvars))
+        return fail(ACC_ERR_INVALID_ARG, "ACC_REDUCE_PLAIN takes one float32 or int32 sum");
     return ACC_OK;
 }
 
 size_t reduce_ws_bytes(int64_t n, uint32_t flags)
 {
     return (flags & ACC_REDUCE_PLAIN) ? accx::reduce_plain_workspace_bytes(n) : accx::reduce_fast_workspace_bytes(n);
+}
+
+size_t vars_ws_bytes(int t, int64_t n, const acc_reduce_var *vars, int nvars, uint32_t flags)
+{
+    if (legacy_sum(t, vars, nvars)) return reduce_ws_bytes(n, flags);
+    return accx::reduce_vars_workspace_bytes();
 }
 
 acc_status run_reduce(int t, const void *x, int64_t n, const void *init, void *dres, uint32_t flags, void *work,
@@ -492,12 +562,32 @@ acc_status run_reduce(int t, const void *x, int64_t n, const void *init, void *d
     return check_launch(e, "reduction launch");
 }
 
+// init: nvars host values of type t; dres: nvars device elements.
+acc_status run_reduce_vars(int t, const void *x, int64_t n, const acc_reduce_var *vars, int nvars, const void *init,
+                           void *dres, uint32_t flags, void *work, hipStream_t s)
+{
+    if (legacy_sum(t, vars, nvars)) return run_reduce(t, x, n, init, dres, flags, work, s);
+    acc_status st = launch_fault();
+    if (st != ACC_OK) return st;
+    accx::RedVars rv{};
+    rv.nvars = nvars;
+    const size_t eb = elem_bytes(t);
+    for (int v = 0; v < nvars; ++v) {
+        rv.op[v] = vars[v].op;
+        rv.square[v] = vars[v].square;
+        std::memcpy(&rv.init[v], static_cast<const char *>(init) + v * eb, eb);
+    }
+    return check_launch(accx::launch_reduce_vars(t, x, n, rv, dres, work, s), "reduction launch");
+}
+
 void free_region(acc_region_s *r)
 {
     State &st = S();
+    // drop this region's references; a mapping goes when its last one does
     for (uintptr_t k : r->keys) {
         auto it = st.present.find(k);
         if (it == st.present.end()) continue;
+        if (--it->second.refs > 0) continue;
         dev_free(it->second.dev, it->second.hend - it->second.hbeg);
         st.present.erase(it);
     }
@@ -505,7 +595,8 @@ void free_region(acc_region_s *r)
     ws_release(r->mm_work);
     ws_release(r->red_work);
     ws_release(r->red_plain_work);
-    if (r->dres) dev_free(r->dres, (size_t)r->nslots * 4);
+    ws_release(r->red_vars_work);
+    if (r->dres) dev_free(r->dres, (size_t)r->nslots * 8);
     if (r->hres) (void)hipHostFree(r->hres);
     r->dres = nullptr;
     r->hres = nullptr;
@@ -519,7 +610,7 @@ acc_status finish_pending(acc_region_s *r)
         r->used_slots = 0;
         return ACC_OK;
     }
-    for (const Pending &p : r->pending) std::memcpy(p.host_dst, r->hres + p.slot, 4);
+    for (const Pending &p : r->pending) std::memcpy(p.host_dst, r->hres + p.slot, p.bytes);
     r->pending.clear();
     r->used_slots = 0;
     return ACC_OK;
@@ -694,7 +785,7 @@ acc_status acc_shutdown(void)
         delete b;
     }
     batches().clear();
-    for (auto *m : {&st.mm_ws, &st.red_ws, &st.red_plain_ws}) {
+    for (auto *m : {&st.mm_ws, &st.red_ws, &st.red_plain_ws, &st.red_vars_ws}) {
         for (auto &kv : *m) ws_release(kv.second);
         m->clear();
     }
@@ -723,26 +814,50 @@ acc_status acc_data_begin(const acc_clause *cl, int ncl, void *hip_stream, acc_r
     acc_status s = check_ready();
     if (s != ACC_OK) return s;
 
-    // Validate every clause before touching the device.
-    std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+    // Validate every clause before touching the device.  A present clause,
+    // and a present_or_* clause whose range is already mapped, takes a
+    // reference to the mapping that holds it; every other clause maps a new
+    // range, which must not overlap any mapped range or another new one.
+    struct Plan {
+        uintptr_t b, e;
+        int kind;            // data movement of a new mapping
+        int dtype;
+        uintptr_t ref = 0;   // key of the mapping referenced, else 0
+        bool fresh = false;  // maps a new range
+    };
+    std::vector<Plan> plan;
     uint64_t total = 0;
     for (int k = 0; k < ncl; ++k) {
         const acc_clause &c = cl[k];
-        if (c.kind < ACC_COPY || c.kind > ACC_CREATE) return fail(ACC_ERR_INVALID_ARG, "unknown clause kind");
+        if (c.kind < ACC_COPY || c.kind > ACC_PRESENT_OR_CREATE)
+            return fail(ACC_ERR_INVALID_ARG, "unknown clause kind");
         if (!valid_dtype(c.dtype)) return fail(ACC_ERR_INVALID_ARG, "unknown clause dtype");
         if (c.start < 0 || c.n < 0) return fail(ACC_ERR_INVALID_ARG, "clause start and n must be >= 0");
         if (c.n == 0) continue;
         if (!c.host) return fail(ACC_ERR_INVALID_ARG, "clause host pointer is NULL");
         if (c.n > (int64_t)(1ll << 40)) return fail(ACC_ERR_INVALID_ARG, "clause too large");
-        const uintptr_t b = reinterpret_cast<uintptr_t>(c.host) + (uintptr_t)c.start * elem_bytes(c.dtype);
-        const uintptr_t e = b + (uintptr_t)c.n * elem_bytes(c.dtype);
-        if (overlaps_present(b, e))
-            return fail(ACC_ERR_ALREADY_PRESENT, "clause " + std::to_string(k) + " overlaps a mapped host range");
-        for (auto &r : ranges)
-            if (b < r.second && r.first < e)
-                return fail(ACC_ERR_ALREADY_PRESENT, "clauses of one region overlap");
-        ranges.push_back({b, e});
-        total += e - b;
+        Plan p;
+        p.b = reinterpret_cast<uintptr_t>(c.host) + (uintptr_t)c.start * elem_bytes(c.dtype);
+        p.e = p.b + (uintptr_t)c.n * elem_bytes(c.dtype);
+        const bool present_kind = c.kind >= ACC_PRESENT;
+        p.kind = c.kind >= ACC_PRESENT_OR_COPY ? c.kind - ACC_PRESENT_OR_COPY + ACC_COPY : c.kind;
+        p.dtype = c.dtype;
+        Entry *hold = present_kind ? lookup(reinterpret_cast<void *>(p.b), p.e - p.b) : nullptr;
+        if (hold) {
+            if (hold->dtype != c.dtype)
+                return fail(ACC_ERR_INVALID_ARG, "clause " + std::to_string(k) + " is mapped with another dtype");
+            p.ref = hold->hbeg;
+        } else if (c.kind == ACC_PRESENT) {
+            return fail(ACC_ERR_NOT_PRESENT, "present clause " + std::to_string(k) + " is not inside a mapped range");
+        } else {
+            if (overlaps_present(p.b, p.e))
+                return fail(ACC_ERR_ALREADY_PRESENT, "clause " + std::to_string(k) + " overlaps a mapped host range");
+            for (const Plan &q : plan)
+                if (q.fresh && p.b < q.e && q.b < p.e) return fail(ACC_ERR_ALREADY_PRESENT, "clauses of one region overlap");
+            p.fresh = true;
+            total += p.e - p.b;
+        }
+        plan.push_back(p);
     }
     if (st.budget && st.used + total > st.budget)
         return fail(ACC_ERR_OUT_OF_MEMORY, "region needs " + std::to_string(total) + " bytes; budget has " +
@@ -761,17 +876,20 @@ acc_status acc_data_begin(const acc_clause *cl, int ncl, void *hip_stream, acc_r
         r->own_stream = true;
     }
 
-    for (int k = 0; k < ncl; ++k) {
-        const acc_clause &c = cl[k];
-        if (c.n == 0) continue;
+    for (const Plan &p : plan) {
+        if (!p.fresh) {
+            st.present[p.ref].refs++;
+            r->keys.push_back(p.ref);
+            continue;
+        }
         Entry en;
-        en.hbeg = reinterpret_cast<uintptr_t>(c.host) + (uintptr_t)c.start * elem_bytes(c.dtype);
-        en.hend = en.hbeg + (uintptr_t)c.n * elem_bytes(c.dtype);
-        en.kind = c.kind;
-        en.dtype = c.dtype;
-        en.owner = r;
+        en.hbeg = p.b;
+        en.hend = p.e;
+        en.kind = p.kind;
+        en.dtype = p.dtype;
+        en.refs = 1;
         s = dev_alloc(&en.dev, en.hend - en.hbeg);
-        if (s == ACC_OK && (c.kind == ACC_COPY || c.kind == ACC_COPYIN)) {
+        if (s == ACC_OK && (p.kind == ACC_COPY || p.kind == ACC_COPYIN)) {
             if (fault_hit(st.fault.copies, st.fault.copy_at)) {
                 s = fail(ACC_ERR_DEVICE, "injected copy fault (ACCX_FAULT)");
             } else {
@@ -823,8 +941,12 @@ acc_status acc_data_end(acc_region r)
         first_msg = t_last_error;
     }
     if (first == ACC_OK) {
-        for (uintptr_t k : r->keys) {
-            const Entry &en = st.present[k];
+        // copy out the mappings whose last reference this region drops
+        std::map<uintptr_t, int> held;
+        for (uintptr_t k : r->keys) held[k]++;
+        for (const auto &kv : held) {
+            const Entry &en = st.present[kv.first];
+            if (en.refs > kv.second) continue;
             if (en.kind != ACC_COPY && en.kind != ACC_COPYOUT) continue;
             if (fault_hit(st.fault.copies, st.fault.copy_at)) {
                 first = ACC_ERR_DEVICE;
@@ -852,6 +974,62 @@ acc_status acc_data_end(acc_region r)
     return ACC_OK;
 }
 
+acc_status acc_update(acc_region r, int direction, acc_dtype t, void *host, int64_t start, int64_t n,
+                      uint32_t flags)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!r || !st.regions.count(r)) return fail(ACC_ERR_INVALID_ARG, "unknown region");
+    if (r->err != ACC_OK) return fail(r->err, "region already failed: " + r->err_msg);
+    if (direction != ACC_UPDATE_HOST && direction != ACC_UPDATE_DEVICE)
+        return fail(ACC_ERR_INVALID_ARG, "direction must be ACC_UPDATE_HOST or ACC_UPDATE_DEVICE");
+    if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "unknown dtype");
+    if (start < 0 || n < 0) return fail(ACC_ERR_INVALID_ARG, "start and n must be >= 0");
+    if (flags & ~ACC_ASYNC) return fail(ACC_ERR_INVALID_ARG, "unknown flag bits");
+    if (n == 0) return ACC_OK;
+    if (!host) return fail(ACC_ERR_INVALID_ARG, "host is NULL");
+    char *h = static_cast<char *>(host) + start * (int64_t)elem_bytes(t);
+    const size_t bytes = (size_t)n * elem_bytes(t);
+    void *dev;
+    acc_status s = resolve(h, bytes, t, "update range", &dev);
+    if (s != ACC_OK) return s;
+    if (fault_hit(st.fault.copies, st.fault.copy_at)) return poison(r, fail(ACC_ERR_DEVICE, "injected copy fault (ACCX_FAULT)"));
+    const hipError_t e = direction == ACC_UPDATE_HOST
+                             ? hipMemcpyAsync(h, dev, bytes, hipMemcpyDeviceToHost, r->stream)
+                             : hipMemcpyAsync(dev, h, bytes, hipMemcpyHostToDevice, r->stream);
+    if (e != hipSuccess) return poison(r, fail_hip(e, "hipMemcpyAsync (update)"));
+    if (flags & ACC_ASYNC) return ACC_OK;
+    return wait_region(r);
+}
+
+acc_status acc_is_present(const void *host, size_t bytes, int *present_out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!present_out) return fail(ACC_ERR_INVALID_ARG, "present_out is NULL");
+    *present_out = host && lookup(host, bytes ? bytes : 1) ? 1 : 0;
+    return ACC_OK;
+}
+
+acc_status accx_host_alloc(size_t bytes, void **host_out)
+{
+    if (!host_out) return fail(ACC_ERR_INVALID_ARG, "host_out is NULL");
+    *host_out = nullptr;
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    const hipError_t e = hipHostMalloc(host_out, bytes ? bytes : 1, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(ACC_ERR_OUT_OF_MEMORY, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    return ACC_OK;
+}
+
+acc_status accx_host_free(void *host)
+{
+    if (!host) return ACC_OK;
+    const hipError_t e = hipHostFree(host);
+    if (e != hipSuccess) return fail_hip(e, "hipHostFree");
+    return ACC_OK;
+}
+
 acc_status acc_deviceptr(const void *host, void **device_out)
 {
     State &st = S();
@@ -864,65 +1042,118 @@ acc_status acc_deviceptr(const void *host, void **device_out)
     return ACC_OK;
 }
 
-acc_status acc_loopnest_matmul(acc_region r, acc_dtype t, const void *a, const void *b, void *c, int64_t len,
-                               uint32_t flags)
+namespace {
+acc_status region_gemm(acc_region r, int t, const GemmShape &sh, const void *a, const void *b, void *c,
+                       uint32_t flags)
 {
     State &st = S();
-    std::lock_guard<std::recursive_mutex> lk(st.mu);
     if (!r || !st.regions.count(r)) return fail(ACC_ERR_INVALID_ARG, "unknown region");
     if (r->err != ACC_OK) return fail(r->err, "region already failed: " + r->err_msg);
-    acc_status s = validate_matmul(t, len, flags);
+    acc_status s = validate_gemm(t, sh, flags);
     if (s != ACC_OK) return s;
-    const size_t bytes = (size_t)len * (size_t)len * 4;
-    void *da, *db, *dc;
-    if ((s = resolve(a, bytes, t, "a", &da)) != ACC_OK) return s;
-    if ((s = resolve(b, bytes, t, "b", &db)) != ACC_OK) return s;
-    if ((s = resolve(c, bytes, t, "c", &dc)) != ACC_OK) return s;
+    if (sh.m == 0 || sh.n == 0) return ACC_OK;
+    const size_t ab = (size_t)span_elems(sh.m, sh.k, sh.lda) * 4, bb = (size_t)span_elems(sh.k, sh.n, sh.ldb) * 4;
+    const size_t cb = (size_t)span_elems(sh.m, sh.n, sh.ldc) * 4;
+    void *da = nullptr, *db = nullptr, *dc;
+    if (ab && (s = resolve(a, ab, t, "a", &da)) != ACC_OK) return s;
+    if (bb && (s = resolve(b, bb, t, "b", &db)) != ACC_OK) return s;
+    if ((s = resolve(c, cb, t, "c", &dc)) != ACC_OK) return s;
     const uintptr_t ci = reinterpret_cast<uintptr_t>(c);
-    for (const void *in : {a, b}) {
-        const uintptr_t ii = reinterpret_cast<uintptr_t>(in);
-        if (ci < ii + bytes && ii < ci + bytes) return fail(ACC_ERR_INVALID_ARG, "c overlaps an input");
+    const std::pair<const void *, size_t> ins[2] = {{a, ab}, {b, bb}};
+    for (const auto &in : ins) {
+        const uintptr_t ii = reinterpret_cast<uintptr_t>(in.first);
+        if (in.second && ci < ii + in.second && ii < ci + cb) return fail(ACC_ERR_INVALID_ARG, "c overlaps an input");
     }
-    const size_t wsb = matmul_ws_bytes(t, len, flags);
+    const size_t wsb = matmul_ws_bytes(t, sh, flags);
     if (wsb && (s = ws_reserve(r->mm_work, wsb, false, r->stream)) != ACC_OK) return s;
-    s = run_matmul(t, da, db, dc, len, flags, r->mm_work.ptr, r->mm_work.bytes, r->stream);
+    s = run_matmul(t, da, db, dc, sh, flags, r->mm_work.ptr, r->mm_work.bytes, r->stream);
     if (s != ACC_OK) return poison(r, s);
     return ACC_OK;
 }
+}  // namespace
+
+acc_status acc_loopnest_matmul(acc_region r, acc_dtype t, const void *a, const void *b, void *c, int64_t len,
+                               uint32_t flags)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    acc_status s = validate_matmul(t, len, flags);
+    if (s != ACC_OK) return s;
+    return region_gemm(r, t, accx::square_shape(len), a, b, c, flags);
+}
+
+acc_status acc_loopnest_gemm(acc_region r, acc_dtype t, int64_t m, int64_t n, int64_t k, const void *a, int64_t lda,
+                             const void *b, int64_t ldb, void *c, int64_t ldc, uint32_t flags)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    return region_gemm(r, t, GemmShape{m, n, k, lda, ldb, ldc}, a, b, c, flags);
+}
+
+namespace {
+// Logical or of zero elements: the variable becomes 1 if it was nonzero, else 0.
+void or_of_nothing(int t, void *inout)
+{
+    switch (t) {
+    case ACC_FLOAT32: *static_cast<float *>(inout) = *static_cast<float *>(inout) != 0.0f ? 1.0f : 0.0f; break;
+    case ACC_INT32: *static_cast<int32_t *>(inout) = *static_cast<int32_t *>(inout) != 0; break;
+    case ACC_FLOAT64: *static_cast<double *>(inout) = *static_cast<double *>(inout) != 0.0 ? 1.0 : 0.0; break;
+    default: *static_cast<int64_t *>(inout) = *static_cast<int64_t *>(inout) != 0; break;
+    }
+}
+
+acc_status region_reduce(acc_region r, int t, const void *x, int64_t n, const acc_reduce_var *vars, int nvars,
+                         void *inout, uint32_t flags)
+{
+    State &st = S();
+    if (!r || !st.regions.count(r)) return fail(ACC_ERR_INVALID_ARG, "unknown region");
+    if (r->err != ACC_OK) return fail(r->err, "region already failed: " + r->err_msg);
+    acc_status s = validate_vars(t, n, vars, nvars, flags);
+    if (s != ACC_OK) return s;
+    if (!inout) return fail(ACC_ERR_INVALID_ARG, "inout_result is NULL");
+    if (n == 0) {  // nothing to fold: every variable keeps its value
+        if (vars[0].op == ACC_RED_OR) or_of_nothing(t, inout);
+        return ACC_OK;
+    }
+    const size_t eb = elem_bytes(t);
+    void *dx;
+    if ((s = resolve(x, (size_t)n * eb, t, "x", &dx)) != ACC_OK) return s;
+    if (!r->dres) {
+        if ((s = dev_alloc(&r->dres, (size_t)kMaxSlots * 8)) != ACC_OK) return s;
+        r->nslots = kMaxSlots;
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&r->hres), (size_t)kMaxSlots * 8);
+        if (e != hipSuccess) return fail_hip(e, "hipHostMalloc");
+    }
+    if (r->used_slots + nvars > r->nslots) {
+        if ((s = wait_region(r)) != ACC_OK) return s;
+    }
+    const bool legacy = legacy_sum(t, vars, nvars);
+    const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
+    Workspace &w = !legacy ? r->red_vars_work : plain ? r->red_plain_work : r->red_work;
+    if ((s = ws_reserve(w, vars_ws_bytes(t, n, vars, nvars, flags), !plain, r->stream)) != ACC_OK) return s;
+    const int slot = r->used_slots;
+    r->used_slots += nvars;
+    void *dslot = static_cast<char *>(r->dres) + (size_t)slot * 8;
+    s = run_reduce_vars(t, dx, n, vars, nvars, inout, dslot, flags, w.ptr, r->stream);
+    if (s != ACC_OK) return poison(r, s);
+    hipError_t e = hipMemcpyAsync(r->hres + slot, dslot, nvars * eb, hipMemcpyDeviceToHost, r->stream);
+    if (e != hipSuccess) return poison(r, fail_hip(e, "hipMemcpyAsync D2H (result)"));
+    r->pending.push_back(Pending{inout, slot, nvars * eb});
+    if (flags & ACC_ASYNC) return ACC_OK;
+    return wait_region(r);
+}
+}  // namespace
 
 acc_status acc_reduce_sum(acc_region r, acc_dtype t, const void *x, int64_t n, void *inout, uint32_t flags)
 {
-    State &st = S();
-    std::lock_guard<std::recursive_mutex> lk(st.mu);
-    if (!r || !st.regions.count(r)) return fail(ACC_ERR_INVALID_ARG, "unknown region");
-    if (r->err != ACC_OK) return fail(r->err, "region already failed: " + r->err_msg);
-    acc_status s = validate_reduce(t, n, flags);
-    if (s != ACC_OK) return s;
-    if (!inout) return fail(ACC_ERR_INVALID_ARG, "inout_result is NULL");
-    if (n == 0) return ACC_OK;  // *inout unchanged
-    void *dx;
-    if ((s = resolve(x, (size_t)n * 4, t, "x", &dx)) != ACC_OK) return s;
-    if (!r->dres) {
-        if ((s = dev_alloc(&r->dres, (size_t)kMaxSlots * 4)) != ACC_OK) return s;
-        r->nslots = kMaxSlots;
-        const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&r->hres), (size_t)kMaxSlots * 4);
-        if (e != hipSuccess) return fail_hip(e, "hipHostMalloc");
-    }
-    if (r->used_slots == r->nslots) {
-        if ((s = wait_region(r)) != ACC_OK) return s;
-    }
-    const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
-    Workspace &w = plain ? r->red_plain_work : r->red_work;
-    if ((s = ws_reserve(w, reduce_ws_bytes(n, flags), !plain, r->stream)) != ACC_OK) return s;
-    const int slot = r->used_slots++;
-    void *dslot = static_cast<char *>(r->dres) + (size_t)slot * 4;
-    s = run_reduce(t, dx, n, inout, dslot, flags, w.ptr, r->stream);
-    if (s != ACC_OK) return poison(r, s);
-    hipError_t e = hipMemcpyAsync(r->hres + slot, dslot, 4, hipMemcpyDeviceToHost, r->stream);
-    if (e != hipSuccess) return poison(r, fail_hip(e, "hipMemcpyAsync D2H (result)"));
-    r->pending.push_back(Pending{inout, slot});
-    if (flags & ACC_ASYNC) return ACC_OK;
-    return wait_region(r);
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    const acc_reduce_var sum{ACC_RED_SUM, 0};
+    return region_reduce(r, t, x, n, &sum, 1, inout, flags);
+}
+
+acc_status acc_reduce(acc_region r, acc_dtype t, const void *x, int64_t n, const acc_reduce_var *vars, int nvars,
+                      void *inout, uint32_t flags)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    return region_reduce(r, t, x, n, vars, nvars, inout, flags);
 }
 
 acc_status accx_matmul_workspace_size(acc_dtype t, int64_t len, uint32_t flags, size_t *bytes_out)
@@ -930,23 +1161,35 @@ acc_status accx_matmul_workspace_size(acc_dtype t, int64_t len, uint32_t flags, 
     if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
     acc_status s = validate_matmul(t, len, flags);
     if (s != ACC_OK) return s;
-    *bytes_out = matmul_ws_bytes(t, len, flags);
+    *bytes_out = matmul_ws_bytes(t, accx::square_shape(len), flags);
     return ACC_OK;
 }
 
-acc_status accx_matmul_dev(acc_dtype t, const void *dA, const void *dB, void *dC, int64_t len, uint32_t flags,
-                           void *dWork, size_t work_bytes, void *hip_stream)
+acc_status accx_gemm_workspace_size(acc_dtype t, int64_t m, int64_t n, int64_t k, uint32_t flags, size_t *bytes_out)
+{
+    if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
+    const GemmShape sh{m, n, k, std::max<int64_t>(1, k), std::max<int64_t>(1, n), std::max<int64_t>(1, n)};
+    acc_status s = validate_gemm(t, sh, flags);
+    if (s != ACC_OK) return s;
+    *bytes_out = matmul_ws_bytes(t, sh, flags);
+    return ACC_OK;
+}
+
+namespace {
+acc_status dev_gemm(int t, const GemmShape &sh, const void *dA, const void *dB, void *dC, uint32_t flags, void *dWork,
+                    size_t work_bytes, void *hip_stream)
 {
     State &st = S();
-    std::lock_guard<std::recursive_mutex> lk(st.mu);
     acc_status s = check_ready();
     if (s != ACC_OK) return s;
-    if ((s = validate_matmul(t, len, flags)) != ACC_OK) return s;
-    if (!dA || !dB || !dC) return fail(ACC_ERR_INVALID_ARG, "NULL device pointer");
+    if ((s = validate_gemm(t, sh, flags)) != ACC_OK) return s;
+    if (flags & ACC_ASYNC) return fail(ACC_ERR_INVALID_ARG, "ACC_ASYNC applies to region calls only");
+    if (sh.m == 0 || sh.n == 0) return ACC_OK;
+    if ((sh.k > 0 && (!dA || !dB)) || !dC) return fail(ACC_ERR_INVALID_ARG, "NULL device pointer");
     if (((uintptr_t)dA | (uintptr_t)dB | (uintptr_t)dC) & 3u)
         return fail(ACC_ERR_INVALID_ARG, "device pointers must be 4-byte aligned");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const size_t need = matmul_ws_bytes(t, len, flags);
+    const size_t need = matmul_ws_bytes(t, sh, flags);
     if (need) {
         if (dWork) {
             if (work_bytes < need) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
@@ -957,61 +1200,123 @@ acc_status accx_matmul_dev(acc_dtype t, const void *dA, const void *dB, void *dC
             work_bytes = w.bytes;
         }
     }
-    return run_matmul(t, dA, dB, dC, len, flags, dWork, work_bytes, stream);
+    return run_matmul(t, dA, dB, dC, sh, flags, dWork, work_bytes, stream);
+}
+}  // namespace
+
+acc_status accx_matmul_dev(acc_dtype t, const void *dA, const void *dB, void *dC, int64_t len, uint32_t flags,
+                           void *dWork, size_t work_bytes, void *hip_stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if ((s = validate_matmul(t, len, flags)) != ACC_OK) return s;
+    return dev_gemm(t, accx::square_shape(len), dA, dB, dC, flags, dWork, work_bytes, hip_stream);
+}
+
+acc_status accx_gemm_dev(acc_dtype t, int64_t m, int64_t n, int64_t k, const void *dA, int64_t lda, const void *dB,
+                         int64_t ldb, void *dC, int64_t ldc, uint32_t flags, void *dWork, size_t work_bytes,
+                         void *hip_stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    return dev_gemm(t, GemmShape{m, n, k, lda, ldb, ldc}, dA, dB, dC, flags, dWork, work_bytes, hip_stream);
 }
 
 acc_status accx_reduce_workspace_size(acc_dtype t, int64_t n, uint32_t flags, size_t *bytes_out)
 {
+    const acc_reduce_var sum{ACC_RED_SUM, 0};
+    return accx_reduce_vars_workspace_size(t, n, &sum, 1, flags, bytes_out);
+}
+
+acc_status accx_reduce_vars_workspace_size(acc_dtype t, int64_t n, const acc_reduce_var *vars, int nvars,
+                                           uint32_t flags, size_t *bytes_out)
+{
     if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
-    acc_status s = validate_reduce(t, n, flags);
+    acc_status s = validate_vars(t, n, vars, nvars, flags);
     if (s != ACC_OK) return s;
-    *bytes_out = reduce_ws_bytes(n, flags);
+    *bytes_out = vars_ws_bytes(t, n, vars, nvars, flags);
     return ACC_OK;
 }
+
+namespace {
+acc_status dev_reduce(int t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars, const void *init,
+                      void *dResult, uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream)
+{
+    State &st = S();
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if ((s = validate_vars(t, n, vars, nvars, flags)) != ACC_OK) return s;
+    if (flags & ACC_ASYNC) return fail(ACC_ERR_INVALID_ARG, "ACC_ASYNC applies to region calls only");
+    if ((n > 0 && !dX) || !dResult || !init) return fail(ACC_ERR_INVALID_ARG, "NULL pointer");
+    const uintptr_t am = elem_bytes(t) - 1;
+    if (((uintptr_t)dX | (uintptr_t)dResult) & am)
+        return fail(ACC_ERR_INVALID_ARG, "pointers must be aligned to the element size");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const bool legacy = legacy_sum(t, vars, nvars);
+    const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
+    const size_t need = vars_ws_bytes(t, n, vars, nvars, flags);
+    if (dWork) {
+        if (work_bytes < need) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
+    } else {
+        Workspace &w = !legacy ? st.red_vars_ws[stream] : plain ? st.red_plain_ws[stream] : st.red_ws[stream];
+        if ((s = ws_reserve(w, need, !plain, stream)) != ACC_OK) return s;
+        dWork = w.ptr;
+    }
+    return run_reduce_vars(t, dX, n, vars, nvars, init, dResult, flags, dWork, stream);
+}
+}  // namespace
 
 acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const void *init, void *dResult,
                                uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream)
 {
-    State &st = S();
-    std::lock_guard<std::recursive_mutex> lk(st.mu);
-    acc_status s = check_ready();
-    if (s != ACC_OK) return s;
-    if ((s = validate_reduce(t, n, flags)) != ACC_OK) return s;
-    if (flags & ACC_ASYNC) return fail(ACC_ERR_INVALID_ARG, "ACC_ASYNC applies to region calls only");
-    if ((n > 0 && !dX) || !dResult || !init) return fail(ACC_ERR_INVALID_ARG, "NULL pointer");
-    if (((uintptr_t)dX | (uintptr_t)dResult) & 3u) return fail(ACC_ERR_INVALID_ARG, "pointers must be 4-byte aligned");
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
-    const size_t need = reduce_ws_bytes(n, flags);
-    if (dWork) {
-        if (work_bytes < need) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
-    } else {
-        Workspace &w = plain ? st.red_plain_ws[stream] : st.red_ws[stream];
-        if ((s = ws_reserve(w, need, !plain, stream)) != ACC_OK) return s;
-        dWork = w.ptr;
-    }
-    return run_reduce(t, dX, n, init, dResult, flags, dWork, stream);
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    const acc_reduce_var sum{ACC_RED_SUM, 0};
+    return dev_reduce(t, dX, n, &sum, 1, init, dResult, flags, dWork, work_bytes, hip_stream);
 }
 
-acc_status accx_probe_layout(int64_t len, uint32_t flags, size_t *offset_out, int *count_out)
+acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars,
+                           const void *init, void *dResult, uint32_t flags, void *dWork, size_t work_bytes,
+                           void *hip_stream)
 {
-    State &st = S();
-    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    return dev_reduce(t, dX, n, vars, nvars, init, dResult, flags, dWork, work_bytes, hip_stream);
+}
+
+namespace {
+acc_status probe_layout(const GemmShape &sh, uint32_t flags, size_t *offset_out, int *count_out)
+{
     if (!offset_out || !count_out) return fail(ACC_ERR_INVALID_ARG, "NULL output");
-    acc_status s = validate_matmul(ACC_FLOAT32, len, flags);
+    acc_status s = validate_gemm(ACC_FLOAT32, sh, flags);
     if (s != ACC_OK) return s;
     if (is_plain(flags) || (flags & ACC_PREC_MASK) != ACC_PREC_AUTO)
         return fail(ACC_ERR_INVALID_ARG, "the probe runs only for the tiled kernel with ACC_PREC_AUTO");
-    const int tile = resolve_tile(ACC_FLOAT32, len, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
-    *offset_out = probe_offset(len);
-    *count_out = accx::probe_tiles(tile, len);
+    if (sh.m == 0 || sh.n == 0) return fail(ACC_ERR_INVALID_ARG, "an empty result has no probe records");
+    const int tile = resolve_tile(ACC_FLOAT32, sh, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
+    *offset_out = probe_offset(sh);
+    *count_out = accx::probe_tiles(tile, sh.m, sh.n);
     return ACC_OK;
+}
+}  // namespace
+
+acc_status accx_probe_layout(int64_t len, uint32_t flags, size_t *offset_out, int *count_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    acc_status s = validate_matmul(ACC_FLOAT32, len, flags);
+    if (s != ACC_OK) return s;
+    return probe_layout(accx::square_shape(len), flags, offset_out, count_out);
+}
+
+acc_status accx_gemm_probe_layout(int64_t m, int64_t n, int64_t k, uint32_t flags, size_t *offset_out, int *count_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    return probe_layout(GemmShape{m, n, k, std::max<int64_t>(1, k), std::max<int64_t>(1, n), std::max<int64_t>(1, n)},
+                        flags, offset_out, count_out);
 }
 
 acc_status accx_packed_size(acc_dtype t, int64_t rows, int64_t k, int planes, size_t *bytes_out)
 {
     if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
-    if (!valid_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
+    if (!matmul_dtype(t)) return fail(ACC_ERR_INVALID_ARG, "dtype must be ACC_FLOAT32 or ACC_INT32");
     if (rows < 1 || k < 1 || rows > 65536 || k > 65536) return fail(ACC_ERR_INVALID_ARG, "rows and k in [1, 65536]");
     if (t == ACC_FLOAT32 ? planes != 3 : (planes < 1 || planes > 4))
         return fail(ACC_ERR_INVALID_ARG, "planes: 3 for float32, 1..4 for int32");
@@ -1036,9 +1341,10 @@ acc_status accx_pack_dev(acc_dtype t, const void *dX, int64_t rows, int64_t k, i
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const hipError_t e =
         (t == ACC_FLOAT32)
-            ? accx::launch_pack_bf16x3(static_cast<const float *>(dX), rows, k, transposed != 0, dOut, stream)
-            : accx::launch_pack_i8(static_cast<const int32_t *>(dX), rows, k, transposed != 0, planes, dOut, nullptr,
-                                   stream);
+            ? accx::launch_pack_bf16x3(static_cast<const float *>(dX), rows, k, transposed ? rows : k,
+                                       transposed != 0, dOut, stream)
+            : accx::launch_pack_i8(static_cast<const int32_t *>(dX), rows, k, transposed ? rows : k, transposed != 0,
+                                   planes, dOut, nullptr, stream);
     return check_launch(e, "pack launch");
 }
 
@@ -1047,51 +1353,58 @@ acc_status accx_pack_dev(acc_dtype t, const void *dX, int64_t rows, int64_t k, i
 }  // extern "C"
 
 namespace {
-acc_status autotune_impl(int t, int64_t len, uint32_t flags, unsigned mask, int family, int *best_out,
+acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned mask, int family, int *best_out,
                          double *ms_out)
 {
     acc_status s = ACC_OK;
     const int limbs = (t == ACC_INT32) ? (flag_limbs(flags) ? flag_limbs(flags) : 1) : 0;
-    const size_t mat = (size_t)len * (size_t)len * 4;
-    const size_t pk = (t == ACC_FLOAT32) ? accx::packed_bytes(len, len, 2, 3) : accx::packed_bytes(len, len, 1, limbs);
+    // one scratch input serves as A (m x k) and as B (k x n)
+    const int64_t xel = std::max<int64_t>(1, std::max(sh.m * sh.k, sh.k * sh.n));
+    const size_t xbytes = (size_t)xel * 4, cbytes = (size_t)std::max<int64_t>(1, sh.m * sh.n) * 4;
+    const size_t pka = (t == ACC_FLOAT32) ? accx::packed_bytes(sh.m, sh.k, 2, 3)
+                                          : accx::packed_bytes(sh.m, sh.k, 1, limbs);
+    const size_t pk2b = std::max<size_t>(256, pka + ((t == ACC_FLOAT32) ? accx::packed_bytes(sh.n, sh.k, 2, 3)
+                                                                      : accx::packed_bytes(sh.n, sh.k, 1, limbs)));
     void *x = nullptr, *c = nullptr, *pk2 = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = 0;
     double best_ms = 1e300;
     hipError_t he = hipSuccess;
-    if ((s = dev_alloc(&x, mat)) != ACC_OK) goto out;
-    if ((s = dev_alloc(&c, mat)) != ACC_OK) goto out;
-    if ((s = dev_alloc(&pk2, 2 * pk)) != ACC_OK) goto out;
+    if ((s = dev_alloc(&x, xbytes)) != ACC_OK) goto out;
+    if ((s = dev_alloc(&c, cbytes)) != ACC_OK) goto out;
+    if ((s = dev_alloc(&pk2, pk2b)) != ACC_OK) goto out;
     if ((he = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking)) != hipSuccess) goto hip_out;
     if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess) goto hip_out;
     // Operands: hashed uniform values, float in [-1, 1) or int in [-16, 16]
     // (one limb); constant operands run the matrix cores at a higher clock
     // than real data and would mislead the choice.
-    if ((he = accx::launch_fill_hash(x, len * len, t == ACC_INT32, stream)) != hipSuccess) goto hip_out;
+    if ((he = accx::launch_fill_hash(x, xel, t == ACC_INT32, stream)) != hipSuccess) goto hip_out;
     if (t == ACC_FLOAT32) {
-        he = accx::launch_pack_bf16x3(static_cast<float *>(x), len, len, false, pk2, stream);
+        he = accx::launch_pack_bf16x3(static_cast<float *>(x), sh.m, sh.k, sh.k, false, pk2, stream);
         if (he == hipSuccess)
-            he = accx::launch_pack_bf16x3(static_cast<float *>(x), len, len, true, static_cast<char *>(pk2) + pk, stream);
+            he = accx::launch_pack_bf16x3(static_cast<float *>(x), sh.n, sh.k, sh.n, true,
+                                          static_cast<char *>(pk2) + pka, stream);
     } else {
-        he = accx::launch_pack_i8(static_cast<int32_t *>(x), len, len, false, limbs, pk2, nullptr, stream);
+        he = accx::launch_pack_i8(static_cast<int32_t *>(x), sh.m, sh.k, sh.k, false, limbs, pk2, nullptr, stream);
         if (he == hipSuccess)
-            he = accx::launch_pack_i8(static_cast<int32_t *>(x), len, len, true, limbs, static_cast<char *>(pk2) + pk,
-                                      nullptr, stream);
+            he = accx::launch_pack_i8(static_cast<int32_t *>(x), sh.n, sh.k, sh.n, true, limbs,
+                                      static_cast<char *>(pk2) + pka, nullptr, stream);
     }
     if (he != hipSuccess) goto hip_out;
     {
         // Round-robin over the candidates, several rounds, best per-call time
         // of each: the first rounds also bring the clocks to their loaded
         // steady state, so no candidate is timed alone on a cold device.
+        const GemmShape csh{sh.m, sh.n, sh.k, sh.k, sh.n, sh.n};
         auto run = [&](int tile) {
             return (t == ACC_FLOAT32)
-                       ? accx::launch_gemm_bf16x3(pk2, static_cast<char *>(pk2) + pk, static_cast<float *>(c), len,
+                       ? accx::launch_gemm_bf16x3(pk2, static_cast<char *>(pk2) + pka, static_cast<float *>(c), csh,
                                                   tune_variant(t, flags, 0), false, tile, stream)
-                       : accx::launch_gemm_i8(pk2, static_cast<char *>(pk2) + pk, static_cast<int32_t *>(c), len, limbs,
-                                              tile, stream);
+                       : accx::launch_gemm_i8(pk2, static_cast<char *>(pk2) + pka, static_cast<int32_t *>(c), csh,
+                                              limbs, tile, stream);
         };
-        const double work = 2.0 * (double)len * (double)len * (double)len;
+        const double work = std::max(1.0, 2.0 * (double)sh.m * (double)sh.n * (double)sh.k);
         const int reps = (int)std::max<double>(2.0, std::min<double>(50.0, 2e11 / work));
         const int rounds = 4;
         std::vector<double> per(accx::GEMM_TILE_COUNT, 1e300);
@@ -1116,8 +1429,7 @@ acc_status autotune_impl(int t, int64_t len, uint32_t flags, unsigned mask, int 
                 best = tile;
             }
     }
-    tune_table()[std::make_tuple((int)t, tune_variant(t, flags, limbs) + 100 * family, size_class(len))] =
-        TuneEntry{best, best_ms};
+    tune_table()[tune_key(t, tune_variant(t, flags, limbs) + 100 * family, sh)] = TuneEntry{best, best_ms};
     if (best_out) *best_out = best;
     if (ms_out) *ms_out = best_ms;
     goto out;
@@ -1128,9 +1440,9 @@ out:
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (stream) (void)hipStreamDestroy(stream);
-    dev_free(x, mat);
-    dev_free(c, mat);
-    dev_free(pk2, 2 * pk);
+    dev_free(x, xbytes);
+    dev_free(c, cbytes);
+    dev_free(pk2, pk2b);
     return s;
 }
 
@@ -1145,8 +1457,21 @@ acc_status accx_autotune(acc_dtype t, int64_t len, uint32_t flags, uint32_t *bes
     acc_status s = check_ready();
     if (s != ACC_OK) return s;
     if ((s = validate_matmul(t, len, flags)) != ACC_OK) return s;
+    return accx_autotune_gemm(t, len, len, len, flags, best_tile_out, ms_out);
+}
+
+acc_status accx_autotune_gemm(acc_dtype t, int64_t m, int64_t n, int64_t k, uint32_t flags, uint32_t *best_tile_out,
+                              double *ms_out)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    const GemmShape sh{m, n, k, std::max<int64_t>(1, k), std::max<int64_t>(1, n), std::max<int64_t>(1, n)};
+    if ((s = validate_gemm(t, sh, flags)) != ACC_OK) return s;
+    if (m == 0 || n == 0 || k == 0) return fail(ACC_ERR_INVALID_ARG, "autotune needs m, n, k >= 1");
     int best = 0;
-    if ((s = autotune_impl(t, len, flags, ~0u, 0, &best, ms_out)) != ACC_OK) return s;
+    if ((s = autotune_impl(t, sh, flags, ~0u, 0, &best, ms_out)) != ACC_OK) return s;
     if (best_tile_out) *best_tile_out = (uint32_t)best << ACC_TILE_SHIFT;
     return ACC_OK;
 }
@@ -1159,8 +1484,8 @@ acc_status accx_tune_save(const char *path)
     FILE *f = std::fopen(path, "w");
     if (!f) return fail(ACC_ERR_INVALID_ARG, std::string("cannot write ") + path);
     for (const auto &kv : tune_table())
-        std::fprintf(f, "%d %d %d %d %.6f\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                     kv.second.tile, kv.second.ms);
+        std::fprintf(f, "%d %d %d %d %d %d %.6f\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                     std::get<3>(kv.first), std::get<4>(kv.first), kv.second.tile, kv.second.ms);
     std::fclose(f);
     return ACC_OK;
 }
@@ -1172,18 +1497,42 @@ acc_status accx_tune_load(const char *path)
     if (!path) return fail(ACC_ERR_INVALID_ARG, "path is NULL");
     FILE *f = std::fopen(path, "r");
     if (!f) return fail(ACC_ERR_INVALID_ARG, std::string("cannot read ") + path);
-    int dt, var, cls, tile;
-    double ms;
-    int n;
+    // lines "dtype variant cm cn ck tile ms", or "dtype variant c tile ms"
+    // for a square size class (m, n, k all in class c)
     acc_status s = ACC_OK;
-    while ((n = std::fscanf(f, "%d %d %d %d %lf", &dt, &var, &cls, &tile, &ms)) == 5) {
-        if (!valid_dtype(dt) || tile < 1 || tile >= accx::GEMM_TILE_COUNT || cls < 0 || cls > 16) {
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        std::vector<std::string> tok;
+        for (char *p = std::strtok(line, " \t\r\n"); p; p = std::strtok(nullptr, " \t\r\n")) tok.emplace_back(p);
+        if (tok.empty()) continue;
+        std::vector<long> iv;
+        double ms = 0;
+        bool ok = tok.size() == 7 || tok.size() == 5;
+        for (size_t q = 0; ok && q + 1 < tok.size(); ++q) {
+            char *end = nullptr;
+            iv.push_back(std::strtol(tok[q].c_str(), &end, 10));
+            ok = end && *end == '\0';
+        }
+        if (ok) {
+            char *end = nullptr;
+            ms = std::strtod(tok.back().c_str(), &end);
+            ok = end && *end == '\0';
+        }
+        if (!ok) {
+            s = fail(ACC_ERR_INVALID_ARG, "malformed tune table");
+            break;
+        }
+        const bool sq = tok.size() == 5;
+        const TuneKey key{(int)iv[0], (int)iv[1], (int)iv[2], (int)iv[sq ? 2 : 3], (int)iv[sq ? 2 : 4]};
+        const int tile = (int)iv[sq ? 3 : 5];
+        const int cm = std::get<2>(key), cn = std::get<3>(key), ck = std::get<4>(key);
+        if (!matmul_dtype(std::get<0>(key)) || tile < 1 || tile >= accx::GEMM_TILE_COUNT || cm < 0 || cm > 17 ||
+            cn < 0 || cn > 17 || ck < 0 || ck > 16) {
             s = fail(ACC_ERR_INVALID_ARG, "bad tune table entry");
             break;
         }
-        tune_table()[std::make_tuple(dt, var, cls)] = TuneEntry{tile, ms};
+        tune_table()[key] = TuneEntry{tile, ms};
     }
-    if (s == ACC_OK && n != EOF) s = fail(ACC_ERR_INVALID_ARG, "malformed tune table");
     std::fclose(f);
     return s;
 }
@@ -1216,13 +1565,20 @@ acc_status fail(acc_status s, const std::string &msg) { return ::fail(s, msg); }
 acc_status fail_hip(hipError_t e, const char *what) { return ::fail_hip(e, what); }
 acc_status ready() { return check_ready(); }
 acc_status check_matmul(int t, int64_t len, uint32_t flags) { return validate_matmul(t, len, flags); }
-acc_status check_reduce(int t, int64_t n, uint32_t flags) { return validate_reduce(t, n, flags); }
-size_t matmul_workspace(int t, int64_t len, uint32_t flags) { return matmul_ws_bytes(t, len, flags); }
+acc_status check_reduce(int t, int64_t n, uint32_t flags)
+{
+    if (!matmul_dtype(t)) return ::fail(ACC_ERR_INVALID_ARG, "served reductions are float32 or int32 sums");
+    return validate_reduce(t, n, flags);
+}
+size_t matmul_workspace(int t, int64_t len, uint32_t flags)
+{
+    return matmul_ws_bytes(t, accx::square_shape(len), flags);
+}
 size_t reduce_workspace(int64_t n, uint32_t flags) { return reduce_ws_bytes(n, flags); }
 acc_status matmul(int t, const void *a, const void *b, void *c, int64_t len, uint32_t flags, void *work,
                   size_t work_bytes, hipStream_t s)
 {
-    return run_matmul(t, a, b, c, len, flags, work, work_bytes, s);
+    return run_matmul(t, a, b, c, accx::square_shape(len), flags, work, work_bytes, s);
 }
 acc_status reduce(int t, const void *x, int64_t n, const void *init, void *result, uint32_t flags, void *work,
                   hipStream_t s)
@@ -1431,8 +1787,10 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
             mats[k].pa = pa;
             mats[k].pb = pb;
             const int64_t nrb = (it.n + 31) / 32;
-            jobs.push_back(accx::BatchPackJob{static_cast<const float *>(it.a), pa, it.n, it.n, nrb, mats[k].nkb, 0, 0});
-            jobs.push_back(accx::BatchPackJob{static_cast<const float *>(it.b), pb, it.n, it.n, nrb, mats[k].nkb, 1, 0});
+            jobs.push_back(
+                accx::BatchPackJob{static_cast<const float *>(it.a), pa, it.n, it.n, it.n, nrb, mats[k].nkb, 0, 0});
+            jobs.push_back(
+                accx::BatchPackJob{static_cast<const float *>(it.b), pb, it.n, it.n, it.n, nrb, mats[k].nkb, 1, 0});
         }
         uint32_t *z = reinterpret_cast<uint32_t *>(base + o_zero);
         size_t w = 64;  // counter at word 0, done at word 1
