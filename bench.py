@@ -50,7 +50,7 @@ def _args():
                    help="force the float32 tile configuration (implies --no-autotune)")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the tile autotuner before the timed region (size heuristic instead)")
-    p.add_argument("--workload", choices=["scale", "small", "precision", "batch", "serve", "rowblock"],
+    p.add_argument("--workload", choices=["scale", "small", "precision", "batch", "serve", "rowblock", "reductions"],
                    default="scale",
                    help="scale (default): the step described above; the others measure the remaining "
                         "configurations (LEN=256 plain method, LEN=8192 precision, batching, serving) and "
@@ -520,6 +520,57 @@ def run_rowblock(args) -> int:
     return 0
 
 
+def run_reductions(args) -> int:
+    """The reduction clause beyond float32 +: float64 and int64 sums, the
+    SRAD statistics (sum and sum of squares of one float32 image in one
+    pass), max and min together, and the logical-or flag of a sparse 0/1
+    frontier; 1 GiB of input each, HBM GB/s per call vs the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1412_1127_amd as ax
+    import synth
+    seed = synth.DEFAULT_SEED
+    nb = 1 << 30
+    cases = [
+        ("f64_sum", ax.ACC_FLOAT64, lambda: synth.uniform_pm1_f64(nb // 8, seed, 31), [("sum", False)]),
+        ("i64_sum", ax.ACC_INT64, lambda: synth.full_range_i64(nb // 8, seed, 32), [("sum", False)]),
+        ("f32_srad_sum_sumsq", ax.ACC_FLOAT32, lambda: synth.uniform01_f32(nb // 4, seed, 33),
+         [("sum", False), ("sum", True)]),
+        ("f32_max_min", ax.ACC_FLOAT32, lambda: synth.uniform_pm1_f32((nb // 4,), seed, 34),
+         [("max", False), ("min", False)]),
+        ("i32_or_flag", ax.ACC_INT32, lambda: synth.sparse_flags_i32(nb // 4, 0.0, seed, 35), [("or", False)]),
+    ]
+    ops = {"sum": ax.ACC_RED_SUM, "max": ax.ACC_RED_MAX, "min": ax.ACC_RED_MIN, "or": ax.ACC_RED_OR}
+    ax.acc_init(0, 0)
+    out = {}
+    for name, dt, gen, vars_ in cases:
+        x = gen()
+        dx = torch.from_numpy(x).cuda()
+        res = torch.zeros(len(vars_), dtype=dx.dtype, device="cuda")
+        v = [(ops[o], sq) for o, sq in vars_]
+        init = [oracle.identity(o, x.dtype) for o, _ in vars_]
+        ts = _event_times(lambda: ax.accx_reduce_dev(dt, dx, x.size, v, init, res), args.steps, args.warmup)
+        got = res.cpu().numpy()
+        ms = float(np.median(ts))
+        errs = []
+        for g, (o, sq), i0 in zip(got, vars_, init):
+            ref = oracle.reduce(x, o, init=i0, square=sq)
+            errs.append(abs(float(g) - ref) / max(abs(ref), 1e-300) if x.dtype.kind == "f" else int(int(g) != ref))
+        out[name] = {"ms": ms, "gbs": nb / (ms * 1e-3) / 1e9, "frac_hbm": nb / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "max_rel_err_or_mismatch": max(errs)}
+        del dx
+    ax.acc_shutdown()
+    srad = out["f32_srad_sum_sumsq"]
+    print(json.dumps(_common(
+        args, "reduction GB/s (1 GiB per call; operators and types beyond float32 +)", srad["gbs"], "GB/s",
+        srad["ms"], {"workload": "reductions: float64 / int64 sums, SRAD sum + sum of squares, max + min, "
+                                 "logical-or flag; 1 GiB each", "bytes_per_call": nb},
+        dtype="f32 / f64 / i32 / i64", cases=out)))
+    return 0
+
+
 def run_serve(args) -> int:
     """Poisson 2000 requests/s of offload-region requests through the
     serving engine; latency from scheduled arrival to completion."""
@@ -572,7 +623,7 @@ def main() -> int:
               "and no multi-GPU form is built; run with --gpus 1.", file=sys.stderr)
         return 2
     return {"scale": run_scale, "small": run_small, "precision": run_precision, "batch": run_batch,
-            "serve": run_serve, "rowblock": run_rowblock}[args.workload](args)
+            "serve": run_serve, "rowblock": run_rowblock, "reductions": run_reductions}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -262,7 +262,13 @@ ACCX_API acc_status acc_reduce(acc_region region, acc_dtype t, const void *x, in
 /* ---- device-pointer entries (memory owned by the caller, e.g. torch) ----- */
 
 /* Workspace bytes accx_matmul_dev needs for (t, len, flags); 0 for the plain
- * kernels.  Errors: INVALID_ARG. */
+ * kernels.  The size depends on the tile the call will use (the autotuned
+ * table, else the size heuristic): when the output tiles leave more than
+ * half of the CUs idle, the K loop of each tile is split over up to eight
+ * workgroups whose partial sums (a split area at the end of the workspace)
+ * are added in a fixed part order by the last to finish.  A workspace that
+ * holds the packed operands but not the split area still works: the call
+ * then runs unsplit.  Errors: INVALID_ARG. */
 ACCX_API acc_status accx_matmul_workspace_size(acc_dtype t, int64_t len, uint32_t flags, size_t *bytes_out);
 
 /* The loop nest on device pointers dA, dB, dC (len*len elements each, 4-byte
@@ -322,7 +328,7 @@ ACCX_API acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, cons
  * tile its flags force); ACC_BATCH_AUTOTUNE picks the threshold by timing
  * the batch itself, otherwise it is 512.  Matmuls in a batch use the six-product bf16x3 split; a matmul's
  * result is bitwise that of accx_matmul_dev with ACC_PREC_FULL6 and the same
- * tile.  Reductions are deterministic (fixed chunking, chunk-order combine). */
+ * tile, run unsplit (a workspace without the split area).  Reductions are deterministic (fixed chunking, chunk-order combine). */
 #define ACC_BATCH_MATMUL 0
 #define ACC_BATCH_REDUCE 1
 typedef struct {

@@ -16,7 +16,7 @@
 // its last chunk (atomic ticket), in chunk order, so results do not depend
 // on which workgroup ran what.  A matmul tile is computed by one workgroup in
 // fixed K order, bitwise as by the standalone kernel in the same tile
-// configuration.  The last workgroup to leave resets the queue counters, so
+// configuration when that one runs unsplit (no split K).  The last workgroup to leave resets the queue counters, so
 // the graph can be replayed with no memset node.
 #include <hip/hip_runtime.h>
 

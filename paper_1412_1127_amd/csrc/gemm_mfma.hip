@@ -123,15 +123,148 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
 }
 
 
-template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC>
+// ---- transposed operands (B^T): packing through an LDS transpose ----------
+//
+// Operand row r is column r of the K x R row-major array X, so one 32-row
+// unit touches only 128 bytes of each row of X.  A workgroup therefore
+// stages a tile of TK rows x 256 columns of X in LDS, each row read as one
+// coalesced 1 KB segment, and then builds 16-byte chunks of eight 32-row
+// units from LDS columns (consecutive lanes read consecutive columns: no
+// bank conflicts).
+constexpr int TP_COLS = 256;  // columns of X per tile (eight units)
+constexpr int TP_ROWS = 32;   // rows of X per tile
+
+__device__ inline void stage_rows(const uint32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld, int64_t k0,
+                                  int64_t c0, uint32_t (*t)[TP_COLS])
+{
+    // 32 rows x 64 four-column groups, eight per thread
+    const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15u) == 0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int q = j * 256 + threadIdx.x;
+        const int row = q >> 6, c4 = (q & 63) * 4;
+        const int64_t k = k0 + row, col = c0 + c4;
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (k < K) {
+            if (vec && col + 4 <= R) {
+                const u32x4_t v = *reinterpret_cast<const u32x4_t *>(X + k * ld + col);
+                w[0] = v.x, w[1] = v.y, w[2] = v.z, w[3] = v.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (col + e < R) w[e] = X[k * ld + col + e];
+            }
+        }
+        *reinterpret_cast<u32x4_t *>(&t[row][c4]) = u32x4_t{w[0], w[1], w[2], w[3]};
+    }
+}
+
+// bf16x3 planes of B^T.  Grid: x = column tiles of X, y = 32-element K units.
+__global__ __launch_bounds__(256) void pack_bf16x3_t(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                                     char *__restrict__ out, int64_t nrb, int64_t nkb)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
+    const int64_t kb = blockIdx.y, rb0 = (int64_t)blockIdx.x * (TP_COLS / 32);
+    stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 32, rb0 * 32, t);
+    __syncthreads();
+    // 8 units x 32 rows x 4 chunks of 8 elements, four per thread
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int q = j * 256 + threadIdx.x;
+        const int r = q & 31, c = (q >> 5) & 3, u = q >> 7;
+        if (rb0 + u >= nrb) continue;
+        u16x8 h, m, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            uint16_t a, b, d;
+            split3(__uint_as_float(t[c * 8 + e][u * 32 + r]), a, b, d);
+            h[e] = a;
+            m[e] = b;
+            l[e] = d;
+        }
+        char *o = out + ((rb0 + u) * nkb + kb) * (3 * PLANE_BYTES) + c * 512 + r * 16;
+        *reinterpret_cast<u16x8 *>(o) = h;
+        *reinterpret_cast<u16x8 *>(o + PLANE_BYTES) = m;
+        *reinterpret_cast<u16x8 *>(o + 2 * PLANE_BYTES) = l;
+    }
+}
+
+// int8 digit planes of B^T.  Grid: x = column tiles of X, y = halves of the
+// 64-element K units (32 rows of X each).  maxabs / decide as for pack_i8.
+__global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                                 char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
+                                                 uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
+                                                 int expect)
+{
+    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
+    __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
+    const int64_t kb = blockIdx.y >> 1, rb0 = (int64_t)blockIdx.x * (TP_COLS / 32);
+    const int half = blockIdx.y & 1;
+    stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 64 + half * 32, rb0 * 32, t);
+    __syncthreads();
+    uint32_t mx = 0;
+    // 8 units x 32 rows x 2 chunks of 16 elements, two per thread
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int q = j * 256 + threadIdx.x;
+        const int r = q & 31, c = (q >> 5) & 1, u = q >> 6;
+        if (rb0 + u >= nrb) continue;
+        int64_t rem[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int32_t v = (int32_t)t[c * 16 + e][u * 32 + r];
+            rem[e] = v;
+            const uint32_t a = v < 0 ? (uint32_t)0 - (uint32_t)v : (uint32_t)v;
+            mx = a > mx ? a : mx;
+        }
+        char *o = out + ((rb0 + u) * nkb + kb) * ((int64_t)nplanes * PLANE_BYTES) + (half * 2 + c) * 512 + r * 16;
+        for (int p = 0; p < nplanes; ++p) {
+            i32x4 word = {0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int d = (int)(((uint32_t)rem[e] + 128u) & 255u) - 128;  // in [-128, 127]
+                rem[e] = (rem[e] - d) >> 8;                                     // exact division by 256
+                word[e >> 2] |= (int)((uint32_t)(uint8_t)(int8_t)d << (8 * (e & 3)));
+            }
+            *reinterpret_cast<i32x4 *>(o + (int64_t)p * PLANE_BYTES) = word;
+        }
+    }
+    if (maxabs) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t v = __shfl_xor(mx, o, 64);
+            mx = v > mx ? v : mx;
+        }
+        if ((threadIdx.x & 63) == 0 && mx > __hip_atomic_load(maxabs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(maxabs, mx);
+    }
+}
+
+
+template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
+          bool LA>
 __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 {
     __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPROD, PL>()];
     int tm, tn;
-    tile_of(blockIdx.x, g.tiles_m, g.tiles_n, tm, tn);
+    const int T = g.tiles_m * g.tiles_n;
+    const int t = (int)(blockIdx.x % (unsigned)T);  // split K: part blockIdx.x / T of tile t
+    tile_of(t, g.tiles_m, g.tiles_n, tm, tn);
     if (g.probe && !g.probe[tm * g.tiles_n + tn].corrected) return;  // whole workgroup: uniform
     if (g.decide && !limb_gate(g.decide, g.expect)) return;             // the whole grid: uniform
-    gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC>(g, tm, tn, lds);
+    if (g.ksplit > 1) {
+        GemmArgs h = g;
+        h.split = (int)(blockIdx.x / (unsigned)T);
+        h.tile = t;
+        const int64_t kb0 = (int64_t)h.split * g.kb_count;
+        h.kb_count = kb0 + g.kb_count <= g.nkb ? g.kb_count : g.nkb - kb0;
+        const int64_t off = kb0 * (int64_t)P * PLANE_BYTES;
+        h.A = g.A + off;
+        h.B = g.B + off;
+        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LA>(h, tm, tn, lds);
+    } else {
+        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LA>(g, tm, tn, lds);
+    }
 }
 
 
@@ -253,16 +386,26 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
 //           two workgroups per CU that do not share barriers.
 //  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3).
 //  T64       64 x 64,  4 waves (2x2), 64 B, 2 stages (several int8 planes).
-//  T256W4   256 x 256, 4 waves (2x2, 128 x 128 each), 32 B / 64 B, 3 stages:
-//           a third less LDS read traffic per matrix instruction than T256,
-//           one wavefront per SIMD, accumulators in AGPRs.
-template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC>
+//  T256W4   256 x 256, 4 waves (2x2, 128 x 128 each), 32 B / 64 B, 3 / 4
+//           stages, look-ahead loop: a third less LDS read traffic per matrix
+//           instruction than T256, one wavefront per SIMD, accumulators in
+//           AGPRs, fragments of the next step read during this step's
+//           matrix instructions.
+template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
+          bool LA = false>
 hipError_t launch_tile(GemmArgs g, hipStream_t s)
 {
     g.tiles_m = (int)((g.M + BM - 1) / BM);
     g.tiles_n = (int)((g.N + BN - 1) / BN);
-    const dim3 grid((unsigned)(g.tiles_m * g.tiles_n));
-    hipLaunchKernelGGL((gemm_packed<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC>), grid,
+    if (NACC != 1 || g.accumulate || g.probe) g.ksplit = 1;  // split K: one accumulator set, C = result
+    if (g.ksplit > 1) {
+        g.kb_count = (g.nkb + g.ksplit - 1) / g.ksplit;
+        if ((g.nkb + g.kb_count - 1) / g.kb_count != g.ksplit) return hipErrorInvalidValue;  // host policy bug
+        hipError_t e = launch_zero_u32(g.tickets, g.tiles_m * g.tiles_n, s);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((unsigned)(g.tiles_m * g.tiles_n * (g.ksplit > 1 ? g.ksplit : 1)));
+    hipLaunchKernelGGL((gemm_packed<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LA>), grid,
                        dim3(WGM * WGN * 64), 0, s, g);
     return hipGetLastError();
 }
@@ -279,7 +422,8 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, multi ? 2 : 4, multi ? 2 : 3, NPROD, PL,
                            NACC>(g, s);
     case GEMM_TILE_256W4:
-        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, 2, multi ? 2 : 3, NPROD, PL, NACC>(g, s);
+        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, 2, multi ? 2 : (INT8 ? 4 : 3), NPROD, PL,
+                           NACC, !multi>(g, s);
     case GEMM_TILE_256x128:
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 128, KS, 2, 2, 2, NPROD, PL, NACC>(g, s);
     case GEMM_TILE_128:
@@ -309,7 +453,7 @@ __global__ void fill_hash(uint32_t *p, int64_t n, int as_int)
 
 __global__ void zero_u32(uint32_t *p, int n)
 {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 unsigned pack_grid(int64_t units)
@@ -324,7 +468,7 @@ unsigned pack_grid(int64_t units)
 
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, s, p, n);
+    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -360,8 +504,8 @@ hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, int64_t l
     const unsigned grid = pack_grid(nrb * nkb);
     tmark("pack_bf16x3", s, true);
     if (trans)
-        hipLaunchKernelGGL(pack_bf16x3<true>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out),
-                           nrb, nkb);
+        hipLaunchKernelGGL(pack_bf16x3_t, dim3((unsigned)cdiv(rows, TP_COLS), (unsigned)nkb), dim3(256), 0, s, x, rows,
+                           k, ld, static_cast<char *>(out), nrb, nkb);
     else
         hipLaunchKernelGGL(pack_bf16x3<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out),
                            nrb, nkb);
@@ -377,8 +521,8 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld,
     const unsigned grid = pack_grid(nrb * nkb);
     tmark("pack_i8", s, true);
     if (trans)
-        hipLaunchKernelGGL(pack_i8<true>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out), nrb,
-                           nkb, planes, maxabs, decide, expect);
+        hipLaunchKernelGGL(pack_i8_t, dim3((unsigned)cdiv(rows, TP_COLS), (unsigned)(2 * nkb)), dim3(256), 0, s, x, rows,
+                           k, ld, static_cast<char *>(out), nrb, nkb, planes, maxabs, decide, expect);
     else
         hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out), nrb,
                            nkb, planes, maxabs, decide, expect);
@@ -407,6 +551,28 @@ hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, cons
     return hipGetLastError();
 }
 
+int split_k_parts(int tile, int64_t m, int64_t n, int64_t nkb)
+{
+    int bm, bn;
+    tile_dims(tile, m, n, bm, bn);
+    const int64_t T = cdiv(m, bm) * cdiv(n, bn);
+    const int64_t cus = device_cu_count();
+    if (T <= 0 || 2 * T > cus) return 1;
+    int64_t parts = std::min<int64_t>(8, cus / T);
+    parts = std::min<int64_t>(parts, nkb / 8);  // at least eight 64-byte K units per part
+    if (parts < 2) return 1;
+    return (int)cdiv(nkb, cdiv(nkb, parts));  // every part non-empty
+}
+
+size_t split_k_bytes(int tile, int64_t m, int64_t n, int parts)
+{
+    if (parts <= 1) return 0;
+    int bm, bn;
+    tile_dims(tile, m, n, bm, bn);
+    const int64_t T = cdiv(m, bm) * cdiv(n, bn);
+    return (size_t)(256 + 4 * T + 255) / 256 * 256 + (size_t)parts * T * bm * bn * 4;
+}
+
 int probe_tiles(int tile, int64_t m, int64_t n)
 {
     int bm, bn;
@@ -414,8 +580,17 @@ int probe_tiles(int tile, int64_t m, int64_t n)
     return (int)(cdiv(m, bm) * cdiv(n, bn));
 }
 
+void set_split(GemmArgs &g, const SplitK &sk, int64_t tiles_bytes_offset)
+{
+    g.ksplit = sk.parts > 1 ? sk.parts : 1;
+    if (g.ksplit > 1) {
+        g.tickets = static_cast<uint32_t *>(sk.work);
+        g.partials = static_cast<char *>(sk.work) + tiles_bytes_offset;
+    }
+}
+
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const GemmShape &sh, int products,
-                              bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe)
+                              bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe, const SplitK &sk)
 {
     if (sh.m <= 0 || sh.n <= 0) return hipSuccess;
     GemmArgs g{};
@@ -431,6 +606,11 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
     g.accumulate = accumulate ? 1 : 0;
     g.probe = probe;
     const int t = tile ? tile : default_tile(sh.m, sh.n);
+    if (sk.parts > 1) {
+        int bm, bn;
+        tile_dims(t, sh.m, sh.n, bm, bn);
+        set_split(g, sk, (256 + 4 * cdiv(sh.m, bm) * cdiv(sh.n, bn) + 255) / 256 * 256);
+    }
     hipError_t e;
     tmark("gemm_bf16x3", s, true);
     if (products == 6)
@@ -446,7 +626,7 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
 }
 
 hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,
-                          hipStream_t s, const uint32_t *decide)
+                          hipStream_t s, const uint32_t *decide, const SplitK &sk)
 {
     if (sh.m <= 0 || sh.n <= 0) return hipSuccess;
     GemmArgs g{};
@@ -462,6 +642,11 @@ hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const Gemm
     g.decide = decide;
     g.expect = limbs;
     const int t = tile ? tile : default_tile(sh.m, sh.n);
+    if (sk.parts > 1 && limbs == 1) {
+        int bm, bn;
+        tile_dims(t, sh.m, sh.n, bm, bn);
+        set_split(g, sk, (256 + 4 * cdiv(sh.m, bm) * cdiv(sh.n, bn) + 255) / 256 * 256);
+    }
     hipError_t e;
     tmark("gemm_i8", s, true);
     switch (limbs) {

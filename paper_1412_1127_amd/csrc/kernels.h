@@ -82,9 +82,24 @@ struct ProbeRecord {
 };
 static_assert(sizeof(ProbeRecord) == 192, "probe record layout");
 
+// Split K (short-and-wide results that leave CUs idle): the K loop of each
+// output tile runs in `parts` workgroups whose partial sums are added in
+// part order by the last to finish.  work: split_k_bytes(...) bytes (tile
+// tickets, then partial sums); parts <= 1 = no split.  Ignored for the
+// accumulating (C +=) and multi-digit launches.
+struct SplitK {
+    int parts = 1;
+    void *work = nullptr;
+};
+// The split the library uses for (tile, m, n) with nkb 64-byte K units per
+// row: more parts while the output tiles leave at least half the CUs idle.
+int split_k_parts(int tile, int64_t m, int64_t n, int64_t nkb);
+size_t split_k_bytes(int tile, int64_t m, int64_t n, int parts);
+
 // probe: non-null = skip the tiles whose record has corrected == 0.
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const GemmShape &sh, int products,
-                              bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe = nullptr);
+                              bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe = nullptr,
+                              const SplitK &sk = SplitK());
 // Float64 probe of C per output tile of `tile`; tau: relative Frobenius
 // threshold above which a tile is marked for correction.
 hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, const GemmShape &sh, int tile, double tau,
@@ -96,7 +111,7 @@ int default_tile(int64_t m, int64_t n);
 // decide (optional): runs only if the device-side digit count is 1 (limbs =
 // 1) or more than 1 (limbs = 4).
 hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,
-                          hipStream_t s, const uint32_t *decide = nullptr);
+                          hipStream_t s, const uint32_t *decide = nullptr, const SplitK &sk = SplitK());
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
 // n pseudo-random 32-bit words for timing runs: float32 in [-1, 1) or int32 in [-16, 16].
 hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s);

@@ -28,6 +28,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int PLANE_BYTES = 2048;  // 32 rows x 64 bytes
 
@@ -115,6 +116,7 @@ template <bool INT8> struct Mma;
 template <> struct Mma<false> {
     using Frag = bf16x8;
     using Acc = f32x16;
+    using Elem = float;
     __device__ static inline Acc run(Frag a, Frag b, Acc c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -123,6 +125,7 @@ template <> struct Mma<false> {
 template <> struct Mma<true> {
     using Frag = i32x4;
     using Acc = i32x16;
+    using Elem = int;
     __device__ static inline Acc run(Frag a, Frag b, Acc c)
     {
         return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
@@ -173,6 +176,14 @@ struct GemmArgs {
     const ProbeRecord *probe;  // non-null: skip tiles whose record says no correction
     const uint32_t *decide;    // non-null: run only if limb_gate(decide, expect)
     int expect;
+    // Split K: ksplit > 1 cuts the K range into ksplit parts (kb_count units
+    // each, the last shorter); the workgroup of part `split` of tile `tile`
+    // stores its partial sums to `partials`, and the last of a tile's parts to
+    // finish (ticket) adds them in part order and writes C.
+    int ksplit, split, tile;
+    int64_t kb_count;     // 64-byte K units this workgroup runs (<= nkb)
+    void *partials;       // ksplit x tiles x BM x BN 4-byte words
+    uint32_t *tickets;    // one per tile: zero before the launch, left at zero
 };
 
 // Digits the int8 path needs for two operands with the given max |x| words:
@@ -209,6 +220,11 @@ __device__ inline void tile_of(int bid, int tiles_m, int tiles_n, int &tm, int &
     tn = w / gsz;
 }
 
+// The 32-bit pattern of an accumulator element, taken by value (a bit cast
+// applied to a vector-element expression itself reads element 0).
+__device__ inline uint32_t word_of(float v) { return __float_as_uint(v); }
+__device__ inline uint32_t word_of(int v) { return (uint32_t)v; }
+
 // s_waitcnt immediate that waits until at most N vector-memory operations of
 // this wavefront are outstanding (gfx9 encoding: vmcnt[3:0] and [15:14],
 // expcnt and lgkmcnt left at their maxima).
@@ -233,7 +249,18 @@ constexpr int gemm_lds_bytes()
     return NS * (BM / 32 + BN / 32) * planes_used(PL, NPROD) * 32 * KBK;
 }
 
-template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC>
+//
+// LA (look-ahead) variant: each iteration waits for the NEXT stage, reads its
+// operand fragments from LDS into a second register set and runs the matrix
+// instructions of the current stage from registers, with the LDS reads
+// spread between the matrix instructions (one read per NMFMA/NREAD of them;
+// issuing the reads in bursts next to the matrix instructions measured
+// several times slower on gfx950).  The LDS read latency of one step then
+// hides behind the matrix work of the previous one even with a single
+// wavefront per SIMD.  It costs a second fragment register set and one step
+// of global-load lead (needs NS >= 3).
+template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
+          bool LA = false>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &g, int tm, int tn, char *lds)
 {
     using M = Mma<INT8>;
@@ -254,6 +281,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     static_assert(KBK == 32 || KBK == 64, "K step is 32 or 64 bytes");
     static_assert(NCOPY % WAVES == 0, "loads must divide evenly over the wavefronts");
     static_assert(NS >= 2 && LPW * (NS - 2) < 64, "vmcnt range");
+    static_assert(!LA || NS >= 3, "look-ahead needs three stages");
     static_assert(NS * STAGE <= 160 * 1024, "LDS");
     static_assert(NPL <= P, "product list names a plane the operand lacks");
 
@@ -263,7 +291,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     const int wm = wave / WGN, wn = wave % WGN;
     const int64_t ustride = (int64_t)P * PLANE_BYTES;  // bytes per packed unit
     const int64_t rb0 = (int64_t)tm * MB, cb0 = (int64_t)tn * NB;
-    const int nsteps = (int)(g.nkb * HALVES);
+    const int nsteps = (int)((g.ksplit > 1 ? g.kb_count : g.nkb) * HALVES);
 
     // Per-wave copy descriptors: global unit-row base and LDS offset.
     const char *src_base[LPW];
@@ -303,6 +331,83 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     for (int s = 0; s < NS - 1; ++s)
         if (s < nsteps) issue(s);
 
+    if constexpr (LA) {
+        struct FragSet {
+            Frag a[SUB][NPL][WBM], b[SUB][NPL][WBN];
+        };
+        auto load_frags = [&](int step, FragSet &F) {
+            const char *sA = lds + (step % NS) * STAGE;
+            const char *sB = sA + MB * LUNIT;
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) {
+                const int off = (2 * s + (lane >> 5)) * 512 + (lane & 31) * 16;
+#pragma unroll
+                for (int p = 0; p < NPL; ++p) {
+#pragma unroll
+                    for (int i = 0; i < WBM; ++i)
+                        F.a[s][p][i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + p * 32 * KBK + off);
+#pragma unroll
+                    for (int j = 0; j < WBN; ++j)
+                        F.b[s][p][j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + p * 32 * KBK + off);
+                }
+            }
+        };
+        auto compute = [&](const FragSet &F) {
+#pragma unroll
+            for (int s = 0; s < SUB; ++s)
+#pragma unroll
+                for (int t = 0; t < NPROD; ++t)
+#pragma unroll
+                    for (int i = 0; i < WBM; ++i)
+#pragma unroll
+                        for (int j = 0; j < WBN; ++j)
+                            acc[prod_acc(PL, t)][i][j] = M::run(F.a[s][prod_p(PL, t)][i], F.b[s][prod_q(PL, t)][j],
+                                                                acc[prod_acc(PL, t)][i][j]);
+        };
+        // one iteration: make stage step+1 visible, refill the ring, read
+        // stage step+1 into `next`, then compute stage `step` from `cur`
+        auto la_step = [&](int step, const FragSet &cur, FragSet &next) {
+            if (step + 1 < nsteps) {
+                // younger than step+1 and issued: NS-3 stages, fewer at the tail
+                if (step + NS - 2 <= nsteps - 1)
+                    __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 3)>());
+                else
+                    __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_barrier();
+                asm volatile("" ::: "memory");
+                if (step + NS - 1 < nsteps) issue(step + NS - 1);
+            }
+            // reads of the next stage (a stale but in-bounds stage at the end)
+            // spread between the matrix instructions: 1 LDS read per 4 MFMA
+            load_frags(step + 1 < nsteps ? step + 1 : step, next);
+            compute(cur);
+            constexpr int NREAD = SUB * NPL * (WBM + WBN);
+            constexpr int NMFMA = SUB * NPROD * WBM * WBN;
+#pragma unroll
+            for (int q = 0; q < NREAD; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / NREAD, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+        };
+        if (nsteps > 0) {
+            if (NS - 2 <= nsteps - 1)
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 2)>());
+            else
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            FragSet F0, F1;
+            load_frags(0, F0);
+            int step = 0;
+            for (; step + 1 < nsteps; step += 2) {
+                la_step(step, F0, F1);
+                la_step(step + 1, F1, F0);
+            }
+            if (step < nsteps) compute(F0);  // odd step count: the last stage is in F0
+        }
+    } else
     for (int step = 0; step < nsteps; ++step) {
         // stage `step` has landed once at most (younger stages issued) x LPW loads are outstanding
         if (step + NS - 2 < nsteps)
@@ -338,6 +443,63 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
                             M::run(fa[prod_p(PL, t)][i], fb[prod_q(PL, t)][j], acc[prod_acc(PL, t)][i][j]);
             }
         }
+    }
+
+    // Split K: store this part's sums (register-major: word r*64 + lane of
+    // block (wave, i, j)), and let the last part to finish add all parts in
+    // part order; the other parts are done.
+    if (NACC == 1 && g.ksplit > 1) {
+        __shared__ int last_part;
+        constexpr int BLOCKS = WAVES * WBM * WBN;
+        uint32_t *mine = static_cast<uint32_t *>(g.partials) +
+                         ((int64_t)g.split * (g.tiles_m * g.tiles_n) + g.tile) * (int64_t)(BLOCKS * 1024);
+#pragma unroll
+        for (int i = 0; i < WBM; ++i)
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) {
+                uint32_t *blk = mine + ((wave * WBM + i) * WBN + j) * 1024;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) blk[r * 64 + lane] = word_of(acc[0][i][j][r]);
+            }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) last_part = atomicAdd(g.tickets + g.tile, 1u) == (uint32_t)(g.ksplit - 1);
+        __syncthreads();
+        if (!last_part) return;
+        __threadfence();
+#pragma unroll
+        for (int i = 0; i < WBM; ++i)
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) {
+                // float: ((0 + part 0) + part 1) + ...; int: the same modulo 2^32
+                float fs[16];
+                uint32_t us[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) fs[r] = 0.0f, us[r] = 0u;
+                for (int q = 0; q < g.ksplit; ++q) {
+                    const uint32_t *blk = static_cast<const uint32_t *>(g.partials) +
+                                          ((int64_t)q * (g.tiles_m * g.tiles_n) + g.tile) * (int64_t)(BLOCKS * 1024) +
+                                          ((wave * WBM + i) * WBN + j) * 1024;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const uint32_t w = q == g.split ? word_of(acc[0][i][j][r])
+                                                        : __hip_atomic_load(blk + r * 64 + lane, __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_AGENT);
+                        if (INT8)
+                            us[r] += w;
+                        else
+                            fs[r] += __builtin_bit_cast(float, w);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    if constexpr (INT8)
+                        acc[0][i][j][r] = (int)us[r];
+                    else
+                        acc[0][i][j][r] = fs[r];
+                }
+            }
+        if (threadIdx.x == 0) __hip_atomic_store(g.tickets + g.tile, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // Epilogue.  32x32 accumulator layout: register r of lane l holds

@@ -355,7 +355,30 @@ size_t probe_bytes_max(const GemmShape &sh)
     return (size_t)accx::probe_tiles(accx::GEMM_TILE_64, sh.m, sh.n) * sizeof(accx::ProbeRecord);
 }
 
-size_t matmul_ws_bytes(int t, const GemmShape &sh, uint32_t flags)
+int resolve_tile(int t, const GemmShape &sh, uint32_t flags, int limbs);
+
+// Split-K plan of the launch that may split (float: the first GEMM pass;
+// int: the one-digit GEMM); the split area follows the other workspace parts.
+struct SplitPlan {
+    int tile = 0, parts = 1;
+    size_t bytes = 0;
+};
+
+SplitPlan split_plan(int t, const GemmShape &sh, uint32_t flags)
+{
+    SplitPlan p;
+    if (is_plain(flags) || sh.m == 0 || sh.n == 0 || sh.k == 0) return p;
+    if (t == ACC_INT32 && flag_limbs(flags) > 1) return p;  // several digits: no split
+    uint32_t f = flags;
+    if (t == ACC_FLOAT32 && (flags & ACC_PREC_MASK) == ACC_PREC_AUTO) f = (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3;
+    p.tile = resolve_tile(t, sh, f, t == ACC_INT32 ? 1 : 0);
+    const int64_t nkb = t == ACC_FLOAT32 ? (sh.k * 2 + 63) / 64 : (sh.k + 63) / 64;
+    p.parts = accx::split_k_parts(p.tile, sh.m, sh.n, nkb);
+    p.bytes = accx::split_k_bytes(p.tile, sh.m, sh.n, p.parts);
+    return p;
+}
+
+size_t matmul_ws_base(int t, const GemmShape &sh, uint32_t flags)
 {
     if (is_plain(flags) || sh.m == 0 || sh.n == 0) return 0;
     if (t == ACC_FLOAT32 && (flags & ACC_PREC_MASK) == ACC_PREC_AUTO) return probe_offset(sh) + probe_bytes_max(sh);
@@ -363,6 +386,13 @@ size_t matmul_ws_bytes(int t, const GemmShape &sh, uint32_t flags)
     if (flag_limbs(flags)) return kMaxabsBytes + packed_pair(sh, 1, flag_limbs(flags));
     // probe: one-digit and four-digit operands side by side
     return kMaxabsBytes + packed_pair(sh, 1, 1) + packed_pair(sh, 1, 4);
+}
+
+size_t matmul_ws_bytes(int t, const GemmShape &sh, uint32_t flags)
+{
+    const size_t base = matmul_ws_base(t, sh, flags);
+    const SplitPlan p = split_plan(t, sh, flags);
+    return p.parts > 1 ? align256(base) + p.bytes : base;
 }
 
 // ---- autotuned tile table -----------------------------------------------
@@ -410,9 +440,24 @@ int resolve_tile(int t, const GemmShape &sh, uint32_t flags, int limbs)
     return it == tab.end() ? 0 : it->second.tile;
 }
 
-acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmShape &sh, uint32_t flags, char *work,
-                         hipStream_t s)
+// The split area if the caller's workspace holds it, else no split (a
+// workspace sized before the tile table changed).
+accx::SplitK split_for(int t, const GemmShape &sh, uint32_t flags, char *work, size_t work_bytes)
 {
+    accx::SplitK sk;
+    const SplitPlan p = split_plan(t, sh, flags);
+    const size_t off = align256(matmul_ws_base(t, sh, flags));
+    if (p.parts > 1 && work_bytes >= off + p.bytes) {
+        sk.parts = p.parts;
+        sk.work = work + off;
+    }
+    return sk;
+}
+
+acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmShape &sh, uint32_t flags, char *work,
+                         size_t work_bytes, hipStream_t s)
+{
+    const accx::SplitK sk = split_for(ACC_FLOAT32, sh, flags, work, work_bytes);
     const size_t pb = accx::packed_bytes(sh.m, sh.k, 2, 3);
     char *pa = work, *pbt = work + pb;
     hipError_t e = accx::launch_pack_bf16x3(a, sh.m, sh.k, sh.lda, false, pa, s);
@@ -424,19 +469,21 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
         // on the tiles the probe marked (the others exit at once)
         const int tile = resolve_tile(ACC_FLOAT32, sh, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
         auto *rec = reinterpret_cast<accx::ProbeRecord *>(work + probe_offset(sh));
-        e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, 3, false, tile, s);
+        e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, 3, false, tile, s, nullptr, sk);
         if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, sh, tile, probe_tau(), rec, s);
         if (e == hipSuccess) e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, -3, true, tile, s, rec);
         return check_launch(e, "gemm (bf16x3, probed) launch");
     }
     const int products = (prec == ACC_PREC_CHEAP3) ? 3 : 6;
-    e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, products, false, resolve_tile(ACC_FLOAT32, sh, flags, 0), s);
+    e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, products, false, resolve_tile(ACC_FLOAT32, sh, flags, 0), s, nullptr,
+                                 sk);
     return check_launch(e, "gemm (bf16x3) launch");
 }
 
 acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const GemmShape &sh, uint32_t flags,
-                         char *work, hipStream_t s)
+                         char *work, size_t work_bytes, hipStream_t s)
 {
+    const accx::SplitK sk = split_for(ACC_INT32, sh, flags, work, work_bytes);
     uint32_t *maxabs = reinterpret_cast<uint32_t *>(work);
     char *pa = work + kMaxabsBytes;
     const int nl = flag_limbs(flags);
@@ -457,7 +504,7 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const G
         if (e == hipSuccess)
             e = accx::launch_pack_i8(b, sh.n, sh.k, sh.ldb, true, 4, p4 + pa4, nullptr, s, maxabs, 4);
         if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
-        e = accx::launch_gemm_i8(pa, pa + pa1, c, sh, 1, resolve_tile(ACC_INT32, sh, flags, 1), s, maxabs);
+        e = accx::launch_gemm_i8(pa, pa + pa1, c, sh, 1, resolve_tile(ACC_INT32, sh, flags, 1), s, maxabs, sk);
         if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pa4, c, sh, 4, 0, s, maxabs);
         return check_launch(e, "gemm (int8) launch");
     }
@@ -465,8 +512,9 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const G
     e = accx::launch_pack_i8(a, sh.m, sh.k, sh.lda, false, nl, pa, nullptr, s);
     if (e == hipSuccess) e = accx::launch_pack_i8(b, sh.n, sh.k, sh.ldb, true, nl, pa + pan, nullptr, s);
     if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
-    return check_launch(accx::launch_gemm_i8(pa, pa + pan, c, sh, nl, resolve_tile(ACC_INT32, sh, flags, nl), s),
-                        "gemm (int8) launch");
+    return check_launch(
+        accx::launch_gemm_i8(pa, pa + pan, c, sh, nl, resolve_tile(ACC_INT32, sh, flags, nl), s, nullptr, sk),
+        "gemm (int8) launch");
 }
 
 acc_status run_matmul(int t, const void *a, const void *b, void *c, const GemmShape &sh, uint32_t flags, void *work,
@@ -487,12 +535,12 @@ acc_status run_matmul(int t, const void *a, const void *b, void *c, const GemmSh
                                                            static_cast<int32_t *>(c), sh, l1b, s);
         return check_launch(e, "matmul (plain) launch");
     }
-    if (work_bytes < matmul_ws_bytes(t, sh, flags)) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
+    if (work_bytes < matmul_ws_base(t, sh, flags)) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
     if (t == ACC_FLOAT32)
         return run_tiled_f32(static_cast<const float *>(a), static_cast<const float *>(b), static_cast<float *>(c), sh,
-                             flags, static_cast<char *>(work), s);
+                             flags, static_cast<char *>(work), work_bytes, s);
     return run_tiled_i32(static_cast<const int32_t *>(a), static_cast<const int32_t *>(b), static_cast<int32_t *>(c),
-                         sh, flags, static_cast<char *>(work), s);
+                         sh, flags, static_cast<char *>(work), work_bytes, s);
 }
 
 // ---- reduction dispatch ---------------------------------------------------
@@ -1192,7 +1240,8 @@ acc_status dev_gemm(int t, const GemmShape &sh, const void *dA, const void *dB, 
     const size_t need = matmul_ws_bytes(t, sh, flags);
     if (need) {
         if (dWork) {
-            if (work_bytes < need) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
+            // below `need` but holding the operands: runs without split K
+            if (work_bytes < matmul_ws_base(t, sh, flags)) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
         } else {
             Workspace &w = st.mm_ws[stream];
             if ((s = ws_reserve(w, need, false, stream)) != ACC_OK) return s;
@@ -1365,6 +1414,13 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
                                           : accx::packed_bytes(sh.m, sh.k, 1, limbs);
     const size_t pk2b = std::max<size_t>(256, pka + ((t == ACC_FLOAT32) ? accx::packed_bytes(sh.n, sh.k, 2, 3)
                                                                       : accx::packed_bytes(sh.n, sh.k, 1, limbs)));
+    // each candidate runs with the split K the library would give it
+    const int64_t nkb = t == ACC_FLOAT32 ? (sh.k * 2 + 63) / 64 : (sh.k + 63) / 64;
+    size_t splitb = 0;
+    for (int tile = 1; tile < accx::GEMM_TILE_COUNT; ++tile)
+        if (limbs <= 1)
+            splitb = std::max(splitb, accx::split_k_bytes(tile, sh.m, sh.n, accx::split_k_parts(tile, sh.m, sh.n, nkb)));
+    void *spl = nullptr;
     void *x = nullptr, *c = nullptr, *pk2 = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1374,6 +1430,7 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
     if ((s = dev_alloc(&x, xbytes)) != ACC_OK) goto out;
     if ((s = dev_alloc(&c, cbytes)) != ACC_OK) goto out;
     if ((s = dev_alloc(&pk2, pk2b)) != ACC_OK) goto out;
+    if (splitb && (s = dev_alloc(&spl, splitb)) != ACC_OK) goto out;
     if ((he = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking)) != hipSuccess) goto hip_out;
     if ((he = hipEventCreate(&e0)) != hipSuccess || (he = hipEventCreate(&e1)) != hipSuccess) goto hip_out;
     // Operands: hashed uniform values, float in [-1, 1) or int in [-16, 16]
@@ -1398,11 +1455,16 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
         // steady state, so no candidate is timed alone on a cold device.
         const GemmShape csh{sh.m, sh.n, sh.k, sh.k, sh.n, sh.n};
         auto run = [&](int tile) {
+            accx::SplitK sk;
+            if (limbs <= 1) {
+                sk.parts = accx::split_k_parts(tile, sh.m, sh.n, nkb);
+                sk.work = spl;
+            }
             return (t == ACC_FLOAT32)
                        ? accx::launch_gemm_bf16x3(pk2, static_cast<char *>(pk2) + pka, static_cast<float *>(c), csh,
-                                                  tune_variant(t, flags, 0), false, tile, stream)
+                                                  tune_variant(t, flags, 0), false, tile, stream, nullptr, sk)
                        : accx::launch_gemm_i8(pk2, static_cast<char *>(pk2) + pka, static_cast<int32_t *>(c), csh,
-                                              limbs, tile, stream);
+                                              limbs, tile, stream, nullptr, sk);
         };
         const double work = std::max(1.0, 2.0 * (double)sh.m * (double)sh.n * (double)sh.k);
         const int reps = (int)std::max<double>(2.0, std::min<double>(50.0, 2e11 / work));
@@ -1443,6 +1505,7 @@ out:
     dev_free(x, xbytes);
     dev_free(c, cbytes);
     dev_free(pk2, pk2b);
+    dev_free(spl, splitb);
     return s;
 }
 

@@ -82,7 +82,12 @@ def test_batch_matmul_bitwise_equals_standalone(ax):
         cs, _ = bt.outputs()
         for (a, b, da, db, dc, n), c in zip(bt.mats, cs):
             solo = torch.empty_like(dc)
-            ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, solo, n, ax.ACC_KERNEL_TILED | ax.ACC_PREC_FULL6 | tile)
+            # a workspace holding just the packed operands: the standalone call
+            # runs unsplit (one workgroup per tile, fixed K order), as the batch does
+            base = 2 * ax.accx_packed_size(ax.ACC_FLOAT32, n, n, 3)
+            w = torch.empty(base, dtype=torch.uint8, device="cuda")
+            ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, solo, n, ax.ACC_KERNEL_TILED | ax.ACC_PREC_FULL6 | tile, w,
+                               base)
             torch.cuda.synchronize()
             assert np.array_equal(c, solo.cpu().numpy()), (tile, n)
         bt.close()

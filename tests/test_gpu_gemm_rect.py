@@ -246,3 +246,40 @@ def test_row_block_shape_sampled_rows(ax):
     ax.accx_gemm_dev(ax.ACC_INT32, m, n, k, dai, k, dbi, n, dci, n, _flags(ax, "tiled"))
     torch.cuda.synchronize()
     assert np.array_equal(dci.cpu().numpy()[rows], refi)
+
+
+@pytest.mark.parametrize("tile", [None, "256", "256w4", "128", "64"])
+def test_split_k_long_inner_dimension(ax, tile):
+    # few output tiles and a long K: the K loop of each tile is split over
+    # several workgroups whose partial sums are added in part order
+    import paper_1412_1127_amd as pk
+    m, n, k = 256, 192, 8192
+    a, b = _inputs(m, n, k, "f32", 81)
+    fl = _flags(ax, "full6") | (pk.TILES[tile] if tile else 0)
+    c1 = _gemm(ax, a, b, fl, pads=(0, 0, 0))
+    assert rel_fro(c1, oracle.gemm(a, b)) <= FP32_REL_FRO_TOL
+    assert np.array_equal(_gemm(ax, a, b, fl, pads=(0, 0, 0)), c1)     # same bits on every run
+    ai, bi = _inputs(m, n, k, "i32small", 83)
+    fi = _flags(ax, "tiled") | (pk.TILES[tile] if tile else 0)
+    assert np.array_equal(_gemm(ax, ai, bi, fi), oracle.gemm(ai, bi))
+    c3 = _gemm(ax, a, b, _flags(ax, "auto") | (pk.TILES[tile] if tile else 0))
+    assert rel_fro(c3, oracle.gemm(a, b)) <= FP32_REL_FRO_TOL
+
+
+def test_split_k_with_a_small_caller_workspace_runs_unsplit(ax):
+    # a workspace that holds the operands but not the split area: no split
+    import torch
+    m, n, k = 128, 128, 4096
+    a, b = _inputs(m, n, k, "f32", 85)
+    fl = _flags(ax, "full6")
+    full = ax.accx_gemm_workspace_size(ax.ACC_FLOAT32, m, n, k, fl)
+    base = 2 * 4 * (-(-2 * k // 64)) * 3 * 2048                       # packed A and B^T
+    assert full > base
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    c = torch.empty((m, n), device="cuda")
+    w = torch.empty(base, dtype=torch.uint8, device="cuda")
+    ax.accx_gemm_dev(ax.ACC_FLOAT32, m, n, k, da, k, db, n, c, n, fl, w, base)
+    torch.cuda.synchronize()
+    assert rel_fro(c.cpu().numpy(), oracle.gemm(a, b)) <= FP32_REL_FRO_TOL
+    with pytest.raises(ax.AccxError):
+        ax.accx_gemm_dev(ax.ACC_FLOAT32, m, n, k, da, k, db, n, c, n, fl, w, base - 256)
