@@ -56,6 +56,9 @@ def _args():
                         "configurations (LEN=256 plain method, LEN=8192 precision, batching, serving) and "
                         "one GPU's 512-row block of the LEN=4096 product (rowblock)")
     p.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    p.add_argument("--streams", type=int, choices=[1, 2], default=1,
+                   help="scale: 2 runs the int32 matmul and the reduction on a second stream, overlapped "
+                        "with the float32 matmul")
     p.add_argument("--copy-calib", action="store_true",
                    help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     return p.parse_args()
@@ -134,10 +137,23 @@ def run_scale(args) -> int:
         tuned["i32"] = ax.accx_autotune(ax.ACC_INT32, n, ax.ACC_LIMBS(1))
         print("autotuned tiles:", tuned, file=sys.stderr, flush=True)
 
+    # The three operations of a step are independent: with --streams 2 the
+    # int32 matmul and the reduction run on a second stream (default
+    # priority), so the HBM-bound reduction and packing overlap the float32
+    # matrix-core GEMM; the step ends when both streams are done.
+    side = torch.cuda.Stream() if args.streams == 2 else stream
+    fork, join = torch.cuda.Event(), torch.cuda.Event()
+
     def step():
+        if side is not stream:
+            fork.record(stream)
+            side.wait_event(fork)
         ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, f_flags, wf, wf.numel(), sh)
-        ax.accx_matmul_dev(ax.ACC_INT32, dai, dbi, dci, n, i_flags, wi, wi.numel(), sh)
-        ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, nred, 0.0, dr, 0, wr, wr.numel(), sh)
+        ax.accx_matmul_dev(ax.ACC_INT32, dai, dbi, dci, n, i_flags, wi, wi.numel(), side.cuda_stream)
+        ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, nred, 0.0, dr, 0, wr, wr.numel(), side.cuda_stream)
+        if side is not stream:
+            join.record(side)
+            stream.wait_event(join)
 
     for _ in range(args.warmup):
         step()
@@ -250,7 +266,7 @@ def run_scale(args) -> int:
         "config": {"workload": "plain method at scale: LEN=%d square row-major matmul in float32 uniform[-1,1] "
                                "and int32 uniform [-16,16], plus reduction(+) over %d float32 uniform[0,1)"
                                % (n, nred),
-                   "len": n, "n_reduce": nred, "precision": args.prec, "seed": seed,
+                   "len": n, "n_reduce": nred, "precision": args.prec, "seed": seed, "streams": args.streams,
                    "tiles": {k: {"tile": [t for t, v in ax.TILES.items() if v == tv][0], "tune_ms": ms}
                              for k, (tv, ms) in tuned.items()}},
         "latency_ms": {"p50": _pct(step_ms, 50), "p99": _pct(step_ms, 99),
