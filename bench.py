@@ -40,7 +40,7 @@ def _args():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--len", type=int, default=4096)
     p.add_argument("--n-reduce", type=int, default=1 << 28)
-    p.add_argument("--prec", choices=["full6", "auto", "cheap3"], default="full6")
+    p.add_argument("--prec", choices=["full6", "five", "auto", "cheap3"], default="full6")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=0,
                    help="rows of C the CPU baseline computes per matmul, scaled to the whole step "
@@ -103,8 +103,9 @@ def run_scale(args) -> int:
         return 1
     n, nred = args.len, args.n_reduce
     seed = synth.DEFAULT_SEED
-    prec = {"full6": ax.ACC_PREC_FULL6, "auto": ax.ACC_PREC_AUTO, "cheap3": ax.ACC_PREC_CHEAP3}[args.prec]
-    nprod = {"full6": 6, "auto": 6, "cheap3": 3}[args.prec]
+    prec = {"full6": ax.ACC_PREC_FULL6, "five": ax.ACC_PREC_FIVE, "auto": ax.ACC_PREC_AUTO,
+            "cheap3": ax.ACC_PREC_CHEAP3}[args.prec]
+    nprod = {"full6": 6, "five": 5, "auto": 6, "cheap3": 3}[args.prec]
 
     t_gen = time.time()
     a = synth.uniform_pm1_f32((n, n), seed, synth.STREAM_A)
@@ -149,8 +150,14 @@ def run_scale(args) -> int:
             fork.record(stream)
             side.wait_event(fork)
         ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, f_flags, wf, wf.numel(), sh)
-        ax.accx_matmul_dev(ax.ACC_INT32, dai, dbi, dci, n, i_flags, wi, wi.numel(), side.cuda_stream)
-        ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, nred, 0.0, dr, 0, wr, wr.numel(), side.cuda_stream)
+        if side is not stream:
+            # the HBM-bound reduction first: it can share CUs with the float32
+            # packing and GEMM; the int32 GEMM needs LDS the float32 GEMM holds
+            ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, nred, 0.0, dr, 0, wr, wr.numel(), side.cuda_stream)
+            ax.accx_matmul_dev(ax.ACC_INT32, dai, dbi, dci, n, i_flags, wi, wi.numel(), side.cuda_stream)
+        else:
+            ax.accx_matmul_dev(ax.ACC_INT32, dai, dbi, dci, n, i_flags, wi, wi.numel(), sh)
+            ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, nred, 0.0, dr, 0, wr, wr.numel(), sh)
         if side is not stream:
             join.record(side)
             stream.wait_event(join)

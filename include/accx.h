@@ -112,6 +112,8 @@ typedef struct acc_region_s *acc_region; /* opaque */
                                  adds the missing products if needed */
 #define ACC_PREC_FULL6 0x10u  /* 6 bf16 products: all pairs with p+q <= 2 */
 #define ACC_PREC_CHEAP3 0x20u /* 3 bf16 products: pairs with p+q <= 1 */
+#define ACC_PREC_FIVE 0x30u   /* 5 bf16 products: FULL6 without mid*mid
+                                 (|mid*mid| <= 2^-16 |a||b|) */
 #define ACC_PREC_MASK 0xF0u
 /* int32 on the tiled kernel: limb count (bits 8..11); 0 = probe max |x|. */
 #define ACC_LIMBS_SHIFT 8

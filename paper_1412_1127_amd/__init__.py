@@ -42,6 +42,7 @@ ACC_KERNEL_TILED = 0x3
 ACC_PREC_AUTO = 0x00
 ACC_PREC_FULL6 = 0x10
 ACC_PREC_CHEAP3 = 0x20
+ACC_PREC_FIVE = 0x30
 ACC_LIMBS_SHIFT = 8
 ACC_ASYNC = 0x1000
 ACC_REDUCE_FAST = 0x0

@@ -10,7 +10,8 @@
 //    three bf16 terms x = hi + mid + lo (hi = RN(x), mid = RN(x - hi),
 //    lo = RN(x - hi - mid), RN = round to nearest even); C accumulates in
 //    float32 the products of term pairs (p, q): all six with p+q <= 2
-//    (FULL6), or the three with p+q <= 1 (CHEAP3).
+//    (FULL6), those five without mid*mid (FIVE), or the three with p+q <= 1
+//    (CHEAP3).
 //  - int32 on int8 matrix cores: each operand is written in balanced
 //    base-256 digits d_k in [-128, 127], x = sum d_k 256^k (mod 2^32); C is
 //    the sum over digit pairs (k, m) with k+m <= 3 of (A_k B_m) << 8(k+m),
@@ -615,6 +616,8 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
     tmark("gemm_bf16x3", s, true);
     if (products == 6)
         e = run_gemm<false, 3, 6, PL_FULL6, 1>(t, g, s);
+    else if (products == 5)
+        e = run_gemm<false, 3, 5, PL_FIVE, 1>(t, g, s);
     else if (products == 3)
         e = run_gemm<false, 3, 3, PL_CHEAP3, 1>(t, g, s);
     else if (products == -3)

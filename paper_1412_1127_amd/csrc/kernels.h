@@ -67,8 +67,8 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld,
                           uint32_t *maxabs, hipStream_t s, const uint32_t *decide = nullptr, int expect = 0);
 // C (m x n, leading dimension ldc) = sum over the product set of A-plane x
 // B-plane, A and B packed with k elements per row.
-// products: 6 = FULL6, 3 = CHEAP3, -3 = the three products FULL6 adds to
-// CHEAP3.  accumulate: C += instead of C =.
+// products: 6 = FULL6, 5 = FIVE (FULL6 without mid*mid), 3 = CHEAP3, -3 = the
+// three products FULL6 adds to CHEAP3.  accumulate: C += instead of C =.
 // tile: one of GEMM_TILE_* (0 = size heuristic).
 enum { GEMM_TILE_DEFAULT = 0, GEMM_TILE_256 = 1, GEMM_TILE_256x128 = 2, GEMM_TILE_128 = 3, GEMM_TILE_64 = 4,
        GEMM_TILE_256W4 = 5, GEMM_TILE_COUNT = 6 };

@@ -145,6 +145,9 @@ constexpr int prod_acc(uint64_t L, int t) { return (int)((L >> (6 * t + 4)) & 3)
 constexpr uint64_t PL_CHEAP3 = prod(0, 0, 0, 0) | prod(1, 0, 1, 0) | prod(2, 1, 0, 0);
 constexpr uint64_t PL_FULL6 = PL_CHEAP3 | prod(3, 0, 2, 0) | prod(4, 2, 0, 0) | prod(5, 1, 1, 0);
 constexpr uint64_t PL_CORR3 = prod(0, 0, 2, 0) | prod(1, 2, 0, 0) | prod(2, 1, 1, 0);
+// FULL6 without mid*mid: |mid| <= 2^-8 |x|, so the dropped term is the
+// smallest of the three second-order ones
+constexpr uint64_t PL_FIVE = PL_CHEAP3 | prod(3, 0, 2, 0) | prod(4, 2, 0, 0);
 // int8 limbs, accumulator = shift group k+m
 constexpr uint64_t PL_L1 = prod(0, 0, 0, 0);
 constexpr uint64_t PL_L2 = prod(0, 0, 0, 0) | prod(1, 0, 1, 1) | prod(2, 1, 0, 1) | prod(3, 1, 1, 2);

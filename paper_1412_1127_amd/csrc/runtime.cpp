@@ -279,7 +279,7 @@ acc_status validate_flags(uint32_t flags)
     const uint32_t k = flags & ACC_KERNEL_MASK;
     if (k > ACC_KERNEL_TILED) return fail(ACC_ERR_INVALID_ARG, "unknown kernel selector");
     const uint32_t p = flags & ACC_PREC_MASK;
-    if (p != ACC_PREC_AUTO && p != ACC_PREC_FULL6 && p != ACC_PREC_CHEAP3)
+    if (p != ACC_PREC_AUTO && p != ACC_PREC_FULL6 && p != ACC_PREC_CHEAP3 && p != ACC_PREC_FIVE)
         return fail(ACC_ERR_INVALID_ARG, "unknown precision selector");
     const uint32_t nl = (flags & ACC_LIMBS_MASK) >> ACC_LIMBS_SHIFT;
     if (nl > 4) return fail(ACC_ERR_INVALID_ARG, "limb count must be 0 (probe) or 1..4");
@@ -407,7 +407,10 @@ int size_class(int64_t len)
 // Variant of the kernel a tile choice applies to: float products or int limbs.
 int tune_variant(int t, uint32_t flags, int limbs)
 {
-    if (t == ACC_FLOAT32) return (flags & ACC_PREC_MASK) == ACC_PREC_CHEAP3 ? 3 : 6;
+    if (t == ACC_FLOAT32) {
+        const uint32_t p = flags & ACC_PREC_MASK;
+        return p == ACC_PREC_CHEAP3 ? 3 : p == ACC_PREC_FIVE ? 5 : 6;
+    }
     return limbs;
 }
 
@@ -474,7 +477,7 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
         if (e == hipSuccess) e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, -3, true, tile, s, rec);
         return check_launch(e, "gemm (bf16x3, probed) launch");
     }
-    const int products = (prec == ACC_PREC_CHEAP3) ? 3 : 6;
+    const int products = (prec == ACC_PREC_CHEAP3) ? 3 : (prec == ACC_PREC_FIVE) ? 5 : 6;
     e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, products, false, resolve_tile(ACC_FLOAT32, sh, flags, 0), s, nullptr,
                                  sk);
     return check_launch(e, "gemm (bf16x3) launch");

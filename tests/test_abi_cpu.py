@@ -65,7 +65,7 @@ def test_no_device_no_fallback():
 def test_argument_validation_without_device():
     import paper_1412_1127_amd as ax
     for bad in [(ax.ACC_FLOAT32, 0, 0), (ax.ACC_FLOAT32, 65537, 0), (7, 16, 0),
-                (ax.ACC_FLOAT32, 16, 0x4), (ax.ACC_FLOAT32, 16, 0x30), (ax.ACC_INT32, 16, ax.ACC_LIMBS(5))]:
+                (ax.ACC_FLOAT32, 16, 0x4), (ax.ACC_FLOAT32, 16, 0x40), (ax.ACC_INT32, 16, ax.ACC_LIMBS(5))]:
         with pytest.raises(ax.AccxError) as e:
             ax.accx_matmul_workspace_size(*bad)
         assert e.value.status == ax.ACC_ERR_INVALID_ARG, bad

@@ -57,13 +57,28 @@ def test_f32_cheap3_error_is_bf16_scale(ax, n):
     assert err <= 2.0 ** -12
 
 
-@pytest.mark.parametrize("prec", ["FULL6", "CHEAP3"])
+@pytest.mark.parametrize("n", [33, 256, 1000])
+def test_f32_five_products(ax, n):
+    # FULL6 without mid*mid: within the float32 bound, and between FULL6 and
+    # CHEAP3 in error (the dropped term is second order: |mid*mid| <= 2^-16 |a||b|)
+    a = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_A)
+    b = synth.uniform_pm1_f32((n, n), SEED, synth.STREAM_B)
+    ref = oracle.matmul_f32(a, b)
+    e5 = rel_fro(_run(ax, a, b, _tiled(ax, ax.ACC_PREC_FIVE)), ref)
+    e6 = rel_fro(_run(ax, a, b, _tiled(ax, ax.ACC_PREC_FULL6)), ref)
+    e3 = rel_fro(_run(ax, a, b, _tiled(ax, ax.ACC_PREC_CHEAP3)), ref)
+    print("LEN=%d FULL6 %.3g FIVE %.3g CHEAP3 %.3g" % (n, e6, e5, e3))
+    assert e5 <= FP32_REL_FRO_TOL
+    assert e6 <= e5 <= e3
+
+
+@pytest.mark.parametrize("prec", ["FULL6", "FIVE", "CHEAP3"])
 def test_identity_ones_exact(ax, prec):
     p = getattr(ax, "ACC_PREC_" + prec)
     n = 160
     a = synth.uniform_pm1_f32((n, n), SEED, 5)
     eye = np.eye(n, dtype=np.float32)
-    if prec == "FULL6":   # hi + mid + lo == a exactly, and 1 * term is exact
+    if prec in ("FULL6", "FIVE"):   # hi + mid + lo == a exactly, and 1 * term is exact
         assert np.array_equal(_run(ax, eye, a, _tiled(ax, p)), a)
         assert np.array_equal(_run(ax, a, eye, _tiled(ax, p)), a)
     one = np.ones((n, n), np.float32)
