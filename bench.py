@@ -105,7 +105,9 @@ def run_scale(args) -> int:
     seed = synth.DEFAULT_SEED
     prec = {"full6": ax.ACC_PREC_FULL6, "five": ax.ACC_PREC_FIVE, "auto": ax.ACC_PREC_AUTO,
             "cheap3": ax.ACC_PREC_CHEAP3}[args.prec]
-    nprod = {"full6": 6, "five": 5, "auto": 6, "cheap3": 3}[args.prec]
+    # matrix products per launch of the kernel named gemm_bf16x3 (with AUTO:
+    # the cheap pass; its correction pass is gemm_bf16x3_corr)
+    nprod = {"full6": 6, "five": 5, "auto": 3, "cheap3": 3}[args.prec]
 
     t_gen = time.time()
     a = synth.uniform_pm1_f32((n, n), seed, synth.STREAM_A)
@@ -210,11 +212,12 @@ def run_scale(args) -> int:
                 "flops_per_launch": g_flops, "avg_ms": g_ms}
 
     components = {}
-    f32_total = sum(v[1] for k, v in ktimes.items() if "bf16x3" in k) / args.steps
+    f32_total = sum(v[1] for k, v in ktimes.items() if "bf16x3" in k or k == "probe_f64") / args.steps
     components["f32_matmul"] = {"kernels_ms_per_step": f32_total, "gemm_ms": g_ms,
                                 "tflops_fp32_equiv_gemm": 2.0 * n ** 3 / (g_ms * 1e-3) / 1e12 if g_ms else None,
                                 "tflops_fp32_equiv_with_pack": 2.0 * n ** 3 / (f32_total * 1e-3) / 1e12,
-                                "products": nprod}
+                                "products": nprod,
+                                "probe_ms": kavg("probe_f64"), "correction_ms": kavg("gemm_bf16x3_corr")}
     i_total = sum(v[1] for k, v in ktimes.items() if k in ("gemm_i8", "pack_i8")) / args.steps
     components["i32_matmul"] = {"kernels_ms_per_step": i_total, "gemm_ms": gi_ms,
                                 "tops_int32_equiv_gemm": 2.0 * n ** 3 / (gi_ms * 1e-3) / 1e12 if gi_ms else None,

@@ -439,21 +439,22 @@ ACCX_API acc_status accx_server_destroy(accx_server s);
 
 /* ---- float64 error probe (ACC_PREC_AUTO) ----------------------------------
  * With ACC_PREC_AUTO the float32 tiled matmul runs the three-product split
- * first, then, per output tile of the tile configuration in use, computes 16
- * sampled entries (4 rows x 4 columns of the tile, one hashed position in
- * each quarter) as float64 dot products of the float32 inputs, compares them
+ * first, then, per output tile of the tile configuration in use, computes 64
+ * sampled entries (8 rows x 8 columns of the tile, one hashed position in
+ * each eighth) as float64 dot products of the float32 inputs, compares them
  * with the cheap result and marks the tile when the sampled relative
  * Frobenius error exceeds 5e-6 (half the 1e-5 bound; the environment variable
- * ACCX_PROBE_TAU overrides it); a correction pass then adds the three missing
- * products (hi*lo, lo*hi, mid*mid) to the marked tiles only.  One record per
- * tile is left in the workspace (row-major tile order) for inspection: */
+ * ACCX_PROBE_TAU overrides it); a correction pass on 64 x 64 tiles then adds
+ * the three missing products (hi*lo, lo*hi, mid*mid) inside the marked tiles
+ * only.  One record per tile is left in the workspace (row-major tile order)
+ * for inspection: */
 typedef struct {
-    int32_t rows[4], cols[4]; /* sampled rows and columns */
-    double ref[16];           /* float64 dot product at (rows[u], cols[v]) in ref[4*u+v] */
+    int32_t rows[8], cols[8]; /* sampled rows and columns */
+    double ref[64];           /* float64 dot product at (rows[u], cols[v]) in ref[8*u+v] */
     double err2, ref2;        /* sums over the samples of (C_cheap - ref)^2 and ref^2 */
     int32_t corrected;        /* 1: the tile received the correction products */
     int32_t pad[3];
-} accx_probe_record;          /* 192 bytes */
+} accx_probe_record;          /* 608 bytes */
 /* Byte offset of the records inside the workspace of accx_matmul_dev and
  * their count, for a float32 tiled call with (len, flags), flags carrying
  * ACC_PREC_AUTO.  Errors: INVALID_ARG. */

@@ -79,7 +79,7 @@ class accx_kernel_time(ctypes.Structure):
 
 
 class accx_probe_record(ctypes.Structure):
-    _fields_ = [("rows", ctypes.c_int32 * 4), ("cols", ctypes.c_int32 * 4), ("ref", ctypes.c_double * 16),
+    _fields_ = [("rows", ctypes.c_int32 * 8), ("cols", ctypes.c_int32 * 8), ("ref", ctypes.c_double * 64),
                 ("err2", ctypes.c_double), ("ref2", ctypes.c_double), ("corrected", ctypes.c_int32),
                 ("pad", ctypes.c_int32 * 3)]
 

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, 
 
 
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          bool LA>
+          int LAM>
 __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 {
     __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPROD, PL>()];
@@ -251,7 +251,9 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
     const int T = g.tiles_m * g.tiles_n;
     const int t = (int)(blockIdx.x % (unsigned)T);  // split K: part blockIdx.x / T of tile t
     tile_of(t, g.tiles_m, g.tiles_n, tm, tn);
-    if (g.probe && !g.probe[tm * g.tiles_n + tn].corrected) return;  // whole workgroup: uniform
+    // probe records are per tile of the probed pass, which may be larger
+    if (g.probe && !g.probe[(tm >> g.probe_shm) * g.probe_tiles_n + (tn >> g.probe_shn)].corrected)
+        return;                                                          // whole workgroup: uniform
     if (g.decide && !limb_gate(g.decide, g.expect)) return;             // the whole grid: uniform
     if (g.ksplit > 1) {
         GemmArgs h = g;
@@ -262,9 +264,9 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
         const int64_t off = kb0 * (int64_t)P * PLANE_BYTES;
         h.A = g.A + off;
         h.B = g.B + off;
-        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LA>(h, tm, tn, lds);
+        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM>(h, tm, tn, lds);
     } else {
-        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LA>(g, tm, tn, lds);
+        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM>(g, tm, tn, lds);
     }
 }
 
@@ -285,8 +287,9 @@ __device__ inline float packed_bf16(const char *base, int64_t nkb, int p, int64_
 }
 
 // The 8 float32 values of elements k8..k8+7 (k8 a multiple of 8) of operand
-// row r, rebuilt exactly in float64 as hi + mid + lo from the three planes.
-__device__ inline void load_exact8(const char *base, int64_t nkb, int64_t r, int64_t k8, double out[8])
+// row r, rebuilt from the three planes: hi + mid + lo of a float32 x is x
+// itself (the terms do not overlap, so the two float32 additions are exact).
+__device__ inline void load_exact8(const char *base, int64_t nkb, int64_t r, int64_t k8, float out[8])
 {
     const int64_t unit = (r >> 5) * nkb + (k8 >> 5);
     const char *c = base + unit * (3 * PLANE_BYTES) + ((k8 & 31) >> 3) * 512 + (r & 31) * 16;
@@ -295,61 +298,64 @@ __device__ inline void load_exact8(const char *base, int64_t nkb, int64_t r, int
     const u16x8 l = *reinterpret_cast<const u16x8 *>(c + 2 * PLANE_BYTES);
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-        out[e] = ((double)__uint_as_float((uint32_t)h[e] << 16) + (double)__uint_as_float((uint32_t)m[e] << 16)) +
-                 (double)__uint_as_float((uint32_t)l[e] << 16);
+        out[e] = (__uint_as_float((uint32_t)h[e] << 16) + __uint_as_float((uint32_t)m[e] << 16)) +
+                 __uint_as_float((uint32_t)l[e] << 16);
 }
+
+constexpr int PS = PROBE_SIDE;  // sampled rows (and columns) per tile
 
 __device__ inline int probe_pick(int64_t tile, int k, int extent)
 {
-    // k-th quarter of [0, extent), a hashed position inside it
-    const int q = (extent + 3) / 4;
-    const int v = k * q + (int)(hash32((uint32_t)(tile * 8 + k) * 2654435761u + 977u) % (uint32_t)q);
+    // k-th of PS equal parts of [0, extent), a hashed position inside it
+    const int q = (extent + PS - 1) / PS;
+    const int v = (k % PS) * q +
+                  (int)(hash32((uint32_t)(tile * (2 * PS) + k) * 2654435761u + 977u) % (uint32_t)q);
     return v < extent ? v : extent - 1;
 }
 
-// One workgroup per output tile of the correction GEMM.  It takes 4 rows and
-// 4 columns of the tile (one hashed position in each quarter), computes the
-// 16 dot products in float64 from the exact operands (hi + mid + lo of every
-// element, summed in float64, is the float32 input itself), compares them with
-// the cheap result C, and marks the tile for correction when the sampled
-// relative Frobenius error exceeds tau (or the samples are all zero but C is
-// not).
+// One workgroup per output tile of the cheap pass.  It takes PS rows and PS
+// columns of the tile (one hashed position in each of PS equal parts),
+// computes the PS x PS dot products in float64 from the exact operands (each
+// float32 x float32 product is exact in float64), compares them with the
+// cheap result C, and marks the tile for correction when the sampled relative
+// Frobenius error exceeds tau (or the samples are all zero but C is not).
 __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, const char *__restrict__ pb,
                                                  const float *__restrict__ C, GemmShape sh, int bm, int bn,
                                                  int tiles_n, int64_t nkb, double tau2, ProbeRecord *__restrict__ rec)
 {
-    __shared__ double part[4][16];
+    __shared__ double part[4][PS * PS];
     const int64_t tile = blockIdx.x;
     const int tm = (int)(tile / tiles_n), tn = (int)(tile % tiles_n);
     const int64_t row0 = (int64_t)tm * bm, col0 = (int64_t)tn * bn;
     const int rext = (int)min<int64_t>(bm, sh.m - row0), cext = (int)min<int64_t>(bn, sh.n - col0);
-    int64_t rows[4], cols[4];
+    int64_t rows[PS], cols[PS];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < PS; ++k) {
         rows[k] = row0 + probe_pick(tile, k, rext);
-        cols[k] = col0 + probe_pick(tile, 4 + k, cext);
+        cols[k] = col0 + probe_pick(tile, PS + k, cext);
     }
-    double acc[16];
+    double acc[PS * PS];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int q = 0; q < PS * PS; ++q) acc[q] = 0.0;
     // one 16-byte chunk (8 consecutive k) per plane and vector per step;
     // elements past k are zero in the packed operands
     for (int64_t k8 = (int64_t)threadIdx.x * 8; k8 < sh.k; k8 += 256 * 8) {
-        double av[4][8], bv[4][8];
+        float bv[PS][8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            load_exact8(pa, nkb, rows[u], k8, av[u]);
-            load_exact8(pb, nkb, cols[u], k8, bv[u]);
+        for (int v = 0; v < PS; ++v) load_exact8(pb, nkb, cols[v], k8, bv[v]);
+#pragma unroll
+        for (int u = 0; u < PS; ++u) {
+            float av[8];
+            load_exact8(pa, nkb, rows[u], k8, av);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+#pragma unroll
+                for (int v = 0; v < PS; ++v)
+                    acc[u * PS + v] = __builtin_fma((double)av[e], (double)bv[v][e], acc[u * PS + v]);
         }
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u * 4 + v] = __builtin_fma(av[u][e], bv[v][e], acc[u * 4 + v]);
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < PS * PS; ++q) {
         double v = acc[q];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -357,18 +363,17 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        ProbeRecord r;
+        ProbeRecord &r = rec[tile];
         double e2 = 0.0, r2 = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < PS * PS; ++q) {
             const double ref = (part[0][q] + part[1][q]) + (part[2][q] + part[3][q]);
-            const double c = (double)C[rows[q / 4] * sh.ldc + cols[q % 4]];
+            const double c = (double)C[rows[q / PS] * sh.ldc + cols[q % PS]];
             r.ref[q] = ref;
             e2 += (c - ref) * (c - ref);
             r2 += ref * ref;
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < PS; ++k) {
             r.rows[k] = (int32_t)rows[k];
             r.cols[k] = (int32_t)cols[k];
         }
@@ -376,7 +381,6 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
         r.ref2 = r2;
         r.corrected = (r2 > 0.0) ? (e2 > tau2 * r2) : (e2 > 0.0);
         r.pad[0] = r.pad[1] = r.pad[2] = 0;
-        rec[tile] = r;
     }
 }
 
@@ -387,13 +391,13 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
 //           two workgroups per CU that do not share barriers.
 //  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3).
 //  T64       64 x 64,  4 waves (2x2), 64 B, 2 stages (several int8 planes).
-//  T256W4   256 x 256, 4 waves (2x2, 128 x 128 each), 32 B / 64 B, 3 / 4
-//           stages, look-ahead loop: a third less LDS read traffic per matrix
-//           instruction than T256, one wavefront per SIMD, accumulators in
-//           AGPRs, fragments of the next step read during this step's
-//           matrix instructions.
+//  T256W4   256 x 256, 4 waves (2x2, 128 x 128 each), 32 B / 64 B, 3
+//           stages: a third less LDS read traffic per matrix instruction
+//           than T256, one wavefront per SIMD, accumulators in AGPRs; for
+//           bf16x3 a look-ahead loop (fragments of the next step read during
+//           this step's matrix instructions).
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          bool LA = false>
+          int LAM = 0>
 hipError_t launch_tile(GemmArgs g, hipStream_t s)
 {
     g.tiles_m = (int)((g.M + BM - 1) / BM);
@@ -406,7 +410,7 @@ hipError_t launch_tile(GemmArgs g, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     const dim3 grid((unsigned)(g.tiles_m * g.tiles_n * (g.ksplit > 1 ? g.ksplit : 1)));
-    hipLaunchKernelGGL((gemm_packed<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LA>), grid,
+    hipLaunchKernelGGL((gemm_packed<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM>), grid,
                        dim3(WGM * WGN * 64), 0, s, g);
     return hipGetLastError();
 }
@@ -423,8 +427,10 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, multi ? 2 : 4, multi ? 2 : 3, NPROD, PL,
                            NACC>(g, s);
     case GEMM_TILE_256W4:
-        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, 2, multi ? 2 : (INT8 ? 4 : 3), NPROD, PL,
-                           NACC, !multi>(g, s);
+        // look-ahead for bf16x3 only: the int8 tile (two K sub-steps per
+        // stage) would need more registers than a wavefront has
+        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, 2, multi ? 2 : 3, NPROD, PL, NACC,
+                           INT8 ? 0 : 1>(g, s);
     case GEMM_TILE_256x128:
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 128, KS, 2, 2, 2, NPROD, PL, NACC>(g, s);
     case GEMM_TILE_128:
@@ -590,8 +596,16 @@ void set_split(GemmArgs &g, const SplitK &sk, int64_t tiles_bytes_offset)
     }
 }
 
+int log2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const GemmShape &sh, int products,
-                              bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe, const SplitK &sk)
+                              bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe, const SplitK &sk,
+                              int probe_tile)
 {
     if (sh.m <= 0 || sh.n <= 0) return hipSuccess;
     GemmArgs g{};
@@ -607,13 +621,24 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
     g.accumulate = accumulate ? 1 : 0;
     g.probe = probe;
     const int t = tile ? tile : default_tile(sh.m, sh.n);
+    if (probe) {
+        // the records' tiles (probe_tile) contain whole tiles of this launch
+        int bm, bn, pbm, pbn;
+        tile_dims(t, sh.m, sh.n, bm, bn);
+        tile_dims(probe_tile ? probe_tile : t, sh.m, sh.n, pbm, pbn);
+        if (pbm % bm || pbn % bn) return hipErrorInvalidValue;
+        g.probe_shm = log2i(pbm / bm);
+        g.probe_shn = log2i(pbn / bn);
+        g.probe_tiles_n = (int)cdiv(sh.n, pbn);
+    }
     if (sk.parts > 1) {
         int bm, bn;
         tile_dims(t, sh.m, sh.n, bm, bn);
         set_split(g, sk, (256 + 4 * cdiv(sh.m, bm) * cdiv(sh.n, bn) + 255) / 256 * 256);
     }
     hipError_t e;
-    tmark("gemm_bf16x3", s, true);
+    const char *tname = accumulate ? "gemm_bf16x3_corr" : "gemm_bf16x3";
+    tmark(tname, s, true);
     if (products == 6)
         e = run_gemm<false, 3, 6, PL_FULL6, 1>(t, g, s);
     else if (products == 5)
@@ -624,7 +649,7 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
         e = run_gemm<false, 3, 3, PL_CORR3, 1>(t, g, s);
     else
         e = hipErrorInvalidValue;
-    tmark("gemm_bf16x3", s, false);
+    tmark(tname, s, false);
     return e;
 }
 

@@ -73,14 +73,15 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld,
 enum { GEMM_TILE_DEFAULT = 0, GEMM_TILE_256 = 1, GEMM_TILE_256x128 = 2, GEMM_TILE_128 = 3, GEMM_TILE_64 = 4,
        GEMM_TILE_256W4 = 5, GEMM_TILE_COUNT = 6 };
 // Per-tile record of the float64 error probe (layout documented in accx.h).
+constexpr int PROBE_SIDE = 8;  // sampled rows and columns per tile
 struct ProbeRecord {
-    int32_t rows[4], cols[4];  // sampled rows and columns of the tile
-    double ref[16];            // float64 dot products, ref[4*u + v] at (rows[u], cols[v])
-    double err2, ref2;         // sum over the samples of (C - ref)^2 and of ref^2
-    int32_t corrected;         // 1 if the tile got the three correction products
+    int32_t rows[PROBE_SIDE], cols[PROBE_SIDE];  // sampled rows and columns of the tile
+    double ref[PROBE_SIDE * PROBE_SIDE];         // float64 dot products, ref[8*u + v] at (rows[u], cols[v])
+    double err2, ref2;                           // sum over the samples of (C - ref)^2 and of ref^2
+    int32_t corrected;                           // 1 if the tile got the three correction products
     int32_t pad[3];
 };
-static_assert(sizeof(ProbeRecord) == 192, "probe record layout");
+static_assert(sizeof(ProbeRecord) == 608, "probe record layout");
 
 // Split K (short-and-wide results that leave CUs idle): the K loop of each
 // output tile runs in `parts` workgroups whose partial sums are added in
@@ -97,9 +98,11 @@ int split_k_parts(int tile, int64_t m, int64_t n, int64_t nkb);
 size_t split_k_bytes(int tile, int64_t m, int64_t n, int parts);
 
 // probe: non-null = skip the tiles whose record has corrected == 0.
+// probe_tile: the tile configuration the records were made for (0 = `tile`);
+// its tiles must contain whole tiles of this launch.
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const GemmShape &sh, int products,
                               bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe = nullptr,
-                              const SplitK &sk = SplitK());
+                              const SplitK &sk = SplitK(), int probe_tile = 0);
 // Float64 probe of C per output tile of `tile`; tau: relative Frobenius
 // threshold above which a tile is marked for correction.
 hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, const GemmShape &sh, int tile, double tau,

@@ -177,6 +177,8 @@ struct GemmArgs {
     int tiles_m, tiles_n;
     int accumulate;  // float: C += result instead of C = result
     const ProbeRecord *probe;  // non-null: skip tiles whose record says no correction
+    int probe_shm, probe_shn;  // log2 of (probed tile) / (this tile), rows and columns
+    int probe_tiles_n;         // probed tiles per row of C
     const uint32_t *decide;    // non-null: run only if limb_gate(decide, expect)
     int expect;
     // Split K: ksplit > 1 cuts the K range into ksplit parts (kb_count units
@@ -263,7 +265,7 @@ constexpr int gemm_lds_bytes()
 // wavefront per SIMD.  It costs a second fragment register set and one step
 // of global-load lead (needs NS >= 3).
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          bool LA = false>
+          int LAM = 0>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &g, int tm, int tn, char *lds)
 {
     using M = Mma<INT8>;
@@ -284,7 +286,9 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     static_assert(KBK == 32 || KBK == 64, "K step is 32 or 64 bytes");
     static_assert(NCOPY % WAVES == 0, "loads must divide evenly over the wavefronts");
     static_assert(NS >= 2 && LPW * (NS - 2) < 64, "vmcnt range");
-    static_assert(!LA || NS >= 3, "look-ahead needs three stages");
+    static_assert(LAM == 0 || NS >= 3, "look-ahead needs three stages");
+    static_assert(LAM != 2 || (SUB == 1 && NPROD >= 1 && prod_p(PL, 0) == 0 && prod_q(PL, 0) == 0),
+                  "plane-0 look-ahead: one matrix step per stage, first product hi*hi");
     static_assert(NS * STAGE <= 160 * 1024, "LDS");
     static_assert(NPL <= P, "product list names a plane the operand lacks");
 
@@ -334,7 +338,83 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     for (int s = 0; s < NS - 1; ++s)
         if (s < nsteps) issue(s);
 
-    if constexpr (LA) {
+    if constexpr (LAM == 2) {
+        // Plane-0 look-ahead (for tiles whose registers cannot hold two full
+        // fragment sets): each iteration waits for the NEXT stage and reads
+        // only its plane-0 fragments ahead; the current stage's other planes
+        // are read at the start of the iteration, behind the matrix
+        // instructions of the first product (plane 0 x plane 0), which need
+        // only the fragments read one iteration earlier.
+        struct P0 {
+            Frag a[WBM], b[WBN];
+        };
+        const int off = (lane >> 5) * 512 + (lane & 31) * 16;
+        auto load_p0 = [&](int step, P0 &F) {
+            const char *sA = lds + (step % NS) * STAGE;
+            const char *sB = sA + MB * LUNIT;
+#pragma unroll
+            for (int i = 0; i < WBM; ++i)
+                F.a[i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + off);
+#pragma unroll
+            for (int j = 0; j < WBN; ++j)
+                F.b[j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + off);
+        };
+        auto pla_step = [&](int step, const P0 &cur, P0 &next) {
+            if (step + 1 < nsteps) {
+                if (step + NS - 2 <= nsteps - 1)
+                    __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 3)>());
+                else
+                    __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_barrier();
+                asm volatile("" ::: "memory");
+                if (step + NS - 1 < nsteps) issue(step + NS - 1);
+            }
+            // planes 1.. of this stage (intact until the next iteration's refill)
+            const char *sA = lds + (step % NS) * STAGE;
+            const char *sB = sA + MB * LUNIT;
+            Frag fa[NPL][WBM], fb[NPL][WBN];
+#pragma unroll
+            for (int i = 0; i < WBM; ++i) fa[0][i] = cur.a[i];
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) fb[0][j] = cur.b[j];
+#pragma unroll
+            for (int p = 1; p < NPL; ++p) {
+#pragma unroll
+                for (int i = 0; i < WBM; ++i)
+                    fa[p][i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + p * 32 * KBK + off);
+#pragma unroll
+                for (int j = 0; j < WBN; ++j)
+                    fb[p][j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + p * 32 * KBK + off);
+            }
+            if (step + 1 < nsteps) load_p0(step + 1, next);
+#pragma unroll
+            for (int t = 0; t < NPROD; ++t)
+#pragma unroll
+                for (int i = 0; i < WBM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WBN; ++j)
+                        acc[prod_acc(PL, t)][i][j] =
+                            M::run(fa[prod_p(PL, t)][i], fb[prod_q(PL, t)][j], acc[prod_acc(PL, t)][i][j]);
+        };
+        if (nsteps > 0) {
+            if (NS - 2 <= nsteps - 1)
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 2)>());
+            else
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            P0 F0, F1;
+            load_p0(0, F0);
+            int step = 0;
+            for (; step + 1 < nsteps; step += 2) {
+                pla_step(step, F0, F1);
+                pla_step(step + 1, F1, F0);
+            }
+            if (step < nsteps) pla_step(step, F0, F1);
+        }
+    } else if constexpr (LAM == 1) {
         struct FragSet {
             Frag a[SUB][NPL][WBM], b[SUB][NPL][WBN];
         };

@@ -474,7 +474,10 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
         auto *rec = reinterpret_cast<accx::ProbeRecord *>(work + probe_offset(sh));
         e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, 3, false, tile, s, nullptr, sk);
         if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, sh, tile, probe_tau(), rec, s);
-        if (e == hipSuccess) e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, -3, true, tile, s, rec);
+        // the correction runs on 64 x 64 tiles, so a marked tile costs its
+        // share of the work, not a whole pass of the big tile
+        if (e == hipSuccess)
+            e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, -3, true, accx::GEMM_TILE_64, s, rec, accx::SplitK(), tile);
         return check_launch(e, "gemm (bf16x3, probed) launch");
     }
     const int products = (prec == ACC_PREC_CHEAP3) ? 3 : (prec == ACC_PREC_FIVE) ? 5 : 6;

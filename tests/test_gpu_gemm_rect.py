@@ -213,7 +213,10 @@ def test_probe_records_on_rectangular_shape(ax):
     ax.accx_gemm_dev(ax.ACC_FLOAT32, m, n, k, da, k, db, n, dc, n, fl, work, ws)
     torch.cuda.synchronize()
     assert rel_fro(dc.cpu().numpy(), oracle.gemm(a, b)) <= FP32_REL_FRO_TOL
-    recs = ax.probe_records(work[off:off + cnt * 192].cpu().numpy().tobytes(), cnt)
+    import ctypes
+    size = ctypes.sizeof(ax.accx_probe_record)
+    assert size == 608
+    recs = ax.probe_records(work[off:off + cnt * size].cpu().numpy().tobytes(), cnt)
     assert len(recs) == cnt > 0
     ref = oracle.gemm(a, b)
     for r in recs:
