@@ -48,9 +48,33 @@ __global__ __launch_bounds__(256) void pack_bf16x3(const float *__restrict__ X, 
 }
 
 
+// Record a workgroup's max |x| (256 threads, each holding its own max) in
+// *maxabs, which starts at zero.  Only maxima above 127 are recorded: the
+// digit count depends on max |x| only through thresholds from 127 up, so the
+// word ends as the operand's max |x| when that exceeds 127 and stays zero
+// otherwise.  One atomic per workgroup at most, and none on one-digit data
+// (a single contended address serialises every atomic on it).
+__device__ inline void block_max_record(uint32_t mx, uint32_t *maxabs)
+{
+    __shared__ uint32_t wmax[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = __shfl_xor(mx, o, 64);
+        mx = t > mx ? t : mx;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = wmax[0];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+        if (m > 127u && m > __hip_atomic_load(maxabs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxabs, m);
+    }
+}
+
 // int32 -> P balanced base-256 digit planes (int8), 16 K elements per thread.
 // Element addressing as for the bf16x3 pack (leading dimension ld).
-// maxabs (optional): running max of |x| over the operand, as uint32.
+// maxabs (optional): max |x| over the operand as block_max_record leaves it.
 // decide (optional): the two max|x| words of a finished probe pass; the
 // kernel then packs only if limb_gate(decide, expect) holds.
 template <bool TRANS>
@@ -110,17 +134,7 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
             *reinterpret_cast<i32x4 *>(u + (int64_t)p * PLANE_BYTES) = word;
         }
     }
-    if (maxabs) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint32_t t = __shfl_xor(mx, o, 64);
-            mx = t > mx ? t : mx;
-        }
-        // Most wavefronts find the running maximum already as large: skip
-        // the atomic then (one contended address otherwise serialises).
-        if ((threadIdx.x & 63) == 0 && mx > __hip_atomic_load(maxabs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(maxabs, mx);
-    }
+    if (maxabs) block_max_record(mx, maxabs);
 }
 
 
@@ -230,15 +244,7 @@ __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, 
             *reinterpret_cast<i32x4 *>(o + (int64_t)p * PLANE_BYTES) = word;
         }
     }
-    if (maxabs) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint32_t v = __shfl_xor(mx, o, 64);
-            mx = v > mx ? v : mx;
-        }
-        if ((threadIdx.x & 63) == 0 && mx > __hip_atomic_load(maxabs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(maxabs, mx);
-    }
+    if (maxabs) block_max_record(mx, maxabs);
 }
 
 
@@ -424,8 +430,10 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
     if (multi) tile = GEMM_TILE_64;
     switch (tile) {
     case GEMM_TILE_256:
+        // first-product look-ahead for bf16x3 (two wavefronts per SIMD leave
+        // no registers for a second full fragment set)
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, multi ? 2 : 4, multi ? 2 : 3, NPROD, PL,
-                           NACC>(g, s);
+                           NACC, INT8 ? 0 : 2>(g, s);
     case GEMM_TILE_256W4:
         // look-ahead for bf16x3 only: the int8 tile (two K sub-steps per
         // stage) would need more registers than a wavefront has

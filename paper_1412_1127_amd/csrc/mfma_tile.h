@@ -193,7 +193,9 @@ struct GemmArgs {
 
 // Digits the int8 path needs for two operands with the given max |x| words:
 // the fewest balanced base-256 digits that hold every value exactly (four
-// hold any int32 modulo 2^32).
+// hold any int32 modulo 2^32).  A word may read zero for any max |x| up to
+// 127 (the pack records only larger maxima): the answer is one digit either
+// way.
 __device__ inline int limbs_needed(const uint32_t *maxabs2)
 {
     const uint32_t m = maxabs2[0] > maxabs2[1] ? maxabs2[0] : maxabs2[1];
@@ -287,8 +289,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     static_assert(NCOPY % WAVES == 0, "loads must divide evenly over the wavefronts");
     static_assert(NS >= 2 && LPW * (NS - 2) < 64, "vmcnt range");
     static_assert(LAM == 0 || NS >= 3, "look-ahead needs three stages");
-    static_assert(LAM != 2 || (SUB == 1 && NPROD >= 1 && prod_p(PL, 0) == 0 && prod_q(PL, 0) == 0),
-                  "plane-0 look-ahead: one matrix step per stage, first product hi*hi");
+    static_assert(LAM != 2 || SUB == 1, "first-product look-ahead: one matrix step per stage");
     static_assert(NS * STAGE <= 160 * 1024, "LDS");
     static_assert(NPL <= P, "product list names a plane the operand lacks");
 
@@ -339,12 +340,13 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
         if (s < nsteps) issue(s);
 
     if constexpr (LAM == 2) {
-        // Plane-0 look-ahead (for tiles whose registers cannot hold two full
-        // fragment sets): each iteration waits for the NEXT stage and reads
-        // only its plane-0 fragments ahead; the current stage's other planes
-        // are read at the start of the iteration, behind the matrix
-        // instructions of the first product (plane 0 x plane 0), which need
-        // only the fragments read one iteration earlier.
+        // First-product look-ahead (for tiles whose registers cannot hold
+        // two full fragment sets): each iteration waits for the NEXT stage
+        // and reads ahead only the two planes of its first product; the
+        // current stage's other planes are read at the start of the
+        // iteration, behind the matrix instructions of that first product,
+        // which need only the fragments read one iteration earlier.
+        constexpr int PA0 = prod_p(PL, 0), PB0 = prod_q(PL, 0);
         struct P0 {
             Frag a[WBM], b[WBN];
         };
@@ -354,10 +356,10 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
             const char *sB = sA + MB * LUNIT;
 #pragma unroll
             for (int i = 0; i < WBM; ++i)
-                F.a[i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + off);
+                F.a[i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + PA0 * 32 * KBK + off);
 #pragma unroll
             for (int j = 0; j < WBN; ++j)
-                F.b[j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + off);
+                F.b[j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + PB0 * 32 * KBK + off);
         };
         auto pla_step = [&](int step, const P0 &cur, P0 &next) {
             if (step + 1 < nsteps) {
@@ -370,22 +372,27 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
                 asm volatile("" ::: "memory");
                 if (step + NS - 1 < nsteps) issue(step + NS - 1);
             }
-            // planes 1.. of this stage (intact until the next iteration's refill)
+            // the other planes of this stage (intact until the next
+            // iteration's refill)
             const char *sA = lds + (step % NS) * STAGE;
             const char *sB = sA + MB * LUNIT;
             Frag fa[NPL][WBM], fb[NPL][WBN];
 #pragma unroll
-            for (int i = 0; i < WBM; ++i) fa[0][i] = cur.a[i];
+            for (int i = 0; i < WBM; ++i) fa[PA0][i] = cur.a[i];
 #pragma unroll
-            for (int j = 0; j < WBN; ++j) fb[0][j] = cur.b[j];
+            for (int j = 0; j < WBN; ++j) fb[PB0][j] = cur.b[j];
 #pragma unroll
-            for (int p = 1; p < NPL; ++p) {
+            for (int p = 0; p < NPL; ++p) {
+                if (p != PA0) {
 #pragma unroll
-                for (int i = 0; i < WBM; ++i)
-                    fa[p][i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + p * 32 * KBK + off);
+                    for (int i = 0; i < WBM; ++i)
+                        fa[p][i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + p * 32 * KBK + off);
+                }
+                if (p != PB0) {
 #pragma unroll
-                for (int j = 0; j < WBN; ++j)
-                    fb[p][j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + p * 32 * KBK + off);
+                    for (int j = 0; j < WBN; ++j)
+                        fb[p][j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + p * 32 * KBK + off);
+                }
             }
             if (step + 1 < nsteps) load_p0(step + 1, next);
 #pragma unroll
