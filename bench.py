@@ -36,8 +36,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 def _args():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--len", type=int, default=4096)
     p.add_argument("--n-reduce", type=int, default=1 << 28)
     p.add_argument("--prec", choices=["full6", "five", "auto", "cheap3"], default="full6")

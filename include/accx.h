@@ -301,8 +301,9 @@ ACCX_API acc_status accx_reduce_workspace_size(acc_dtype t, int64_t n, uint32_t 
 
 /* dResult (device scalar of type t) = init + sum of dX[0..n), enqueued on
  * `hip_stream`.  `init` points to a HOST value of type t.  dWork as above
- * (NULL: library-owned per-stream workspace); a workspace passed in must be
- * zero-filled before its first use, and the kernel leaves it so.
+ * (NULL: library-owned per-stream workspace); a workspace passed in may hold
+ * anything: it receives per-workgroup partial results, which every call
+ * overwrites.  Calls that share a workspace must be ordered (one stream).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
 ACCX_API acc_status accx_reduce_sum_dev(acc_dtype t, const void *dX, int64_t n, const void *init, void *dResult,
                                uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
@@ -314,7 +315,7 @@ ACCX_API acc_status accx_reduce_vars_workspace_size(acc_dtype t, int64_t n, cons
 /* acc_reduce on device memory: dResult[v] (nvars device elements of type t)
  * = the variable's result; init: nvars HOST values of type t.  dX and
  * dResult aligned to the element size.  dWork as for accx_reduce_sum_dev
- * (zero-filled before first use, left so; NULL: library-owned per stream).
+ * (any contents; NULL: library-owned per stream).
  * accx_reduce_sum_dev is the case of one sum variable.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
 ACCX_API acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars,

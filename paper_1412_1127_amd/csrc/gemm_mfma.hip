@@ -430,10 +430,12 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
     if (multi) tile = GEMM_TILE_64;
     switch (tile) {
     case GEMM_TILE_256:
-        // first-product look-ahead for bf16x3 (two wavefronts per SIMD leave
-        // no registers for a second full fragment set)
+        // Look-ahead: full for the one-digit int8 tile (two fragment sets of
+        // 48 registers fit beside its 128 accumulator registers), first-product
+        // only for bf16x3, whose three planes leave no room for a second full
+        // set at two wavefronts per SIMD.
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, multi ? 2 : 4, multi ? 2 : 3, NPROD, PL,
-                           NACC, INT8 ? 0 : 2>(g, s);
+                           NACC, multi ? 0 : INT8 ? 1 : 2>(g, s);
     case GEMM_TILE_256W4:
         // look-ahead for bf16x3 only: the int8 tile (two K sub-steps per
         // stage) would need more registers than a wavefront has

@@ -257,7 +257,9 @@ constexpr int gemm_lds_bytes()
 }
 
 //
-// LA (look-ahead) variant: each iteration waits for the NEXT stage, reads its
+// LAM selects the main loop: 0 plain (wait, barrier, read, compute), 1 full
+// look-ahead, 2 first-product look-ahead (described at its loop below).
+// Full look-ahead: each iteration waits for the NEXT stage, reads its
 // operand fragments from LDS into a second register set and runs the matrix
 // instructions of the current stage from registers, with the LDS reads
 // spread between the matrix instructions (one read per NMFMA/NREAD of them;

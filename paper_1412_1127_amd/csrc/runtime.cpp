@@ -1182,7 +1182,7 @@ acc_status region_reduce(acc_region r, int t, const void *x, int64_t n, const ac
     const bool legacy = legacy_sum(t, vars, nvars);
     const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
     Workspace &w = !legacy ? r->red_vars_work : plain ? r->red_plain_work : r->red_work;
-    if ((s = ws_reserve(w, vars_ws_bytes(t, n, vars, nvars, flags), !plain, r->stream)) != ACC_OK) return s;
+    if ((s = ws_reserve(w, vars_ws_bytes(t, n, vars, nvars, flags), false, r->stream)) != ACC_OK) return s;
     const int slot = r->used_slots;
     r->used_slots += nvars;
     void *dslot = static_cast<char *>(r->dres) + (size_t)slot * 8;
@@ -1314,7 +1314,7 @@ acc_status dev_reduce(int t, const void *dX, int64_t n, const acc_reduce_var *va
         if (work_bytes < need) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
     } else {
         Workspace &w = !legacy ? st.red_vars_ws[stream] : plain ? st.red_plain_ws[stream] : st.red_ws[stream];
-        if ((s = ws_reserve(w, need, !plain, stream)) != ACC_OK) return s;
+        if ((s = ws_reserve(w, need, false, stream)) != ACC_OK) return s;
         dWork = w.ptr;
     }
     return run_reduce_vars(t, dX, n, vars, nvars, init, dResult, flags, dWork, stream);
