@@ -519,6 +519,12 @@ typedef struct {
 } accx_kernel_time;
 
 ACCX_API acc_status accx_timing_enable(int on);
+/* Restrict timing to the kernels named in `names` (comma-separated timing
+ * names as accx_timing_read reports them, e.g. "gemm_bf16x3"); NULL or ""
+ * times every kernel again.  Kernels not named get no event records.
+ * Errors: INVALID_ARG (called between a kernel's two event records, i.e.
+ * from another thread during a launch). */
+ACCX_API acc_status accx_timing_filter(const char *names);
 /* Fills up to `cap` entries, sets *n_out to the number of kernels seen;
  * reset != 0 clears the totals afterwards.  Errors: INVALID_ARG. */
 ACCX_API acc_status accx_timing_read(accx_kernel_time *out, int cap, int *n_out, int reset);

@@ -182,6 +182,7 @@ _SIGS = {
     "accx_tune_save": [ctypes.c_char_p],
     "accx_tune_load": [ctypes.c_char_p],
     "accx_timing_enable": [ctypes.c_int],
+    "accx_timing_filter": [ctypes.c_char_p],
     "accx_timing_read": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int],
 }
 _STRINGS = {"acc_status_string": [ctypes.c_int], "acc_last_error_string": [], "accx_version": []}
@@ -423,6 +424,12 @@ def accx_pack_dev(dtype: int, dX, rows: int, k: int, transposed: bool, planes: i
 
 def accx_timing_enable(on: bool = True) -> None:
     _check(_lib.accx_timing_enable(int(bool(on))), "accx_timing_enable")
+
+
+def accx_timing_filter(names=None) -> None:
+    """Time only the kernels in `names` (an iterable of timing names); None: all."""
+    arg = None if not names else ",".join(names).encode()
+    _check(_lib.accx_timing_filter(arg), "accx_timing_filter")
 
 
 def accx_timing_read(reset: bool = False) -> dict:

@@ -693,6 +693,7 @@ struct TimingStats {
 struct Timing {
     std::mutex mu;
     bool on = false;
+    std::vector<std::string> only;  // record only these kernels (empty: all)
     std::vector<hipEvent_t> pool;
     std::vector<TimingRec> pending;
     int open = -1;
@@ -747,6 +748,7 @@ void tmark(const char *name, hipStream_t s, bool begin)
     Timing &t = TM();
     if (!t.on || t_capturing) return;
     std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.only.empty() && std::find(t.only.begin(), t.only.end(), name) == t.only.end()) return;
     if (begin) {
         TimingRec r{name, tm_event(t), nullptr};
         if (r.start) (void)hipEventRecord(r.start, s);
@@ -770,6 +772,26 @@ acc_status accx_timing_enable(int on)
     Timing &t = TM();
     std::lock_guard<std::mutex> lk(t.mu);
     t.on = on != 0;
+    return ACC_OK;
+}
+
+acc_status accx_timing_filter(const char *names)
+{
+    Timing &t = TM();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (t.open >= 0) return fail(ACC_ERR_INVALID_ARG, "a kernel is being timed");
+    t.only.clear();
+    if (names) {
+        std::string all(names), cur;
+        for (char c : all + ",") {
+            if (c == ',') {
+                if (!cur.empty()) t.only.push_back(cur);
+                cur.clear();
+            } else {
+                cur += c;
+            }
+        }
+    }
     return ACC_OK;
 }
 
