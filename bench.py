@@ -40,7 +40,7 @@ def _args():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--len", type=int, default=4096)
     p.add_argument("--n-reduce", type=int, default=1 << 28)
-    p.add_argument("--prec", choices=["full6", "five", "auto", "cheap3"], default="full6")
+    p.add_argument("--prec", choices=["full6", "five", "auto", "cheap3"], default="auto")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=0,
                    help="rows of C the CPU baseline computes per matmul, scaled to the whole step "
@@ -59,6 +59,8 @@ def _args():
     p.add_argument("--streams", type=int, choices=[1, 2], default=1,
                    help="scale: 2 runs the int32 matmul and the reduction on a second stream, overlapped "
                         "with the float32 matmul")
+    p.add_argument("--ingest-counters", metavar="DIR", default=None,
+                   help="write the HBM traffic summary from rocprofv3 FETCH_SIZE/WRITE_SIZE runs in DIR and exit")
     p.add_argument("--time-all-kernels", action="store_true",
                    help="scale: event-time every kernel inside the timed region (default: the dominant one only)")
     p.add_argument("--copy-calib", action="store_true",
@@ -86,6 +88,75 @@ def _traffic(kernel: str, workload: str):
         return float(e["fetch_bytes"]) + float(e["write_bytes"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def ingest_counters(root: str, prec: str) -> int:
+    """Fold two rocprofv3 counter runs of this script (FETCH_SIZE under
+    root/fetch, WRITE_SIZE under root/write, csv output named after the
+    directory, both with --copy-calib and precision `prec`) into
+    TRAFFIC_FILE: per-dispatch KiB scaled by what the same counter reads for
+    the plain 1 GiB device copy, averaged over the float32 LEN=4096 GEMM's
+    dispatches.  Prints the per-kernel table as well."""
+    import collections
+    import csv
+
+    def load(kind):
+        per, names = collections.defaultdict(float), {}
+        with open(os.path.join(root, kind, kind + "_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                per[r["Dispatch_Id"]] += float(r["Counter_Value"])
+                names[r["Dispatch_Id"]] = r["Kernel_Name"]
+        return per, names
+
+    fetch, fnames = load("fetch")
+    write, wnames = load("write")
+    by = collections.defaultdict(lambda: ([], []))
+    for d, v in fetch.items():
+        by[fnames[d]][0].append(v)
+    for d, v in write.items():
+        by[wnames[d]][1].append(v)
+    copy = [k for k in by if "copyBuffer" in k and by[k][0] and by[k][1]]
+    if not copy:
+        print("no device-copy dispatch found: run both passes with --copy-calib", file=sys.stderr)
+        return 1
+    ff, wf = 1048576.0 / by[copy[0]][0][-1], 1048576.0 / by[copy[0]][1][-1]
+    print("copy calibration: FETCH_SIZE x %.4f, WRITE_SIZE x %.4f" % (ff, wf))
+    print("| kernel | FETCH_SIZE raw (KiB) | WRITE_SIZE raw (KiB) | fetched (MB, scaled) | written (MB, scaled) |")
+    print("|---|---|---|---|---|")
+    for k, (fv, wv) in by.items():
+        if fv and wv:
+            fm, wm = sum(fv) / len(fv), sum(wv) / len(wv)
+            name = k.replace("void ", "", 1).replace("accx::(anonymous namespace)::", "")
+            depth, cut = 0, len(name)
+            for i, ch in enumerate(name):                 # drop the parameter list
+                depth += (ch == "<") - (ch == ">")
+                if ch == "(" and depth == 0 and i > 0:
+                    cut = i
+                    break
+            print("| `%s` | %.0f | %.0f | %.1f | %.1f |" % (name[:cut][:100], fm, wm, fm * ff * 1.024e-3,
+                                                          wm * wf * 1.024e-3))
+    # the float32 GEMM of the run: the bf16x3 kernel with the largest fetch
+    g = sorted((k for k in by if k.startswith("void accx::(anonymous namespace)::gemm_packed<false,")
+                and by[k][0] and by[k][1]), key=lambda k: -sum(by[k][0]) / len(by[k][0]))
+    if not g:
+        print("no float32 GEMM dispatch found", file=sys.stderr)
+        return 1
+    fv, wv = by[g[0]]
+    fm, wm = sum(fv) / len(fv), sum(wv) / len(wv)
+    cur = _source_hash("gemm_mfma.hip", "mfma_tile.h")
+    try:
+        with open(TRAFFIC_FILE) as f:
+            old = json.load(f).get("gemm_bf16x3", {})
+    except (OSError, ValueError, AttributeError):
+        old = {}
+    out = {"gemm_bf16x3": {k: v for k, v in old.items() if v.get("source_hash") == cur}}  # drop stale entries
+    out["gemm_bf16x3"]["len4096_" + prec] = {
+        "fetch_bytes": fm * ff * 1024, "write_bytes": wm * wf * 1024, "fetch_kib_raw": fm, "write_kib_raw": wm,
+        "fetch_factor": ff, "write_factor": wf, "source_hash": cur, "kernel": g[0]}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+    return 0
 
 
 def _pct(v, q):
@@ -219,7 +290,7 @@ def run_scale(args) -> int:
     red_ms = kavg("reduce_fast")
     g_flops = nprod * 2.0 * n ** 3
     achieved = g_flops / (g_ms * 1e-3) / 1e12 if g_ms else None
-    workload = "len%d" % n
+    workload = "len%d_%s" % (n, args.prec)
     roofline = {"kernel": "gemm_bf16x3", "bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": (achieved / PEAK_BF16_TFLOPS) if achieved else None,
                 "traffic": _traffic("gemm_bf16x3", workload),
@@ -658,6 +729,8 @@ def run_serve(args) -> int:
 
 def main() -> int:
     args = _args()
+    if args.ingest_counters:
+        return ingest_counters(args.ingest_counters, args.prec)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: every step of this offload path runs on a single device, "

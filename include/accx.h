@@ -441,11 +441,12 @@ ACCX_API acc_status accx_server_destroy(accx_server s);
 /* ---- float64 error probe (ACC_PREC_AUTO) ----------------------------------
  * With ACC_PREC_AUTO the float32 tiled matmul runs the three-product split
  * first, then, per output tile of the tile configuration in use, computes 64
- * sampled entries (8 rows x 8 columns of the tile, one hashed position in
- * each eighth) as float64 dot products of the float32 inputs, compares them
- * with the cheap result and marks the tile when the sampled relative
- * Frobenius error exceeds 5e-6 (half the 1e-5 bound; the environment variable
- * ACCX_PROBE_TAU overrides it); a correction pass on 64 x 64 tiles then adds
+ * sampled entries (8 consecutive rows x 8 consecutive columns of the tile at
+ * a hashed, 8-aligned position) as float64 dot products of the float32
+ * inputs, compares them with the cheap result and marks the tile when the
+ * sampled relative Frobenius error exceeds 7e-6 (0.7 x the 1e-5 bound; the
+ * environment variable ACCX_PROBE_TAU overrides it); a correction pass on
+ * 64 x 64 tiles then adds
  * the three missing products (hi*lo, lo*hi, mid*mid) inside the marked tiles
  * only.  One record per tile is left in the workspace (row-major tile order)
  * for inspection: */

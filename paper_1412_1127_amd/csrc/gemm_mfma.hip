@@ -310,26 +310,34 @@ __device__ inline void load_exact8(const char *base, int64_t nkb, int64_t r, int
 
 constexpr int PS = PROBE_SIDE;  // sampled rows (and columns) per tile
 
-__device__ inline int probe_pick(int64_t tile, int k, int extent)
+// The k-th of PS consecutive positions in [0, extent), starting at a hashed
+// multiple of PS (salt 0: rows, 1: columns); clamped at a ragged edge.  PS
+// consecutive rows of a packed operand share each 128-byte line of a 16-byte
+// K chunk (rows are 16 bytes apart in a unit), so the probe reads whole
+// lines; rows spread over the tile would use 16 bytes of each.
+__device__ inline int probe_pick(int64_t tile, int k, int extent, int salt)
 {
-    // k-th of PS equal parts of [0, extent), a hashed position inside it
-    const int q = (extent + PS - 1) / PS;
-    const int v = (k % PS) * q +
-                  (int)(hash32((uint32_t)(tile * (2 * PS) + k) * 2654435761u + 977u) % (uint32_t)q);
+    const int blocks = (extent + PS - 1) / PS;
+    const int b = (int)(hash32((uint32_t)(tile * 2 + salt) * 2654435761u + 977u) % (uint32_t)blocks);
+    const int v = b * PS + k;
     return v < extent ? v : extent - 1;
 }
 
-// One workgroup per output tile of the cheap pass.  It takes PS rows and PS
-// columns of the tile (one hashed position in each of PS equal parts),
+// One workgroup per output tile of the cheap pass.  It takes PS consecutive
+// rows and PS consecutive columns of the tile (hashed block positions),
 // computes the PS x PS dot products in float64 from the exact operands (each
 // float32 x float32 product is exact in float64), compares them with the
 // cheap result C, and marks the tile for correction when the sampled relative
 // Frobenius error exceeds tau (or the samples are all zero but C is not).
-__global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, const char *__restrict__ pb,
-                                                 const float *__restrict__ C, GemmShape sh, int bm, int bn,
-                                                 int tiles_n, int64_t nkb, double tau2, ProbeRecord *__restrict__ rec)
+constexpr int PROBE_THREADS = 256;
+
+__global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restrict__ pa, const char *__restrict__ pb,
+                                                           const float *__restrict__ C, GemmShape sh, int bm, int bn,
+                                                           int tiles_n, int64_t nkb, double tau2,
+                                                           ProbeRecord *__restrict__ rec)
 {
-    __shared__ double part[4][PS * PS];
+    constexpr int NW = PROBE_THREADS / 64;
+    __shared__ double part[NW][PS * PS];
     const int64_t tile = blockIdx.x;
     const int tm = (int)(tile / tiles_n), tn = (int)(tile % tiles_n);
     const int64_t row0 = (int64_t)tm * bm, col0 = (int64_t)tn * bn;
@@ -337,15 +345,15 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
     int64_t rows[PS], cols[PS];
 #pragma unroll
     for (int k = 0; k < PS; ++k) {
-        rows[k] = row0 + probe_pick(tile, k, rext);
-        cols[k] = col0 + probe_pick(tile, PS + k, cext);
+        rows[k] = row0 + probe_pick(tile, k, rext, 0);
+        cols[k] = col0 + probe_pick(tile, k, cext, 1);
     }
     double acc[PS * PS];
 #pragma unroll
     for (int q = 0; q < PS * PS; ++q) acc[q] = 0.0;
     // one 16-byte chunk (8 consecutive k) per plane and vector per step;
     // elements past k are zero in the packed operands
-    for (int64_t k8 = (int64_t)threadIdx.x * 8; k8 < sh.k; k8 += 256 * 8) {
+    for (int64_t k8 = (int64_t)threadIdx.x * 8; k8 < sh.k; k8 += PROBE_THREADS * 8) {
         float bv[PS][8];
 #pragma unroll
         for (int v = 0; v < PS; ++v) load_exact8(pb, nkb, cols[v], k8, bv[v]);
@@ -368,31 +376,41 @@ __global__ __launch_bounds__(256) void probe_f64(const char *__restrict__ pa, co
         if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        ProbeRecord &r = rec[tile];
-        double e2 = 0.0, r2 = 0.0;
-        for (int q = 0; q < PS * PS; ++q) {
-            const double ref = (part[0][q] + part[1][q]) + (part[2][q] + part[3][q]);
-            const double c = (double)C[rows[q / PS] * sh.ldc + cols[q % PS]];
-            r.ref[q] = ref;
-            e2 += (c - ref) * (c - ref);
-            r2 += ref * ref;
-        }
+    // wavefront 0, one sample per lane: compare, then sum the squares over
+    // the wavefront (a fixed butterfly: every lane ends with the same sums)
+    static_assert(PS * PS == 64, "one sample per lane");
+    if (threadIdx.x < 64) {
+        const int q = threadIdx.x;
+        const int64_t row = row0 + probe_pick(tile, q / PS, rext, 0), col = col0 + probe_pick(tile, q % PS, cext, 1);
+        double ref = part[0][q];
 #pragma unroll
-        for (int k = 0; k < PS; ++k) {
-            r.rows[k] = (int32_t)rows[k];
-            r.cols[k] = (int32_t)cols[k];
+        for (int w = 1; w < NW; ++w) ref += part[w][q];
+        const double c = (double)C[row * sh.ldc + col];
+        ProbeRecord &r = rec[tile];
+        r.ref[q] = ref;
+        double e2 = (c - ref) * (c - ref), r2 = ref * ref;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            e2 += __shfl_xor(e2, o, 64);
+            r2 += __shfl_xor(r2, o, 64);
         }
-        r.err2 = e2;
-        r.ref2 = r2;
-        r.corrected = (r2 > 0.0) ? (e2 > tau2 * r2) : (e2 > 0.0);
-        r.pad[0] = r.pad[1] = r.pad[2] = 0;
+        if (q < PS) {
+            r.rows[q] = (int32_t)(row0 + probe_pick(tile, q, rext, 0));
+            r.cols[q] = (int32_t)(col0 + probe_pick(tile, q, cext, 1));
+        }
+        if (q == 0) {
+            r.err2 = e2;
+            r.ref2 = r2;
+            r.corrected = (r2 > 0.0) ? (e2 > tau2 * r2) : (e2 > 0.0);
+            r.pad[0] = r.pad[1] = r.pad[2] = 0;
+        }
     }
 }
 
 // Tile configurations (BM x BN, wavefront grid, K-step bytes, ring depth):
 //  T256     256 x 256, 8 waves (2x4), 32 B (bf16x3) / 64 B (int8), 3 stages:
-//           one workgroup per CU, 144 / 96 KB LDS.
+//           one workgroup per CU, 144 / 96 KB LDS; bf16x3 products that use
+//           two planes only: 64 B, 2 stages, 128 KB.
 //  T256x128 256 x 128, 4 waves (2x2), 32 B / 64 B, 2 stages: 72 / 48 KB LDS,
 //           two workgroups per CU that do not share barriers.
 //  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3).
@@ -430,6 +448,11 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
     if (multi) tile = GEMM_TILE_64;
     switch (tile) {
     case GEMM_TILE_256:
+        // Two planes (the cheap three products): 64-byte K steps in a
+        // two-stage ring (2 x 64 KB) give each barrier as many matrix
+        // instructions as the six products get from 32-byte steps.
+        if constexpr (!INT8 && planes_used(PL, NPROD) == 2)
+            return launch_tile<INT8, P, 256, 256, 64, 2, 4, 2, NPROD, PL, NACC>(g, s);
         // Look-ahead: full for the one-digit int8 tile (two fragment sets of
         // 48 registers fit beside its 128 accumulator registers), first-product
         // only for bf16x3, whose three planes leave no room for a second full
@@ -562,7 +585,7 @@ hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, cons
     const int tiles_m = (int)cdiv(sh.m, bm), tiles_n = (int)cdiv(sh.n, bn);
     if (tiles_m * tiles_n == 0) return hipSuccess;
     tmark("probe_f64", s, true);
-    hipLaunchKernelGGL(probe_f64, dim3((unsigned)(tiles_m * tiles_n)), dim3(256), 0, s, static_cast<const char *>(pa),
+    hipLaunchKernelGGL(probe_f64, dim3((unsigned)(tiles_m * tiles_n)), dim3(PROBE_THREADS), 0, s, static_cast<const char *>(pa),
                        static_cast<const char *>(pb), c, sh, bm, bn, tiles_n, cdiv(sh.k * 2, 64), tau * tau, rec);
     tmark("probe_f64", s, false);
     return hipGetLastError();

@@ -326,15 +326,20 @@ constexpr size_t kMaxabsBytes = 256;  // int path: two max|x| words, padded
 
 int flag_limbs(uint32_t flags) { return (int)((flags & ACC_LIMBS_MASK) >> ACC_LIMBS_SHIFT); }
 
-// ACC_PREC_AUTO: relative Frobenius error a tile may show on the probe's
-// samples and still keep the cheap (three-product) result: half the 1e-5
-// bound the float32 path is held to (ACCX_PROBE_TAU overrides).
+// ACC_PREC_AUTO: relative Frobenius error a tile may show on the probe's 64
+// samples and still keep the cheap (three-product) result (ACCX_PROBE_TAU
+// overrides).  7e-6 = 0.7 x the 1e-5 bound of the float32 path: a tile whose
+// true error is at the bound passes only if its sampled mean square falls
+// below 0.49 x its expectation (for 64 independent errors a chi-square tail
+// of about 1e-4), while a tile at the cheap pass's usual 4e-6 is marked only
+// if its mean square exceeds 3 x its expectation, which practically never
+// happens.
 double probe_tau()
 {
     static double tau = [] {
         const char *e = std::getenv("ACCX_PROBE_TAU");
         const double v = e ? std::atof(e) : 0.0;
-        return v > 0.0 ? v : 5e-6;
+        return v > 0.0 ? v : 7e-6;
     }();
     return tau;
 }

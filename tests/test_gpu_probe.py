@@ -9,7 +9,7 @@ import synth
 from _util import FP32_REL_FRO_TOL, SEED, rel_fro
 
 pytestmark = pytest.mark.gpu
-TAU = 5e-6
+TAU = 7e-6
 
 
 @pytest.fixture(scope="module")
