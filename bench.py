@@ -135,11 +135,19 @@ def ingest_counters(root: str, prec: str) -> int:
                     break
             print("| `%s` | %.0f | %.0f | %.1f | %.1f |" % (name[:cut][:100], fm, wm, fm * ff * 1.024e-3,
                                                           wm * wf * 1.024e-3))
-    # the float32 GEMM of the run: the bf16x3 kernel with the largest fetch
-    g = sorted((k for k in by if k.startswith("void accx::(anonymous namespace)::gemm_packed<false,")
-                and by[k][0] and by[k][1]), key=lambda k: -sum(by[k][0]) / len(by[k][0]))
-    if not g:
-        print("no float32 GEMM dispatch found", file=sys.stderr)
+    # the float32 GEMM of the run (the counter runs fix the 256 x 256 tile,
+    # so that no autotuner candidate is in them): the bf16x3 kernel of that
+    # tile with the precision's product count (template argument 9)
+    nprod = {"full6": 6, "five": 5, "auto": 3, "cheap3": 3}[prec]
+
+    def targs(k):
+        head = "void accx::(anonymous namespace)::gemm_packed<"
+        return k[len(head):k.index(">(")].split(", ") if k.startswith(head) and ">(" in k else []
+
+    g = [k for k in by if targs(k)[:4] == ["false", "3", "256", "256"] and targs(k)[8] == str(nprod)
+         and by[k][0] and by[k][1]]
+    if len(g) != 1:
+        print("expected one float32 256 x 256 GEMM with %d products, found %d" % (nprod, len(g)), file=sys.stderr)
         return 1
     fv, wv = by[g[0]]
     fm, wm = sum(fv) / len(fv), sum(wv) / len(wv)

@@ -329,59 +329,73 @@ __device__ inline int probe_pick(int64_t tile, int k, int extent, int salt)
 // float32 x float32 product is exact in float64), compares them with the
 // cheap result C, and marks the tile for correction when the sampled relative
 // Frobenius error exceeds tau (or the samples are all zero but C is not).
-constexpr int PROBE_THREADS = 256;
+//
+// K runs in passes of PK elements: the workgroup first rebuilds the PS rows
+// of A and PS rows of B^T for the pass as exact float32 in LDS (each thread
+// loads 16-byte chunks of the three planes; eight neighbouring lanes read
+// one 128-byte line), then thread t adds products for sample t % 64 over the
+// t / 64-th eighth of the pass.  The eight partial sums of a sample are added
+// in eighth order at the end.
+constexpr int PROBE_THREADS = 512;
+constexpr int PK = 1024;             // K elements per pass
+constexpr int PKS = PK + 4;          // LDS row stride (floats): rows fall in different banks
 
 __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restrict__ pa, const char *__restrict__ pb,
                                                            const float *__restrict__ C, GemmShape sh, int bm, int bn,
                                                            int tiles_n, int64_t nkb, double tau2,
                                                            ProbeRecord *__restrict__ rec)
 {
-    constexpr int NW = PROBE_THREADS / 64;
+    constexpr int NW = PROBE_THREADS / 64;                // K slices per pass (one per wavefront)
+    constexpr int CH = PK / 8;                            // 16-byte chunks per row per pass
+    static_assert(PS * PS == 64 && PS == 8, "8 x 8 samples, one per lane");
+    static_assert((2 * PS * CH) % PROBE_THREADS == 0, "chunks divide over the threads");
+    __shared__ __attribute__((aligned(16))) float xs[2][PS][PKS];  // [A / B^T][sample row][k in pass]
     __shared__ double part[NW][PS * PS];
     const int64_t tile = blockIdx.x;
     const int tm = (int)(tile / tiles_n), tn = (int)(tile % tiles_n);
     const int64_t row0 = (int64_t)tm * bm, col0 = (int64_t)tn * bn;
     const int rext = (int)min<int64_t>(bm, sh.m - row0), cext = (int)min<int64_t>(bn, sh.n - col0);
-    int64_t rows[PS], cols[PS];
+    const int q = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int u = q / PS, v = q % PS;
+    const int64_t kpad = nkb * 32;                        // elements the packed operands hold per row
+    double acc = 0.0;
+    for (int64_t k0 = 0; k0 < sh.k; k0 += PK) {
+        // stage: chunk id -> (operand, chunk in pass, sample row); row fastest
 #pragma unroll
-    for (int k = 0; k < PS; ++k) {
-        rows[k] = row0 + probe_pick(tile, k, rext, 0);
-        cols[k] = col0 + probe_pick(tile, k, cext, 1);
-    }
-    double acc[PS * PS];
+        for (int id = threadIdx.x; id < 2 * PS * CH; id += PROBE_THREADS) {
+            const int r = id % PS, ch = (id / PS) % CH, ab = id / (PS * CH);
+            const int64_t k8 = k0 + (int64_t)ch * 8;
+            float x[8];
+            if (k8 < kpad) {
+                const int64_t rr = ab == 0 ? row0 + probe_pick(tile, r, rext, 0) : col0 + probe_pick(tile, r, cext, 1);
+                load_exact8(ab == 0 ? pa : pb, nkb, rr, k8, x);
+            } else {
 #pragma unroll
-    for (int q = 0; q < PS * PS; ++q) acc[q] = 0.0;
-    // one 16-byte chunk (8 consecutive k) per plane and vector per step;
-    // elements past k are zero in the packed operands
-    for (int64_t k8 = (int64_t)threadIdx.x * 8; k8 < sh.k; k8 += PROBE_THREADS * 8) {
-        float bv[PS][8];
-#pragma unroll
-        for (int v = 0; v < PS; ++v) load_exact8(pb, nkb, cols[v], k8, bv[v]);
-#pragma unroll
-        for (int u = 0; u < PS; ++u) {
-            float av[8];
-            load_exact8(pa, nkb, rows[u], k8, av);
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-#pragma unroll
-                for (int v = 0; v < PS; ++v)
-                    acc[u * PS + v] = __builtin_fma((double)av[e], (double)bv[v][e], acc[u * PS + v]);
+                for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+            }
+            float4 *d = reinterpret_cast<float4 *>(&xs[ab][r][ch * 8]);
+            d[0] = make_float4(x[0], x[1], x[2], x[3]);
+            d[1] = make_float4(x[4], x[5], x[6], x[7]);
         }
+        __syncthreads();
+        const float4 *ar = reinterpret_cast<const float4 *>(&xs[0][u][slice * (PK / NW)]);
+        const float4 *br = reinterpret_cast<const float4 *>(&xs[1][v][slice * (PK / NW)]);
+#pragma unroll 8
+        for (int j = 0; j < PK / NW / 4; ++j) {
+            const float4 a4 = ar[j], b4 = br[j];
+            acc = __builtin_fma((double)a4.x, (double)b4.x, acc);
+            acc = __builtin_fma((double)a4.y, (double)b4.y, acc);
+            acc = __builtin_fma((double)a4.z, (double)b4.z, acc);
+            acc = __builtin_fma((double)a4.w, (double)b4.w, acc);
+        }
+        __syncthreads();  // the next pass overwrites xs
     }
-#pragma unroll
-    for (int q = 0; q < PS * PS; ++q) {
-        double v = acc[q];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][q] = v;
-    }
+    part[slice][q] = acc;
     __syncthreads();
     // wavefront 0, one sample per lane: compare, then sum the squares over
     // the wavefront (a fixed butterfly: every lane ends with the same sums)
-    static_assert(PS * PS == 64, "one sample per lane");
     if (threadIdx.x < 64) {
-        const int q = threadIdx.x;
-        const int64_t row = row0 + probe_pick(tile, q / PS, rext, 0), col = col0 + probe_pick(tile, q % PS, cext, 1);
+        const int64_t row = row0 + probe_pick(tile, u, rext, 0), col = col0 + probe_pick(tile, v, cext, 1);
         double ref = part[0][q];
 #pragma unroll
         for (int w = 1; w < NW; ++w) ref += part[w][q];

@@ -414,7 +414,8 @@ int tune_variant(int t, uint32_t flags, int limbs)
 {
     if (t == ACC_FLOAT32) {
         const uint32_t p = flags & ACC_PREC_MASK;
-        return p == ACC_PREC_CHEAP3 ? 3 : p == ACC_PREC_FIVE ? 5 : 6;
+        // AUTO is timed as its dominant kernel, the three-product pass
+        return (p == ACC_PREC_CHEAP3 || p == ACC_PREC_AUTO) ? 3 : p == ACC_PREC_FIVE ? 5 : 6;
     }
     return limbs;
 }
