@@ -126,7 +126,9 @@ def test_serving_workload(ax):
     def check(r, view):
         a, b = _region_inputs(ax, pools, r)
         c = view.numpy().reshape(r.n, r.n)
-        ii, jj = g.integers(0, r.n, 16), g.integers(0, r.n, 16)
+        # 256 entries: from 16 the estimate (a ratio of two 16-term sums of
+        # squares) exceeds 2.6 times the true error for about 1 in 5000 requests
+        ii, jj = g.integers(0, r.n, 256), g.integers(0, r.n, 256)
         ref = oracle.matmul_at(a, b, ii, jj)
         ok = np.array_equal(c[ii, jj], ref) if r.dtype == ax.ACC_INT32 else rel_fro(c[ii, jj], ref) <= 1e-5
         if not ok:
