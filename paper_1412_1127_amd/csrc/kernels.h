@@ -23,9 +23,9 @@ hipError_t launch_matmul_plain_i32(const int32_t *a, const int32_t *b, int32_t *
                                    bool listing1b_mapping, hipStream_t s);
 
 // ---- reduction(+) ----------------------------------------------------------
-// Fast: one pass, per-block partials, last block combines them in index order.
-// Workspace: [0,256) ticket word (must start at zero, left at zero),
-//            [256, 256 + 4*blocks) partials.
+// Fast: a streaming pass that stores one partial per block, then a
+// one-block launch that adds them in index order.
+// Workspace: 4 bytes per block (<= 4096 blocks), any contents.
 size_t reduce_fast_workspace_bytes(int64_t n);
 // Plain: one element per thread and a block tree, then one block combines.
 size_t reduce_plain_workspace_bytes(int64_t n);
@@ -43,8 +43,7 @@ struct RedVars {
     int32_t square[RED_MAX_VARS];  // 1: the variable folds x*x
     uint64_t init[RED_MAX_VARS];   // initial values as element bit patterns
 };
-// Workspace: [0,256) ticket word (zero before the first call, left at zero),
-// then RED_MAX_VARS x 4096 partial words of 8 bytes.
+// Workspace: RED_MAX_VARS x 4096 partial words of 8 bytes, any contents.
 size_t reduce_vars_workspace_bytes();
 // dtype: 0 float32, 1 int32, 2 float64, 3 int64; result: nvars elements.
 hipError_t launch_reduce_vars(int dtype, const void *x, int64_t n, const RedVars &vars, void *result, void *work,
