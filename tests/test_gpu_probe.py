@@ -67,6 +67,35 @@ def test_auto_full_precision_inputs(ax, n):
         assert err <= FP32_REL_FRO_TOL
 
 
+def _biased_split(g, shape):
+    # x = h + m + l with h in [1, 1.125) on the bf16 grid, m in
+    # [1.5, 2) * 2^-9 on its grid (below half an ulp of h) and l in
+    # [1.5, 2) * 2^-18 with 6 bits (below half an ulp of m): the split returns
+    # (h, m, l) exactly, and every term the three cheap products drop (h*l,
+    # l*h, m*m) is positive, so the cheap error accumulates instead of
+    # cancelling: 2.3e-5 relative, against 4e-8 for the six products.
+    h = 1.0 + g.integers(0, 16, shape) * 2.0 ** -7
+    m = 2.0 ** -9 * (1.0 + g.integers(64, 128, shape) * 2.0 ** -7)
+    l = 2.0 ** -18 * (1.0 + g.integers(16, 32, shape) * 2.0 ** -5)
+    x = (h + m + l).astype(np.float32)
+    assert np.array_equal(x.astype(np.float64), h + m + l)   # 24 significant bits: exact
+    return x
+
+
+@pytest.mark.parametrize("n", [256, 300])
+def test_auto_corrects_biased_split_error(ax, n):
+    g = synth.rng(SEED, 8)
+    a, b = _biased_split(g, (n, n)), _biased_split(g, (n, n))
+    c, cheap, recs = _auto(ax, a, b)
+    _check_records(a, b, cheap, recs)
+    ref = oracle.matmul_f32(a, b)
+    print("LEN=%d biased split: CHEAP3 rel_fro=%.3g AUTO=%.3g corrected %d/%d" % (
+        n, rel_fro(cheap, ref), rel_fro(c, ref), sum(r.corrected for r in recs), len(recs)))
+    assert rel_fro(cheap, ref) > 1.2e-5          # the cheap pass alone misses the bound
+    assert all(r.corrected for r in recs)        # the probe marks every tile
+    assert rel_fro(c, ref) <= FP32_REL_FRO_TOL   # and the correction brings it back
+
+
 def test_auto_low_precision_inputs_keep_cheap(ax):
     # 8-bit significands: every input is one bf16 term, the three cheap
     # products are exact, no tile needs the correction.
