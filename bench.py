@@ -61,6 +61,8 @@ def _args():
                         "with the float32 matmul")
     p.add_argument("--ingest-counters", metavar="DIR", default=None,
                    help="write the HBM traffic summary from rocprofv3 FETCH_SIZE/WRITE_SIZE runs in DIR and exit")
+    p.add_argument("--no-onbox", action="store_true",
+                   help="scale: skip the on-box reference points (device copy, vendor GEMMs)")
     p.add_argument("--time-all-kernels", action="store_true",
                    help="scale: event-time every kernel inside the timed region (default: the dominant one only)")
     p.add_argument("--copy-calib", action="store_true",
@@ -165,6 +167,36 @@ def ingest_counters(root: str, prec: str) -> int:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
     return 0
+
+
+def _onbox(torch, x):
+    """Reference points measured on this GPU outside the timed region: a
+    plain device copy of the 1 GiB reduction input (read + write bytes), and
+    the vendor library's bf16 and float32 GEMMs at LEN=4096 (torch.matmul,
+    hipBLASLt), beside the datasheet peaks the roofline fractions use."""
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    out = {"datasheet": {"bf16_tflops": PEAK_BF16_TFLOPS, "int8_tops": PEAK_INT8_TOPS, "hbm_gbs": PEAK_HBM_GBS}}
+    dst = torch.empty_like(x)
+    ms = timed(lambda: dst.copy_(x), 10)
+    out["copy_gbs"] = 2.0 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9
+    del dst
+    n = 4096
+    for name, dt in (("vendor_bf16_gemm_tflops", torch.bfloat16), ("vendor_fp32_gemm_tflops", torch.float32)):
+        a = torch.rand((n, n), device=x.device, dtype=dt)
+        b = torch.rand((n, n), device=x.device, dtype=dt)
+        timed(lambda: torch.matmul(a, b), 10)               # clocks to their loaded state
+        out[name] = 2.0 * n ** 3 / (timed(lambda: torch.matmul(a, b), 30) * 1e-3) / 1e12
+        del a, b
+    return out
 
 
 def _pct(v, q):
@@ -340,6 +372,8 @@ def run_scale(args) -> int:
         sref = oracle.sum_f32(x)
         accuracy["reduce_rel_err"] = abs(float(dr.item()) - sref) / sref
 
+    onbox = None if args.no_onbox else _onbox(torch, dx)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -379,6 +413,7 @@ def run_scale(args) -> int:
         "cpu_baseline": cpu,
         "components": components,
         "accuracy": accuracy,
+        "onbox": onbox,
     }
     ax.acc_shutdown()
     print(json.dumps(line))
