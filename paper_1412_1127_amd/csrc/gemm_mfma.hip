@@ -48,6 +48,14 @@ __global__ __launch_bounds__(256) void pack_bf16x3(const float *__restrict__ X, 
 }
 
 
+// Digit 0 of four consecutive elements, packed into one word: the balanced
+// base-256 digit ((x + 128) mod 256) - 128 is the low byte of x read as int8.
+__device__ inline int low_bytes4(int32_t a, int32_t b, int32_t c, int32_t d)
+{
+    return (int)(((uint32_t)a & 255u) | (((uint32_t)b & 255u) << 8) | (((uint32_t)c & 255u) << 16) |
+                 ((uint32_t)d << 24));
+}
+
 // Record a workgroup's max |x| (256 threads, each holding its own max) in
 // *maxabs, which starts at zero.  Only maxima above 127 are recorded: the
 // digit count depends on max |x| only through thresholds from 127 up, so the
@@ -115,14 +123,21 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
                 v[t] = in ? (TRANS ? X[(k0 + t) * ld + row] : X[row * ld + k0 + t]) : 0;
             }
         }
-        int64_t rem[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
-            rem[t] = v[t];
             const uint32_t a = v[t] < 0 ? (uint32_t)0 - (uint32_t)v[t] : (uint32_t)v[t];
             mx = a > mx ? a : mx;
         }
         char *u = out + unit * ((int64_t)nplanes * PLANE_BYTES) + c * 512 + r * 16;
+        if (nplanes == 1) {  // one digit: the low bytes, no carries to follow
+            *reinterpret_cast<i32x4 *>(u) = i32x4{low_bytes4(v[0], v[1], v[2], v[3]), low_bytes4(v[4], v[5], v[6], v[7]),
+                                                  low_bytes4(v[8], v[9], v[10], v[11]),
+                                                  low_bytes4(v[12], v[13], v[14], v[15])};
+            continue;
+        }
+        int64_t rem[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) rem[t] = v[t];
         for (int p = 0; p < nplanes; ++p) {
             i32x4 word = {0, 0, 0, 0};
 #pragma unroll
@@ -224,15 +239,23 @@ __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, 
         const int q = j * 256 + threadIdx.x;
         const int r = q & 31, c = (q >> 5) & 1, u = q >> 6;
         if (rb0 + u >= nrb) continue;
-        int64_t rem[16];
+        int32_t x[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int32_t v = (int32_t)t[c * 16 + e][u * 32 + r];
-            rem[e] = v;
-            const uint32_t a = v < 0 ? (uint32_t)0 - (uint32_t)v : (uint32_t)v;
+            x[e] = (int32_t)t[c * 16 + e][u * 32 + r];
+            const uint32_t a = x[e] < 0 ? (uint32_t)0 - (uint32_t)x[e] : (uint32_t)x[e];
             mx = a > mx ? a : mx;
         }
         char *o = out + ((rb0 + u) * nkb + kb) * ((int64_t)nplanes * PLANE_BYTES) + (half * 2 + c) * 512 + r * 16;
+        if (nplanes == 1) {  // one digit: the low bytes
+            *reinterpret_cast<i32x4 *>(o) = i32x4{low_bytes4(x[0], x[1], x[2], x[3]), low_bytes4(x[4], x[5], x[6], x[7]),
+                                                  low_bytes4(x[8], x[9], x[10], x[11]),
+                                                  low_bytes4(x[12], x[13], x[14], x[15])};
+            continue;
+        }
+        int64_t rem[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) rem[e] = x[e];
         for (int p = 0; p < nplanes; ++p) {
             i32x4 word = {0, 0, 0, 0};
 #pragma unroll
