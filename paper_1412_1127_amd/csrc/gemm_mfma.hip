@@ -85,16 +85,15 @@ __device__ inline void block_max_record(uint32_t mx, uint32_t *maxabs)
 // maxabs (optional): max |x| over the operand as block_max_record leaves it.
 // decide (optional): the two max|x| words of a finished probe pass; the
 // kernel then packs only if limb_gate(decide, expect) holds.
+// Work item id in [id0, total) by `step`; returns the thread's max |x|.
 template <bool TRANS>
-__global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
-                                               char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
-                                               uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
-                                               int expect)
+__device__ inline uint32_t pack_i8_items(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                         char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int64_t id0,
+                                         int64_t step)
 {
-    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
     const int64_t total = nrb * nkb * 128;
     uint32_t mx = 0;
-    for (int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x; id < total; id += (int64_t)gridDim.x * 256) {
+    for (int64_t id = id0; id < total; id += step) {
         const int64_t unit = id >> 7;
         const int w = (int)(id & 127);
         int r, c;
@@ -149,6 +148,18 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
             *reinterpret_cast<i32x4 *>(u + (int64_t)p * PLANE_BYTES) = word;
         }
     }
+    return mx;
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                               char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
+                                               uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
+                                               int expect)
+{
+    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
+    const uint32_t mx = pack_i8_items<TRANS>(X, R, K, ld, out, nrb, nkb, nplanes,
+                                             (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
     if (maxabs) block_max_record(mx, maxabs);
 }
 
@@ -189,12 +200,12 @@ __device__ inline void stage_rows(const uint32_t *__restrict__ X, int64_t R, int
     }
 }
 
-// bf16x3 planes of B^T.  Grid: x = column tiles of X, y = 32-element K units.
-__global__ __launch_bounds__(256) void pack_bf16x3_t(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
-                                                     char *__restrict__ out, int64_t nrb, int64_t nkb)
+// bf16x3 planes of B^T for column tile bx of X and 32-element K unit by.
+__device__ inline void pack_bf16x3_cols(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                        char *__restrict__ out, int64_t nrb, int64_t nkb, int64_t bx, int64_t by,
+                                        uint32_t (*t)[TP_COLS])
 {
-    __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
-    const int64_t kb = blockIdx.y, rb0 = (int64_t)blockIdx.x * (TP_COLS / 32);
+    const int64_t kb = by, rb0 = bx * (TP_COLS / 32);
     stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 32, rb0 * 32, t);
     __syncthreads();
     // 8 units x 32 rows x 4 chunks of 8 elements, four per thread
@@ -219,17 +230,40 @@ __global__ __launch_bounds__(256) void pack_bf16x3_t(const float *__restrict__ X
     }
 }
 
-// int8 digit planes of B^T.  Grid: x = column tiles of X, y = halves of the
-// 64-element K units (32 rows of X each).  maxabs / decide as for pack_i8.
-__global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
-                                                 char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
-                                                 uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
-                                                 int expect)
+// Grid: x = column tiles of X, y = 32-element K units.
+__global__ __launch_bounds__(256) void pack_bf16x3_t(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                                     char *__restrict__ out, int64_t nrb, int64_t nkb)
 {
-    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
     __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
-    const int64_t kb = blockIdx.y >> 1, rb0 = (int64_t)blockIdx.x * (TP_COLS / 32);
-    const int half = blockIdx.y & 1;
+    pack_bf16x3_cols(X, R, K, ld, out, nrb, nkb, blockIdx.x, blockIdx.y, t);
+}
+
+// A and B^T of one product in one launch (one kernel start instead of two):
+// workgroups [0, ga) pack the rows of A, the others column tiles of B
+// (gbx per K unit).
+__global__ __launch_bounds__(256) void pack_bf16x3_pair(const float *__restrict__ A, int64_t M, int64_t lda,
+                                                        char *__restrict__ pa, const float *__restrict__ B, int64_t N,
+                                                        int64_t ldb, char *__restrict__ pb, int64_t K, int ga, int gbx)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
+    const int64_t nkb = (K + 31) / 32;
+    if ((int)blockIdx.x < ga) {
+        pack_bf16x3_range<false>(A, M, K, lda, pa, (M + 31) / 32, nkb, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                                 (int64_t)ga * 256);
+    } else {
+        const int64_t b = blockIdx.x - ga;
+        pack_bf16x3_cols(B, N, K, ldb, pb, (N + 31) / 32, nkb, b % gbx, b / gbx, t);
+    }
+}
+
+// int8 digit planes of B^T for column tile bx of X and half by of the
+// 64-element K units (32 rows of X each); returns the thread's max |x|.
+__device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                        char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int64_t bx,
+                                        int64_t by, uint32_t (*t)[TP_COLS])
+{
+    const int64_t kb = by >> 1, rb0 = bx * (TP_COLS / 32);
+    const int half = (int)(by & 1);
     stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 64 + half * 32, rb0 * 32, t);
     __syncthreads();
     uint32_t mx = 0;
@@ -267,7 +301,43 @@ __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, 
             *reinterpret_cast<i32x4 *>(o + (int64_t)p * PLANE_BYTES) = word;
         }
     }
+    return mx;
+}
+
+// Grid: x = column tiles of X, y = halves of the 64-element K units.
+// maxabs / decide as for pack_i8.
+__global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                                 char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
+                                                 uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
+                                                 int expect)
+{
+    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
+    __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
+    const uint32_t mx = pack_i8_cols(X, R, K, ld, out, nrb, nkb, nplanes, blockIdx.x, blockIdx.y, t);
     if (maxabs) block_max_record(mx, maxabs);
+}
+
+// A and B^T of one product in one launch: workgroups [0, ga) pack the rows of
+// A (max |x| into maxabs[0]), the others column tiles of B (gbx per K half
+// unit; maxabs[1]).  maxabs (optional) / decide as for pack_i8.
+__global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ A, int64_t M, int64_t lda,
+                                                    char *__restrict__ pa, const int32_t *__restrict__ B, int64_t N,
+                                                    int64_t ldb, char *__restrict__ pb, int64_t K, int nplanes, int ga,
+                                                    int gbx, uint32_t *__restrict__ maxabs,
+                                                    const uint32_t *__restrict__ decide, int expect)
+{
+    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
+    __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
+    const int64_t nkb = (K + 63) / 64;
+    uint32_t mx;
+    if ((int)blockIdx.x < ga) {
+        mx = pack_i8_items<false>(A, M, K, lda, pa, (M + 31) / 32, nkb, nplanes,
+                                  (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)ga * 256);
+    } else {
+        const int64_t b = blockIdx.x - ga;
+        mx = pack_i8_cols(B, N, K, ldb, pb, (N + 31) / 32, nkb, nplanes, b % gbx, b / gbx, t);
+    }
+    if (maxabs) block_max_record(mx, maxabs + ((int)blockIdx.x < ga ? 0 : 1));
 }
 
 
@@ -603,6 +673,34 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld,
     else
         hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out), nrb,
                            nkb, planes, maxabs, decide, expect);
+    tmark("pack_i8", s, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_bf16x3_pair(const float *a, int64_t m, int64_t lda, const float *b, int64_t n, int64_t ldb,
+                                   int64_t k, void *pa, void *pb, hipStream_t s)
+{
+    const int64_t nkb = cdiv(k, 32), ua = cdiv(m, 32) * nkb;
+    const int64_t ga = ua > 0 ? pack_grid(ua) : 0, gbx = cdiv(n, TP_COLS), gb = gbx * nkb;
+    if (ga + gb == 0) return hipSuccess;
+    tmark("pack_bf16x3", s, true);
+    hipLaunchKernelGGL(pack_bf16x3_pair, dim3((unsigned)(ga + gb)), dim3(256), 0, s, a, m, lda,
+                       static_cast<char *>(pa), b, n, ldb, static_cast<char *>(pb), k, (int)ga, (int)std::max<int64_t>(gbx, 1));
+    tmark("pack_bf16x3", s, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const int32_t *b, int64_t n, int64_t ldb,
+                               int64_t k, int planes, void *pa, void *pb, uint32_t *maxabs, hipStream_t s,
+                               const uint32_t *decide, int expect)
+{
+    const int64_t nkb = cdiv(k, 64), ua = cdiv(m, 32) * nkb;
+    const int64_t ga = ua > 0 ? pack_grid(ua) : 0, gbx = cdiv(n, TP_COLS), gb = gbx * 2 * nkb;
+    if (ga + gb == 0) return hipSuccess;
+    tmark("pack_i8", s, true);
+    hipLaunchKernelGGL(pack_i8_pair, dim3((unsigned)(ga + gb)), dim3(256), 0, s, a, m, lda, static_cast<char *>(pa), b,
+                       n, ldb, static_cast<char *>(pb), k, planes, (int)ga, (int)std::max<int64_t>(gbx, 1), maxabs,
+                       decide, expect);
     tmark("pack_i8", s, false);
     return hipGetLastError();
 }

@@ -64,6 +64,14 @@ hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, int64_t l
 // from the two max|x| words is 1 (expect = 1) or more (expect = 4).
 hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld, bool trans, int planes, void *out,
                           uint32_t *maxabs, hipStream_t s, const uint32_t *decide = nullptr, int expect = 0);
+// Both operands of one product in one launch: A (m x k, rows) into pa and B
+// (k x n, packed as B^T) into pb, as the two calls above would; for int8,
+// maxabs (nullable) gets A's max in word 0 and B's in word 1.
+hipError_t launch_pack_bf16x3_pair(const float *a, int64_t m, int64_t lda, const float *b, int64_t n, int64_t ldb,
+                                   int64_t k, void *pa, void *pb, hipStream_t s);
+hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const int32_t *b, int64_t n, int64_t ldb,
+                               int64_t k, int planes, void *pa, void *pb, uint32_t *maxabs, hipStream_t s,
+                               const uint32_t *decide = nullptr, int expect = 0);
 // C (m x n, leading dimension ldc) = sum over the product set of A-plane x
 // B-plane, A and B packed with k elements per row.
 // products: 6 = FULL6, 5 = FIVE (FULL6 without mid*mid), 3 = CHEAP3, -3 = the

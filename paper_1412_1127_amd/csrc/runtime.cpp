@@ -469,8 +469,7 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
     const accx::SplitK sk = split_for(ACC_FLOAT32, sh, flags, work, work_bytes);
     const size_t pb = accx::packed_bytes(sh.m, sh.k, 2, 3);
     char *pa = work, *pbt = work + pb;
-    hipError_t e = accx::launch_pack_bf16x3(a, sh.m, sh.k, sh.lda, false, pa, s);
-    if (e == hipSuccess) e = accx::launch_pack_bf16x3(b, sh.n, sh.k, sh.ldb, true, pbt, s);
+    hipError_t e = accx::launch_pack_bf16x3_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, pa, pbt, s);
     if (e != hipSuccess) return fail_hip(e, "pack (bf16x3) launch");
     const uint32_t prec = flags & ACC_PREC_MASK;
     if (prec == ACC_PREC_AUTO) {
@@ -510,19 +509,18 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const G
         const size_t pa1 = accx::packed_bytes(sh.m, sh.k, 1, 1), pa4 = accx::packed_bytes(sh.m, sh.k, 1, 4);
         char *p4 = pa + packed_pair(sh, 1, 1);
         e = accx::launch_zero_u32(maxabs, 2, s);
-        if (e == hipSuccess) e = accx::launch_pack_i8(a, sh.m, sh.k, sh.lda, false, 1, pa, maxabs, s);
-        if (e == hipSuccess) e = accx::launch_pack_i8(b, sh.n, sh.k, sh.ldb, true, 1, pa + pa1, maxabs + 1, s);
-        if (e == hipSuccess) e = accx::launch_pack_i8(a, sh.m, sh.k, sh.lda, false, 4, p4, nullptr, s, maxabs, 4);
         if (e == hipSuccess)
-            e = accx::launch_pack_i8(b, sh.n, sh.k, sh.ldb, true, 4, p4 + pa4, nullptr, s, maxabs, 4);
+            e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 1, pa, pa + pa1, maxabs, s);
+        if (e == hipSuccess)
+            e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 4, p4, p4 + pa4, nullptr, s, maxabs,
+                                          4);
         if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
         e = accx::launch_gemm_i8(pa, pa + pa1, c, sh, 1, resolve_tile(ACC_INT32, sh, flags, 1), s, maxabs, sk);
         if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pa4, c, sh, 4, 0, s, maxabs);
         return check_launch(e, "gemm (int8) launch");
     }
     const size_t pan = accx::packed_bytes(sh.m, sh.k, 1, nl);
-    e = accx::launch_pack_i8(a, sh.m, sh.k, sh.lda, false, nl, pa, nullptr, s);
-    if (e == hipSuccess) e = accx::launch_pack_i8(b, sh.n, sh.k, sh.ldb, true, nl, pa + pan, nullptr, s);
+    e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, nl, pa, pa + pan, nullptr, s);
     if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
     return check_launch(
         accx::launch_gemm_i8(pa, pa + pan, c, sh, nl, resolve_tile(ACC_INT32, sh, flags, nl), s, nullptr, sk),
