@@ -50,7 +50,8 @@ def _args():
                    help="force the float32 tile configuration (implies --no-autotune)")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the tile autotuner before the timed region (size heuristic instead)")
-    p.add_argument("--workload", choices=["scale", "small", "precision", "batch", "serve", "rowblock", "reductions"],
+    p.add_argument("--workload", choices=["scale", "small", "precision", "batch", "serve", "rowblock", "reductions",
+                                          "regions"],
                    default="scale",
                    help="scale (default): the step described above; the others measure the remaining "
                         "configurations (LEN=256 plain method, LEN=8192 precision, batching, serving) and "
@@ -781,6 +782,77 @@ def run_serve(args) -> int:
     return 0
 
 
+def run_regions(args) -> int:
+    """The data directive around the worked example (section 1.3): a region
+    with copyin(a, b) and copyout(c) for a LEN=4096 float32 matmul, from
+    pageable numpy arrays and from page-locked host memory, plus the update
+    directive on a subrange.  Host<->device bytes over PCIe are in every
+    time here: these rates are transfer rates, not the kernel's."""
+    import ctypes
+
+    import numpy as np
+
+    import oracle
+    import paper_1412_1127_amd as ax
+    import synth
+    ax.acc_init(0, 0)
+    n = args.len
+    seed = synth.DEFAULT_SEED
+    a0 = synth.uniform_pm1_f32((n, n), seed, synth.STREAM_A)
+    b0 = synth.uniform_pm1_f32((n, n), seed, synth.STREAM_B)
+    nbytes = n * n * 4
+    flags = ax.ACC_KERNEL_TILED | ax.ACC_PREC_AUTO
+    out, pinned = {}, []
+    try:
+        for mode in ("pageable", "pinned"):
+            if mode == "pageable":
+                a, b, c = a0.copy(), b0.copy(), np.zeros((n, n), np.float32)
+            else:
+                bufs = []
+                for _ in range(3):
+                    p_ = ax.accx_host_alloc(nbytes)
+                    pinned.append(p_)
+                    bufs.append(np.ctypeslib.as_array((ctypes.c_float * (n * n)).from_address(p_)).reshape(n, n))
+                a, b, c = bufs
+                a[:], b[:], c[:] = a0, b0, 0.0
+            cl = [ax.clause(ax.ACC_COPYIN, ax.ACC_FLOAT32, a), ax.clause(ax.ACC_COPYIN, ax.ACC_FLOAT32, b),
+                  ax.clause(ax.ACC_COPYOUT, ax.ACC_FLOAT32, c)]
+            tin, tk, tout, tup = [], [], [], []
+            for it in range(args.warmup + args.steps):
+                t0 = time.perf_counter()
+                r = ax.acc_data_begin(cl)
+                ax.acc_wait(r)
+                t1 = time.perf_counter()
+                ax.acc_loopnest_matmul(r, ax.ACC_FLOAT32, a, b, c, n, flags)
+                ax.acc_wait(r)
+                t2 = time.perf_counter()
+                ax.acc_update(r, ax.ACC_UPDATE_DEVICE, ax.ACC_FLOAT32, a, 0, n * n // 4)   # a quarter of a
+                t3 = time.perf_counter()
+                ax.acc_data_end(r)
+                t4 = time.perf_counter()
+                if it >= args.warmup:
+                    tin.append(t1 - t0), tk.append(t2 - t1), tup.append(t3 - t2), tout.append(t4 - t3)
+            g = synth.rng(seed, 99)
+            ii, jj = g.integers(0, n, 1024), g.integers(0, n, 1024)
+            ref = oracle.matmul_at(a0, b0, ii, jj)
+            med = lambda v: float(np.median(v))
+            out[mode] = {"copyin_gbs": 2 * nbytes / med(tin) / 1e9, "copyout_gbs": nbytes / med(tout) / 1e9,
+                         "update_device_gbs": nbytes / 4 / med(tup) / 1e9, "matmul_ms": med(tk) * 1e3,
+                         "region_ms": (med(tin) + med(tk) + med(tup) + med(tout)) * 1e3,
+                         "rel_fro_vs_oracle_sampled": float(np.linalg.norm(c[ii, jj] - ref) / np.linalg.norm(ref))}
+    finally:
+        for p_ in pinned:
+            ax.accx_host_free(p_)
+        ax.acc_shutdown()
+    best = out["pinned"]
+    print(json.dumps(_common(
+        args, "data-region host<->device GB/s (copyin, pinned host memory)", best["copyin_gbs"], "GB/s",
+        best["region_ms"], {"workload": "data region around the LEN=%d float32 matmul: copyin(a, b), copyout(c), "
+                                         "update device on a quarter of a" % n, "len": n},
+        modes=out)))
+    return 0
+
+
 def main() -> int:
     args = _args()
     if args.ingest_counters:
@@ -791,7 +863,8 @@ def main() -> int:
               "and no multi-GPU form is built; run with --gpus 1.", file=sys.stderr)
         return 2
     return {"scale": run_scale, "small": run_small, "precision": run_precision, "batch": run_batch,
-            "serve": run_serve, "rowblock": run_rowblock, "reductions": run_reductions}[args.workload](args)
+            "serve": run_serve, "rowblock": run_rowblock, "reductions": run_reductions,
+            "regions": run_regions}[args.workload](args)
 
 
 if __name__ == "__main__":
