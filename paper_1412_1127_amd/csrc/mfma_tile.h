@@ -107,10 +107,18 @@ __device__ __attribute__((always_inline)) inline void pack_bf16x3_range(const fl
 // ------------------------------------------------------------------- GEMM --
 
 // 16-byte direct global->LDS load of one wavefront: lane l reads 16 bytes at
-// its own `src` and they land at dst + 16*l (dst is wavefront-uniform).
-// Kept out of the kernel templates: the builtin is device-only, and a kernel
-// template that names it directly loses its host launch stub.
-__device__ inline void dma16(const void *src, void *dst) { __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0); }
+// its own `src` and they land at dst + 16*l (dst is wavefront-uniform; M0
+// holds its LDS address).  Issued as inline assembly, not through the
+// compiler's builtin: for the builtin the compiler cannot tell the LDS bytes
+// a load writes from those the following reads use, and waits for every
+// load in flight before the first LDS read after it, i.e. for the stage just
+// issued, which undoes the ring's prefetch.  The kernels order these loads
+// themselves: s_waitcnt vmcnt(N) for the stage they read, then a barrier.
+__device__ inline void dma16(const void *src, void *dst)
+{
+    const uint32_t lds = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)dst);
+    asm volatile("global_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(lds) : "memory");
+}
 
 template <bool INT8> struct Mma;
 template <> struct Mma<false> {
