@@ -516,8 +516,8 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restric
 
 // Tile configurations (BM x BN, wavefront grid, K-step bytes, ring depth):
 //  T256     256 x 256, 8 waves (2x4), 32 B (bf16x3) / 64 B (int8), 3 stages:
-//           one workgroup per CU, 144 / 96 KB LDS; bf16x3 products that use
-//           two planes only: 64 B, 2 stages, 128 KB.
+//           one workgroup per CU, 144 / 96 KB LDS (bf16x3 with two planes:
+//           96 KB).
 //  T256x128 256 x 128, 4 waves (2x2), 32 B / 64 B, 2 stages: 72 / 48 KB LDS,
 //           two workgroups per CU that do not share barriers.
 //  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3).
@@ -555,11 +555,6 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
     if (multi) tile = GEMM_TILE_64;
     switch (tile) {
     case GEMM_TILE_256:
-        // Two planes (the cheap three products): 64-byte K steps in a
-        // two-stage ring (2 x 64 KB) give each barrier as many matrix
-        // instructions as the six products get from 32-byte steps.
-        if constexpr (!INT8 && planes_used(PL, NPROD) == 2)
-            return launch_tile<INT8, P, 256, 256, 64, 2, 4, 2, NPROD, PL, NACC>(g, s);
         // Look-ahead: full for the one-digit int8 tile (two fragment sets of
         // 48 registers fit beside its 128 accumulator registers), first-product
         // only for bf16x3, whose three planes leave no room for a second full
