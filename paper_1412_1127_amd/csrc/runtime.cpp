@@ -1517,10 +1517,16 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
                 if (r > 0) per[tile] = std::min(per[tile], (double)ms / reps);  // round 0 warms up
             }
         }
-        for (int tile = 1; tile < accx::GEMM_TILE_COUNT; ++tile)
-            if (per[tile] < best_ms) {
-                best_ms = per[tile];
+        // the fastest, except that a candidate earlier in the fixed order
+        // within 2 % of it wins: tiles that differ less than the clock's
+        // drift between boxes would otherwise change from run to run
+        double fastest = 1e300;
+        for (int tile = 1; tile < accx::GEMM_TILE_COUNT; ++tile) fastest = std::min(fastest, per[tile]);
+        for (int tile = 1; tile < accx::GEMM_TILE_COUNT && fastest < 1e300; ++tile)
+            if (per[tile] <= fastest * 1.02) {
                 best = tile;
+                best_ms = per[tile];
+                break;
             }
     }
     tune_table()[tune_key(t, tune_variant(t, flags, limbs) + 100 * family, sh)] = TuneEntry{best, best_ms};
