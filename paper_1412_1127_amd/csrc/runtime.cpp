@@ -1500,10 +1500,13 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
         };
         const double work = std::max(1.0, 2.0 * (double)sh.m * (double)sh.n * (double)sh.k);
         const int reps = (int)std::max<double>(2.0, std::min<double>(50.0, 2e11 / work));
-        const int rounds = 4;
+        // The clock drifts up over the first rounds: the order alternates
+        // (forward, backward) so that no candidate is always timed later.
+        const int rounds = 5;
         std::vector<double> per(accx::GEMM_TILE_COUNT, 1e300);
         for (int r = 0; r < rounds; ++r) {
-            for (int tile = 1; tile < accx::GEMM_TILE_COUNT; ++tile) {
+            for (int q = 1; q < accx::GEMM_TILE_COUNT; ++q) {
+                const int tile = (r & 1) ? accx::GEMM_TILE_COUNT - q : q;
                 if (!(mask & (1u << tile))) continue;
                 if (limbs > 1 && tile != accx::GEMM_TILE_64) continue;  // several limbs: small tile only
                 if ((he = run(tile)) != hipSuccess) goto hip_out;
