@@ -558,7 +558,8 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
         // Look-ahead: full for the one-digit int8 tile (two fragment sets of
         // 48 registers fit beside its 128 accumulator registers), first-product
         // only for bf16x3, whose three planes leave no room for a second full
-        // set at two wavefronts per SIMD.
+        // set at two wavefronts per SIMD.  (A fourth stage, which fits for a
+        // two-plane pass, measured 4 % slower: the loads are not the limit.)
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, multi ? 2 : 4, multi ? 2 : 3, NPROD, PL,
                            NACC, multi ? 0 : INT8 ? 1 : 2>(g, s);
     case GEMM_TILE_256W4:

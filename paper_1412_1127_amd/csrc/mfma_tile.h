@@ -163,6 +163,31 @@ constexpr uint64_t PL_L3 = prod(0, 0, 0, 0) | prod(1, 0, 1, 1) | prod(2, 1, 0, 1
                            prod(4, 1, 1, 2) | prod(5, 2, 0, 2) | prod(6, 1, 2, 3) | prod(7, 2, 1, 3);
 constexpr uint64_t PL_L4 = PL_L3 | prod(8, 0, 3, 3) | prod(9, 3, 0, 3);
 
+// Product t is the first of products 1..t to need A plane prod_p(L, t) (or B
+// plane prod_q(L, t)), and that plane is not the one product 0 uses.
+constexpr bool first_use_a(uint64_t L, int t)
+{
+    if (prod_p(L, t) == prod_p(L, 0)) return false;
+    for (int u = 1; u < t; ++u)
+        if (prod_p(L, u) == prod_p(L, t)) return false;
+    return true;
+}
+constexpr bool first_use_b(uint64_t L, int t)
+{
+    if (prod_q(L, t) == prod_q(L, 0)) return false;
+    for (int u = 1; u < t; ++u)
+        if (prod_q(L, u) == prod_q(L, t)) return false;
+    return true;
+}
+
+// Fragment reads of products 1..nprod-1 beyond product 0's planes.
+constexpr int later_reads(uint64_t L, int nprod, int wbm, int wbn)
+{
+    int r = 0;
+    for (int t = 1; t < nprod; ++t) r += (first_use_a(L, t) ? wbm : 0) + (first_use_b(L, t) ? wbn : 0);
+    return r;
+}
+
 // Planes a product list touches: 1 + the largest plane index on either side.
 constexpr int planes_used(uint64_t L, int nprod)
 {
@@ -299,7 +324,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     static_assert(NCOPY % WAVES == 0, "loads must divide evenly over the wavefronts");
     static_assert(NS >= 2 && LPW * (NS - 2) < 64, "vmcnt range");
     static_assert(LAM == 0 || NS >= 3, "look-ahead needs three stages");
-    static_assert(LAM != 2 || SUB == 1, "first-product look-ahead: one matrix step per stage");
+    static_assert(LAM != 2 || (SUB == 1 && NPROD > 1), "first-product look-ahead: one matrix step per stage");
     static_assert(NS * STAGE <= 160 * 1024, "LDS");
     static_assert(NPL <= P, "product list names a plane the operand lacks");
 
@@ -383,7 +408,8 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
                 if (step + NS - 1 < nsteps) issue(step + NS - 1);
             }
             // the other planes of this stage (intact until the next
-            // iteration's refill)
+            // iteration's refill), B before A and in the order the products
+            // need them, so that each product waits only for its own reads
             const char *sA = lds + (step % NS) * STAGE;
             const char *sB = sA + MB * LUNIT;
             Frag fa[NPL][WBM], fb[NPL][WBN];
@@ -392,19 +418,24 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
 #pragma unroll
             for (int j = 0; j < WBN; ++j) fb[PB0][j] = cur.b[j];
 #pragma unroll
-            for (int p = 0; p < NPL; ++p) {
-                if (p != PA0) {
-#pragma unroll
-                    for (int i = 0; i < WBM; ++i)
-                        fa[p][i] = *reinterpret_cast<const Frag *>(sA + (wm * WBM + i) * LUNIT + p * 32 * KBK + off);
-                }
-                if (p != PB0) {
+            for (int t = 1; t < NPROD; ++t) {
+                if (first_use_b(PL, t)) {
 #pragma unroll
                     for (int j = 0; j < WBN; ++j)
-                        fb[p][j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + p * 32 * KBK + off);
+                        fb[prod_q(PL, t)][j] = *reinterpret_cast<const Frag *>(
+                            sB + (wn * WBN + j) * LUNIT + prod_q(PL, t) * 32 * KBK + off);
+                }
+                if (first_use_a(PL, t)) {
+#pragma unroll
+                    for (int i = 0; i < WBM; ++i)
+                        fa[prod_p(PL, t)][i] = *reinterpret_cast<const Frag *>(
+                            sA + (wm * WBM + i) * LUNIT + prod_p(PL, t) * 32 * KBK + off);
                 }
             }
-            if (step + 1 < nsteps) load_p0(step + 1, next);
+            // Unconditional, so that reads and matrix instructions form one
+            // block the scheduler can interleave: after the last step it
+            // reads a stage no load is writing, and the values go unused.
+            load_p0(step + 1, next);
 #pragma unroll
             for (int t = 0; t < NPROD; ++t)
 #pragma unroll
@@ -413,6 +444,19 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
                     for (int j = 0; j < WBN; ++j)
                         acc[prod_acc(PL, t)][i][j] =
                             M::run(fa[prod_p(PL, t)][i], fb[prod_q(PL, t)][j], acc[prod_acc(PL, t)][i][j]);
+            // Order: this stage's reads; product 0 (registers only); the
+            // other products with the next stage's first-product reads spread
+            // between their matrix instructions.
+            constexpr int NCUR = later_reads(PL, NPROD, WBM, WBN), NNEXT = WBM + WBN;
+            constexpr int NREST = (NPROD - 1) * WBM * WBN, PER = NREST / NNEXT;
+            __builtin_amdgcn_sched_group_barrier(0x100, NCUR, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, WBM * WBN, 0);
+#pragma unroll
+            for (int r = 0; r < NNEXT; ++r) {
+                __builtin_amdgcn_sched_group_barrier(0x008, PER, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, NREST - PER * NNEXT, 0);
         };
         if (nsteps > 0) {
             if (NS - 2 <= nsteps - 1)
