@@ -571,7 +571,7 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
         return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 128, KS, 2, 2, 2, NPROD, PL, NACC>(g, s);
     case GEMM_TILE_128:
         return launch_tile<INT8, P, multi ? 64 : 128, multi ? 64 : 128, multi ? 64 : 32, 2, 2, multi ? 2 : 3, NPROD,
-                           PL, NACC>(g, s);
+                           PL, NACC, INT8 ? 0 : 2>(g, s);
     default: break;
     }
     return launch_tile<INT8, P, 64, 64, 64, 2, 2, 2, NPROD, PL, NACC>(g, s);
