@@ -168,20 +168,24 @@ __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, in
 //
 // Operand row r is column r of the K x R row-major array X, so one 32-row
 // unit touches only 128 bytes of each row of X.  A workgroup therefore
-// stages a tile of TK rows x 256 columns of X in LDS, each row read as one
-// coalesced 1 KB segment, and then builds 16-byte chunks of eight 32-row
+// stages a tile of TP_ROWS rows x 256 columns of X in LDS, each row read as
+// one coalesced 1 KB segment, and then builds 16-byte chunks of eight 32-row
 // units from LDS columns (consecutive lanes read consecutive columns: no
-// bank conflicts).
-constexpr int TP_COLS = 256;  // columns of X per tile (eight units)
-constexpr int TP_ROWS = 32;   // rows of X per tile
+// bank conflicts).  16 rows (16 KB of LDS) rather than 32: the pair kernels
+// give every workgroup, those packing A too, the transpose's LDS, and at
+// 32 KB it held them to five per CU.
+constexpr int TP_COLS = 256;         // columns of X per tile (eight units)
+constexpr int TP_ROWS = 16;          // rows of X per tile
+constexpr int BF_SPLIT = 32 / TP_ROWS;  // tiles per 32-element bf16x3 K unit
+constexpr int I8_SPLIT = 64 / TP_ROWS;  // tiles per 64-element int8 K unit
 
 __device__ inline void stage_rows(const uint32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld, int64_t k0,
                                   int64_t c0, uint32_t (*t)[TP_COLS])
 {
-    // 32 rows x 64 four-column groups, eight per thread
+    // TP_ROWS rows x 64 four-column groups, TP_ROWS / 4 per thread
     const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15u) == 0);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < TP_ROWS * 64 / 256; ++j) {
         const int q = j * 256 + threadIdx.x;
         const int row = q >> 6, c4 = (q & 63) * 4;
         const int64_t k = k0 + row, col = c0 + c4;
@@ -200,19 +204,22 @@ __device__ inline void stage_rows(const uint32_t *__restrict__ X, int64_t R, int
     }
 }
 
-// bf16x3 planes of B^T for column tile bx of X and 32-element K unit by.
+// bf16x3 planes of B^T for column tile bx of X and part by % BF_SPLIT of
+// the 32-element K unit by / BF_SPLIT.
 __device__ inline void pack_bf16x3_cols(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
                                         char *__restrict__ out, int64_t nrb, int64_t nkb, int64_t bx, int64_t by,
                                         uint32_t (*t)[TP_COLS])
 {
-    const int64_t kb = by, rb0 = bx * (TP_COLS / 32);
-    stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 32, rb0 * 32, t);
+    constexpr int CPT = TP_ROWS / 8;  // 8-element chunks per row per tile
+    const int64_t kb = by / BF_SPLIT, rb0 = bx * (TP_COLS / 32);
+    const int part = (int)(by % BF_SPLIT);
+    stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 32 + part * TP_ROWS, rb0 * 32, t);
     __syncthreads();
-    // 8 units x 32 rows x 4 chunks of 8 elements, four per thread
+    // 8 units x 32 rows x CPT chunks of 8 elements
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8 * 32 * CPT / 256; ++j) {
         const int q = j * 256 + threadIdx.x;
-        const int r = q & 31, c = (q >> 5) & 3, u = q >> 7;
+        const int r = q & 31, c = (q >> 5) % CPT, u = q / (32 * CPT);
         if (rb0 + u >= nrb) continue;
         u16x8 h, m, l;
 #pragma unroll
@@ -223,24 +230,24 @@ __device__ inline void pack_bf16x3_cols(const float *__restrict__ X, int64_t R, 
             m[e] = b;
             l[e] = d;
         }
-        char *o = out + ((rb0 + u) * nkb + kb) * (3 * PLANE_BYTES) + c * 512 + r * 16;
+        char *o = out + ((rb0 + u) * nkb + kb) * (3 * PLANE_BYTES) + (part * CPT + c) * 512 + r * 16;
         *reinterpret_cast<u16x8 *>(o) = h;
         *reinterpret_cast<u16x8 *>(o + PLANE_BYTES) = m;
         *reinterpret_cast<u16x8 *>(o + 2 * PLANE_BYTES) = l;
     }
 }
 
-// Grid: x = column tiles of X, y = 32-element K units.
+// Grid: gbx column tiles of X per K tile, BF_SPLIT K tiles per K unit.
 __global__ __launch_bounds__(256) void pack_bf16x3_t(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
-                                                     char *__restrict__ out, int64_t nrb, int64_t nkb)
+                                                     char *__restrict__ out, int64_t nrb, int64_t nkb, int gbx)
 {
     __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
-    pack_bf16x3_cols(X, R, K, ld, out, nrb, nkb, blockIdx.x, blockIdx.y, t);
+    pack_bf16x3_cols(X, R, K, ld, out, nrb, nkb, blockIdx.x % gbx, blockIdx.x / gbx, t);
 }
 
 // A and B^T of one product in one launch (one kernel start instead of two):
 // workgroups [0, ga) pack the rows of A, the others column tiles of B
-// (gbx per K unit).
+// (gbx per K tile).
 __global__ __launch_bounds__(256) void pack_bf16x3_pair(const float *__restrict__ A, int64_t M, int64_t lda,
                                                         char *__restrict__ pa, const float *__restrict__ B, int64_t N,
                                                         int64_t ldb, char *__restrict__ pb, int64_t K, int ga, int gbx)
@@ -256,22 +263,23 @@ __global__ __launch_bounds__(256) void pack_bf16x3_pair(const float *__restrict_
     }
 }
 
-// int8 digit planes of B^T for column tile bx of X and half by of the
-// 64-element K units (32 rows of X each); returns the thread's max |x|.
+// int8 digit planes of B^T for column tile bx of X and part by % I8_SPLIT of
+// the 64-element K unit by / I8_SPLIT; returns the thread's max |x|.
 __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
                                         char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int64_t bx,
                                         int64_t by, uint32_t (*t)[TP_COLS])
 {
-    const int64_t kb = by >> 1, rb0 = bx * (TP_COLS / 32);
-    const int half = (int)(by & 1);
-    stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 64 + half * 32, rb0 * 32, t);
+    constexpr int CPT = TP_ROWS / 16;  // 16-element chunks per row per tile
+    const int64_t kb = by / I8_SPLIT, rb0 = bx * (TP_COLS / 32);
+    const int part = (int)(by % I8_SPLIT);
+    stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 64 + part * TP_ROWS, rb0 * 32, t);
     __syncthreads();
     uint32_t mx = 0;
-    // 8 units x 32 rows x 2 chunks of 16 elements, two per thread
+    // 8 units x 32 rows x CPT chunks of 16 elements
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < 8 * 32 * CPT / 256; ++j) {
         const int q = j * 256 + threadIdx.x;
-        const int r = q & 31, c = (q >> 5) & 1, u = q >> 6;
+        const int r = q & 31, c = (q >> 5) % CPT, u = q / (32 * CPT);
         if (rb0 + u >= nrb) continue;
         int32_t x[16];
 #pragma unroll
@@ -280,7 +288,7 @@ __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R
             const uint32_t a = x[e] < 0 ? (uint32_t)0 - (uint32_t)x[e] : (uint32_t)x[e];
             mx = a > mx ? a : mx;
         }
-        char *o = out + ((rb0 + u) * nkb + kb) * ((int64_t)nplanes * PLANE_BYTES) + (half * 2 + c) * 512 + r * 16;
+        char *o = out + ((rb0 + u) * nkb + kb) * ((int64_t)nplanes * PLANE_BYTES) + (part * CPT + c) * 512 + r * 16;
         if (nplanes == 1) {  // one digit: the low bytes
             *reinterpret_cast<i32x4 *>(o) = i32x4{low_bytes4(x[0], x[1], x[2], x[3]), low_bytes4(x[4], x[5], x[6], x[7]),
                                                   low_bytes4(x[8], x[9], x[10], x[11]),
@@ -304,22 +312,22 @@ __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R
     return mx;
 }
 
-// Grid: x = column tiles of X, y = halves of the 64-element K units.
+// Grid: gbx column tiles of X per K tile, I8_SPLIT K tiles per K unit.
 // maxabs / decide as for pack_i8.
 __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
                                                  char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
                                                  uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
-                                                 int expect)
+                                                 int expect, int gbx)
 {
     if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
     __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
-    const uint32_t mx = pack_i8_cols(X, R, K, ld, out, nrb, nkb, nplanes, blockIdx.x, blockIdx.y, t);
+    const uint32_t mx = pack_i8_cols(X, R, K, ld, out, nrb, nkb, nplanes, blockIdx.x % gbx, blockIdx.x / gbx, t);
     if (maxabs) block_max_record(mx, maxabs);
 }
 
 // A and B^T of one product in one launch: workgroups [0, ga) pack the rows of
-// A (max |x| into maxabs[0]), the others column tiles of B (gbx per K half
-// unit; maxabs[1]).  maxabs (optional) / decide as for pack_i8.
+// A (max |x| into maxabs[0]), the others column tiles of B (gbx per K tile;
+// maxabs[1]).  maxabs (optional) / decide as for pack_i8.
 __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ A, int64_t M, int64_t lda,
                                                     char *__restrict__ pa, const int32_t *__restrict__ B, int64_t N,
                                                     int64_t ldb, char *__restrict__ pb, int64_t K, int nplanes, int ga,
@@ -647,8 +655,8 @@ hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, int64_t l
     const unsigned grid = pack_grid(nrb * nkb);
     tmark("pack_bf16x3", s, true);
     if (trans)
-        hipLaunchKernelGGL(pack_bf16x3_t, dim3((unsigned)cdiv(rows, TP_COLS), (unsigned)nkb), dim3(256), 0, s, x, rows,
-                           k, ld, static_cast<char *>(out), nrb, nkb);
+        hipLaunchKernelGGL(pack_bf16x3_t, dim3((unsigned)(cdiv(rows, TP_COLS) * BF_SPLIT * nkb)), dim3(256), 0, s, x,
+                           rows, k, ld, static_cast<char *>(out), nrb, nkb, (int)cdiv(rows, TP_COLS));
     else
         hipLaunchKernelGGL(pack_bf16x3<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out),
                            nrb, nkb);
@@ -664,8 +672,9 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld,
     const unsigned grid = pack_grid(nrb * nkb);
     tmark("pack_i8", s, true);
     if (trans)
-        hipLaunchKernelGGL(pack_i8_t, dim3((unsigned)cdiv(rows, TP_COLS), (unsigned)(2 * nkb)), dim3(256), 0, s, x, rows,
-                           k, ld, static_cast<char *>(out), nrb, nkb, planes, maxabs, decide, expect);
+        hipLaunchKernelGGL(pack_i8_t, dim3((unsigned)(cdiv(rows, TP_COLS) * I8_SPLIT * nkb)), dim3(256), 0, s, x, rows,
+                           k, ld, static_cast<char *>(out), nrb, nkb, planes, maxabs, decide, expect,
+                           (int)cdiv(rows, TP_COLS));
     else
         hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out), nrb,
                            nkb, planes, maxabs, decide, expect);
@@ -677,7 +686,7 @@ hipError_t launch_pack_bf16x3_pair(const float *a, int64_t m, int64_t lda, const
                                    int64_t k, void *pa, void *pb, hipStream_t s)
 {
     const int64_t nkb = cdiv(k, 32), ua = cdiv(m, 32) * nkb;
-    const int64_t ga = ua > 0 ? pack_grid(ua) : 0, gbx = cdiv(n, TP_COLS), gb = gbx * nkb;
+    const int64_t ga = ua > 0 ? pack_grid(ua) : 0, gbx = cdiv(n, TP_COLS), gb = gbx * BF_SPLIT * nkb;
     if (ga + gb == 0) return hipSuccess;
     tmark("pack_bf16x3", s, true);
     hipLaunchKernelGGL(pack_bf16x3_pair, dim3((unsigned)(ga + gb)), dim3(256), 0, s, a, m, lda,
@@ -691,7 +700,7 @@ hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const i
                                const uint32_t *decide, int expect)
 {
     const int64_t nkb = cdiv(k, 64), ua = cdiv(m, 32) * nkb;
-    const int64_t ga = ua > 0 ? pack_grid(ua) : 0, gbx = cdiv(n, TP_COLS), gb = gbx * 2 * nkb;
+    const int64_t ga = ua > 0 ? pack_grid(ua) : 0, gbx = cdiv(n, TP_COLS), gb = gbx * I8_SPLIT * nkb;
     if (ga + gb == 0) return hipSuccess;
     tmark("pack_i8", s, true);
     hipLaunchKernelGGL(pack_i8_pair, dim3((unsigned)(ga + gb)), dim3(256), 0, s, a, m, lda, static_cast<char *>(pa), b,
