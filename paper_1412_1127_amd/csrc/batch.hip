@@ -32,9 +32,9 @@ constexpr int BT = 256;              // threads per workgroup (both kernels)
 constexpr int WG_PER_CU = 2;         // persistent workgroups per CU (LDS: 2 x 72 KB)
 constexpr uint32_t UNIT_RED = 0x80000000u;
 
-// Tile variants the persistent kernel carries: T128 and T64, six products
-// (FULL6).  More variants in one kernel push its register need past the 256
-// that two wavefronts per SIMD allow.
+// Tile variants the persistent kernel carries: T128 (first-product
+// look-ahead) and T64, six products (FULL6).  More variants in one kernel
+// push its register need past the 256 that two wavefronts per SIMD allow.
 #define ACCX_T128(NP, PLIST) false, 3, 128, 128, 32, 2, 2, 3, NP, PLIST, 1, 2
 #define ACCX_T64(NP, PLIST) false, 3, 64, 64, 64, 2, 2, 2, NP, PLIST, 1
 

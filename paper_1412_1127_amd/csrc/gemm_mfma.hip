@@ -525,10 +525,12 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restric
 // Tile configurations (BM x BN, wavefront grid, K-step bytes, ring depth):
 //  T256     256 x 256, 8 waves (2x4), 32 B (bf16x3) / 64 B (int8), 3 stages:
 //           one workgroup per CU, 144 / 96 KB LDS (bf16x3 with two planes:
-//           96 KB).
+//           96 KB); first-product look-ahead (bf16x3), full look-ahead
+//           (one-digit int8).
 //  T256x128 256 x 128, 4 waves (2x2), 32 B / 64 B, 2 stages: 72 / 48 KB LDS,
 //           two workgroups per CU that do not share barriers.
-//  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3).
+//  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3);
+//           first-product look-ahead for bf16x3.
 //  T64       64 x 64,  4 waves (2x2), 64 B, 2 stages (several int8 planes).
 //  T256W4   256 x 256, 4 waves (2x2, 128 x 128 each), 32 B / 64 B, 3
 //           stages: a third less LDS read traffic per matrix instruction
