@@ -102,6 +102,24 @@ def test_forced_tiles(ax, tile):
                           oracle.gemm(ai, bi))
 
 
+@pytest.mark.parametrize("tile", ["256", "128", "256w4"])
+@pytest.mark.parametrize("k", [1, 16, 32, 33, 64, 65, 96])
+def test_forced_tiles_short_k(ax, tile, k):
+    # bf16x3 K loops of two, four or six 16-element steps: the ends of the
+    # look-ahead loops, where the read-ahead runs past the last stage; the
+    # int8 tile's loop over one or two 64-element steps
+    import paper_1412_1127_amd as pk
+    m, n = 300, 270
+    a, b = _inputs(m, n, k, "f32", 31)
+    ref = oracle.gemm(a, b)
+    for prec, tol in (("full6", FP32_REL_FRO_TOL), ("auto", FP32_REL_FRO_TOL), ("cheap3", 2.0 ** -12)):
+        err = rel_fro(_gemm(ax, a, b, _flags(ax, prec) | pk.TILES[tile]), ref)
+        assert err <= tol, (prec, err)
+    ai, bi = _inputs(m, n, k, "i32small", 33)
+    assert np.array_equal(_gemm(ax, ai, bi, _flags(ax, "tiled") | ax.ACC_LIMBS(1) | pk.TILES[tile]),
+                          oracle.gemm(ai, bi))
+
+
 @pytest.mark.parametrize("kernel", ["plain", "listing1b", "full6", "cheap3", "auto"])
 def test_f32_leading_dimensions_do_not_change_the_result(ax, kernel):
     # padded rows (odd and multiple-of-4 strides) give the bits of tight rows
