@@ -393,22 +393,6 @@ __device__ inline float packed_bf16(const char *base, int64_t nkb, int p, int64_
     return __uint_as_float((uint32_t)h << 16);
 }
 
-// The 8 float32 values of elements k8..k8+7 (k8 a multiple of 8) of operand
-// row r, rebuilt from the three planes: hi + mid + lo of a float32 x is x
-// itself (the terms do not overlap, so the two float32 additions are exact).
-__device__ inline void load_exact8(const char *base, int64_t nkb, int64_t r, int64_t k8, float out[8])
-{
-    const int64_t unit = (r >> 5) * nkb + (k8 >> 5);
-    const char *c = base + unit * (3 * PLANE_BYTES) + ((k8 & 31) >> 3) * 512 + (r & 31) * 16;
-    const u16x8 h = *reinterpret_cast<const u16x8 *>(c);
-    const u16x8 m = *reinterpret_cast<const u16x8 *>(c + PLANE_BYTES);
-    const u16x8 l = *reinterpret_cast<const u16x8 *>(c + 2 * PLANE_BYTES);
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-        out[e] = (__uint_as_float((uint32_t)h[e] << 16) + __uint_as_float((uint32_t)m[e] << 16)) +
-                 __uint_as_float((uint32_t)l[e] << 16);
-}
-
 constexpr int PS = PROBE_SIDE;  // sampled rows (and columns) per tile
 
 // The k-th of PS consecutive positions in [0, extent), starting at a hashed
@@ -460,25 +444,67 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restric
     const int u = q / PS, v = q % PS;
     const int64_t kpad = nkb * 32;                        // elements the packed operands hold per row
     double acc = 0.0;
+    // The raw plane words of the next pass are loaded while this pass is
+    // staged and summed (double buffering in registers); the barriers are raw
+    // s_barrier after an LDS-only wait, since a full workgroup fence would
+    // also wait for those loads.
+    constexpr int PER = 2 * PS * CH / PROBE_THREADS;  // 16-byte chunks per thread per pass
+    constexpr int LGKM0 = 0xF | (7 << 4) | (3 << 14);  // s_waitcnt lgkmcnt(0)
+    // chunk j of this thread: operand ab, sample row r, chunk ch of a pass
+    const char *src[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int id = threadIdx.x + j * PROBE_THREADS;
+        const int r = id % PS, ab = id / (PS * CH);
+        const int64_t rr = ab == 0 ? row0 + probe_pick(tile, r, rext, 0) : col0 + probe_pick(tile, r, cext, 1);
+        src[j] = (ab == 0 ? pa : pb) + (rr >> 5) * nkb * (3 * PLANE_BYTES) + (rr & 31) * 16;
+    }
+    u32x4_t rh[PER], rm[PER], rl[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int ch = ((threadIdx.x + j * PROBE_THREADS) / PS) % CH;
+        const int64_t k8 = (int64_t)ch * 8;
+        const char *c = src[j] + (k8 >> 5) * (3 * PLANE_BYTES) + ((k8 & 31) >> 3) * 512;
+        const bool in = k8 < kpad;
+        rh[j] = in ? *reinterpret_cast<const u32x4_t *>(c) : u32x4_t{0, 0, 0, 0};
+        rm[j] = in ? *reinterpret_cast<const u32x4_t *>(c + PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
+        rl[j] = in ? *reinterpret_cast<const u32x4_t *>(c + 2 * PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
+    }
     for (int64_t k0 = 0; k0 < sh.k; k0 += PK) {
-        // stage: chunk id -> (operand, chunk in pass, sample row); row fastest
+        // stage: chunk id -> (operand, chunk in pass, sample row); row fastest;
+        // hi + mid + lo of a float32 x is x itself (the two additions are exact)
 #pragma unroll
-        for (int id = threadIdx.x; id < 2 * PS * CH; id += PROBE_THREADS) {
+        for (int j = 0; j < PER; ++j) {
+            const int id = threadIdx.x + j * PROBE_THREADS;
             const int r = id % PS, ch = (id / PS) % CH, ab = id / (PS * CH);
-            const int64_t k8 = k0 + (int64_t)ch * 8;
             float x[8];
-            if (k8 < kpad) {
-                const int64_t rr = ab == 0 ? row0 + probe_pick(tile, r, rext, 0) : col0 + probe_pick(tile, r, cext, 1);
-                load_exact8(ab == 0 ? pa : pb, nkb, rr, k8, x);
-            } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+            for (int w = 0; w < 4; ++w) {
+                x[2 * w] = (__uint_as_float(rh[j][w] << 16) + __uint_as_float(rm[j][w] << 16)) +
+                           __uint_as_float(rl[j][w] << 16);
+                x[2 * w + 1] = (__uint_as_float(rh[j][w] & 0xffff0000u) + __uint_as_float(rm[j][w] & 0xffff0000u)) +
+                               __uint_as_float(rl[j][w] & 0xffff0000u);
             }
             float4 *d = reinterpret_cast<float4 *>(&xs[ab][r][ch * 8]);
             d[0] = make_float4(x[0], x[1], x[2], x[3]);
             d[1] = make_float4(x[4], x[5], x[6], x[7]);
         }
-        __syncthreads();
+        __builtin_amdgcn_s_waitcnt(LGKM0);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (k0 + PK < sh.k) {
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int ch = ((threadIdx.x + j * PROBE_THREADS) / PS) % CH;
+                const int64_t k8 = k0 + PK + (int64_t)ch * 8;
+                const char *c = src[j] + (k8 >> 5) * (3 * PLANE_BYTES) + ((k8 & 31) >> 3) * 512;
+                const bool in = k8 < kpad;
+                rh[j] = in ? *reinterpret_cast<const u32x4_t *>(c) : u32x4_t{0, 0, 0, 0};
+                rm[j] = in ? *reinterpret_cast<const u32x4_t *>(c + PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
+                rl[j] = in ? *reinterpret_cast<const u32x4_t *>(c + 2 * PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
+            }
+        }
         const float4 *ar = reinterpret_cast<const float4 *>(&xs[0][u][slice * (PK / NW)]);
         const float4 *br = reinterpret_cast<const float4 *>(&xs[1][v][slice * (PK / NW)]);
 #pragma unroll 8
@@ -489,7 +515,10 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restric
             acc = __builtin_fma((double)a4.z, (double)b4.z, acc);
             acc = __builtin_fma((double)a4.w, (double)b4.w, acc);
         }
-        __syncthreads();  // the next pass overwrites xs
+        // the next pass overwrites xs: every LDS read above has been consumed
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
     }
     part[slice][q] = acc;
     __syncthreads();
