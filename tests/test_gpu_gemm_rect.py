@@ -102,7 +102,7 @@ def test_forced_tiles(ax, tile):
                           oracle.gemm(ai, bi))
 
 
-@pytest.mark.parametrize("tile", ["256", "128", "256w4"])
+@pytest.mark.parametrize("tile", ["256", "128", "256w4", "64"])
 @pytest.mark.parametrize("k", [1, 16, 32, 33, 64, 65, 96])
 def test_forced_tiles_short_k(ax, tile, k):
     # bf16x3 K loops of two, four or six 16-element steps: the ends of the
