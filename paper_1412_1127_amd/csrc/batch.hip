@@ -32,14 +32,14 @@ constexpr int BT = 256;              // threads per workgroup (both kernels)
 constexpr int WG_PER_CU = 2;         // persistent workgroups per CU (LDS: 2 x 72 KB)
 constexpr uint32_t UNIT_RED = 0x80000000u;
 
-// Tile variants the persistent kernel carries: T128 and T64, both with
-// first-product look-ahead, six products (FULL6).  More variants in one kernel
+// Tile variants the persistent kernel carries: T128 (first-product
+// look-ahead) and T64, six products (FULL6).  More variants in one kernel
 // push its register need past the 256 that two wavefronts per SIMD allow.
 #define ACCX_T128(NP, PLIST) false, 3, 128, 128, 32, 2, 2, 3, NP, PLIST, 1, 2
-#define ACCX_T64(NP, PLIST) false, 3, 64, 64, 32, 2, 2, 3, NP, PLIST, 1, 2
+#define ACCX_T64(NP, PLIST) false, 3, 64, 64, 64, 2, 2, 2, NP, PLIST, 1
 
 constexpr int LDS_T128_FULL = gemm_lds_bytes<128, 128, 32, 3, 6, PL_FULL6>();
-constexpr int LDS_T64_FULL = gemm_lds_bytes<64, 64, 32, 3, 6, PL_FULL6>();
+constexpr int LDS_T64_FULL = gemm_lds_bytes<64, 64, 64, 2, 6, PL_FULL6>();
 constexpr int LDS_MAX = LDS_T128_FULL > LDS_T64_FULL ? LDS_T128_FULL : LDS_T64_FULL;
 static_assert(LDS_MAX * WG_PER_CU <= 160 * 1024, "persistent kernel LDS");
 

@@ -560,8 +560,7 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restric
 //           two workgroups per CU that do not share barriers.
 //  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3);
 //           first-product look-ahead for bf16x3.
-//  T64       64 x 64,  4 waves (2x2), 32 B, 3 stages, first-product
-//           look-ahead (bf16x3); 64 B, 2 stages (int8, several planes).
+//  T64       64 x 64,  4 waves (2x2), 64 B, 2 stages (several int8 planes).
 //  T256W4   256 x 256, 4 waves (2x2, 128 x 128 each), 32 B / 64 B, 3
 //           stages: a third less LDS read traffic per matrix instruction
 //           than T256, one wavefront per SIMD, accumulators in AGPRs; for
@@ -614,11 +613,7 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
                            PL, NACC, INT8 ? 0 : 2>(g, s);
     default: break;
     }
-    // bf16x3: 32-byte steps in three stages with first-product look-ahead
-    if constexpr (!INT8)
-        return launch_tile<INT8, P, 64, 64, 32, 2, 2, 3, NPROD, PL, NACC, (NPROD > 1 ? 2 : 0)>(g, s);
-    else
-        return launch_tile<INT8, P, 64, 64, 64, 2, 2, 2, NPROD, PL, NACC>(g, s);
+    return launch_tile<INT8, P, 64, 64, 64, 2, 2, 2, NPROD, PL, NACC>(g, s);
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
