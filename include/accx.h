@@ -133,7 +133,9 @@ typedef struct acc_region_s *acc_region; /* opaque */
 #define ACC_TILE_256W4 0x50000u   /* 256 x 256 output tile, 4 wavefronts */
 
 /* ---- flags for acc_reduce_sum / accx_reduce_sum_dev --------------------- */
-#define ACC_REDUCE_FAST 0x0u  /* single pass, last-block-done final stage */
+#define ACC_REDUCE_FAST 0x0u  /* streaming pass (grid-stride 16-byte loads, one partial
+                                 per workgroup), then a one-workgroup launch that
+                                 adds the partials in index order */
 #define ACC_REDUCE_PLAIN 0x1u /* one element per thread + block tree, then a
                                  second one-block launch over the partials */
 
@@ -418,7 +420,9 @@ typedef struct {
 typedef struct {
     int64_t submitted, admitted, completed, rejected;
     int64_t regions_open, max_inflight, max_regions_open;
-    uint64_t budget_used, budget_peak;
+    uint64_t budget_used, budget_peak; /* device bytes of the blocks open regions hold (now, peak) */
+    uint64_t blocks_held, blocks_held_peak; /* device bytes the server holds, cached free blocks included:
+                                               never above the budget when one is set */
 } accx_server_stats_t;
 
 typedef struct accx_server_s *accx_server; /* opaque */

@@ -112,7 +112,8 @@ class accx_server_stats_t(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("rejected", ctypes.c_int64), ("regions_open", ctypes.c_int64), ("max_inflight", ctypes.c_int64),
                 ("max_regions_open", ctypes.c_int64), ("budget_used", ctypes.c_uint64),
-                ("budget_peak", ctypes.c_uint64)]
+                ("budget_peak", ctypes.c_uint64), ("blocks_held", ctypes.c_uint64),
+                ("blocks_held_peak", ctypes.c_uint64)]
 
 
 class acc_reduce_var(ctypes.Structure):

@@ -78,13 +78,14 @@ struct acc_region_s {
     acc_status err = ACC_OK;
     std::string err_msg;
     Workspace mm_work;            // matmul workspace
-    Workspace red_work;           // reduction workspace (zero-filled ticket)
+    Workspace red_work;           // fast reduction partials (any contents)
     Workspace red_plain_work;     // plain reduction partials
-    Workspace red_vars_work;      // reduction variables (zero-filled ticket)
+    Workspace red_vars_work;      // reduction-variable partials (any contents)
     void *dres = nullptr;         // device result slots (8 bytes each)
     uint64_t *hres = nullptr;     // pinned host staging for the slots
     int nslots = 0, used_slots = 0;
     std::vector<Pending> pending;
+    std::vector<hipEvent_t> waits;  // events this region's stream waits on (present ranges)
 };
 
 namespace {
@@ -296,7 +297,15 @@ acc_status validate_matmul(int t, int64_t len, uint32_t flags)
 }
 
 constexpr int64_t kMaxMN = 131072;  // rows of A, columns of B
-constexpr int64_t kMaxK = 65536;    // int8 digit products summed over k stay below 2^31
+// Longest sequential loop.  int32 path: a digit product is at most 2^14 in
+// magnitude, and shift group g (digit pairs with k+m = g) sums g+1 pairs per
+// element of k (g = 3 of four digits: 4 pairs), so its int32 accumulator can
+// pass 2^31 from k = 32768 on (4 * 2^14 * 2^15 = 2^31; 2^32 at k = 65536).
+// Group g enters C shifted left by 8g, so only its value modulo 2^(32-8g)
+// matters, and the matrix cores' integer accumulation wraps modulo 2^32
+// (two's complement, no saturation): the result stays exact modulo 2^32.
+// Group 0 (one pair) stays within 2^30 up to this limit.
+constexpr int64_t kMaxK = 65536;
 constexpr int64_t kMaxLd = (int64_t)1 << 31;
 
 acc_status validate_gemm(int t, const GemmShape &sh, uint32_t flags)
@@ -474,8 +483,12 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
     const uint32_t prec = flags & ACC_PREC_MASK;
     if (prec == ACC_PREC_AUTO) {
         // cheap pass, float64 probe per tile, then the three missing products
-        // on the tiles the probe marked (the others exit at once)
-        const int tile = resolve_tile(ACC_FLOAT32, sh, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
+        // on the tiles the probe marked (the others exit at once).  The tile
+        // is made concrete here: the correction reads the probe's records in
+        // the layout of this tile, which must not be left to a default that
+        // each launch would resolve on its own.
+        int tile = resolve_tile(ACC_FLOAT32, sh, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
+        if (!tile) tile = accx::default_tile(sh.m, sh.n);
         auto *rec = reinterpret_cast<accx::ProbeRecord *>(work + probe_offset(sh));
         e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, 3, false, tile, s, nullptr, sk);
         if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, sh, tile, probe_tau(), rec, s);
@@ -658,6 +671,8 @@ void free_region(acc_region_s *r)
     if (r->hres) (void)hipHostFree(r->hres);
     r->dres = nullptr;
     r->hres = nullptr;
+    for (hipEvent_t ev : r->waits) (void)hipEventDestroy(ev);
+    r->waits.clear();
     if (r->own_stream && r->stream) (void)hipStreamDestroy(r->stream);
     r->stream = nullptr;
 }
@@ -958,6 +973,26 @@ acc_status acc_data_begin(const acc_clause *cl, int ncl, void *hip_stream, acc_r
 
     for (const Plan &p : plan) {
         if (!p.fresh) {
+            // The mapping's contents are whatever the regions holding it have
+            // enqueued so far (its copy-in, kernels that write it): this
+            // region's stream waits for all of it before its own work.
+            for (acc_region_s *h : st.regions) {
+                if (h->stream == r->stream || std::find(h->keys.begin(), h->keys.end(), p.ref) == h->keys.end())
+                    continue;
+                hipEvent_t ev = nullptr;
+                hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (e == hipSuccess) e = hipEventRecord(ev, h->stream);
+                if (e == hipSuccess) e = hipStreamWaitEvent(r->stream, ev, 0);
+                if (ev) r->waits.push_back(ev);
+                if (e != hipSuccess) {
+                    s = fail_hip(e, "ordering after the regions holding a present range");
+                    const std::string msg = t_last_error;
+                    (void)hipStreamSynchronize(r->stream);
+                    free_region(r);
+                    delete r;
+                    return fail(s, msg);
+                }
+            }
             st.present[p.ref].refs++;
             r->keys.push_back(p.ref);
             continue;

@@ -63,7 +63,10 @@ struct Region {
 
 // Device block cache: a cached block serves a request when it is at most
 // twice the request's size; otherwise a block is allocated with hipMalloc.
-// Blocks are freed only when the server is destroyed.
+// `held` counts every byte the cache holds, in use or free.  Under a budget
+// the server charges each region the size of the block it was given and
+// frees cached blocks before an allocation would take `held` past the
+// budget, so the device memory the engine holds never exceeds it.
 struct BlockCache {
     std::multimap<size_t, void *> free;  // block size -> block
     std::unordered_map<void *, size_t> size;
@@ -74,11 +77,32 @@ struct BlockCache {
         const size_t mb = (size_t)1 << 20;
         return b <= mb ? (b + 4095) & ~(size_t)4095 : (b + mb - 1) & ~(mb - 1);
     }
-    void *take(size_t bytes)
+    // The size of the block take(bytes) would hand out, and whether it is a
+    // cached one (else a new allocation of that size).
+    size_t fit(size_t bytes, bool *cached) const
     {
         const size_t want = round(bytes);
         auto it = free.lower_bound(want);
-        if (it != free.end() && it->first <= 2 * want) {
+        *cached = it != free.end() && it->first <= 2 * want;
+        return *cached ? it->first : want;
+    }
+    // Free cached blocks, largest first, until held <= limit (or none is left).
+    void trim(uint64_t limit)
+    {
+        while (held > limit && !free.empty()) {
+            auto it = std::prev(free.end());
+            (void)hipFree(it->second);
+            held -= it->first;
+            size.erase(it->second);
+            free.erase(it);
+        }
+    }
+    // allow_cached = false: a new block of round(bytes) bytes
+    void *take(size_t bytes, bool allow_cached = true)
+    {
+        const size_t want = round(bytes);
+        auto it = free.lower_bound(want);
+        if (allow_cached && it != free.end() && it->first <= 2 * want) {
             void *p = it->second;
             free.erase(it);
             return p;
@@ -86,13 +110,7 @@ struct BlockCache {
         void *p = nullptr;
         if (hipMalloc(&p, want) != hipSuccess) {
             (void)hipGetLastError();
-            // drop every cached block and retry once
-            for (auto &kv : free) {
-                (void)hipFree(kv.second);
-                held -= size[kv.second];
-                size.erase(kv.second);
-            }
-            free.clear();
+            trim(0);  // drop every cached block and retry once
             if (hipMalloc(&p, want) != hipSuccess) {
                 (void)hipGetLastError();
                 return nullptr;
@@ -101,6 +119,11 @@ struct BlockCache {
         size[p] = want;
         held += want;
         return p;
+    }
+    size_t block_size(void *p) const
+    {
+        auto it = size.find(p);
+        return it == size.end() ? 0 : it->second;
     }
     void give(void *p)
     {
@@ -217,17 +240,17 @@ void complete(accx_server_s *sv, const accx_request &r, acc_status status, doubl
 }
 
 // Open the region of first request r on stream s: allocate and copy in.
-acc_status open_region(accx_server_s *sv, const accx_request &r, size_t bytes, size_t work, hipStream_t s,
-                       Region &g)
+acc_status open_region(accx_server_s *sv, const accx_request &r, size_t bytes, size_t work, bool use_cached,
+                       hipStream_t s, Region &g)
 {
     g.op = r.op;
     g.dtype = r.dtype;
     g.n = r.n;
     g.flags = r.flags;
-    g.bytes = bytes;
     g.work_bytes = work;
-    g.mem = sv->blocks.take(bytes);
+    g.mem = sv->blocks.take(bytes, use_cached);
     if (!g.mem) return fail(ACC_ERR_OUT_OF_MEMORY, "device allocation failed");
+    g.bytes = sv->blocks.block_size(g.mem);  // the block's size is what the region holds
     hipError_t e = hipSuccess;
     char *p = static_cast<char *>(g.mem);
     if (r.op == ACC_SERVE_MATMUL) {
@@ -243,14 +266,16 @@ acc_status open_region(accx_server_s *sv, const accx_request &r, size_t bytes, s
         g.a = p;
         g.c = p + m;  // device result
         g.work = p + m + 256;
+        // the reduction's workspace needs no clearing: every call
+        // overwrites the partial sums it reads
         if (r.n > 0) e = hipMemcpyAsync(g.a, r.a, (size_t)r.n * 4, hipMemcpyHostToDevice, s);
-        // the fast reduction's ticket word must start at zero
-        if (e == hipSuccess && work) e = hipMemsetAsync(g.work, 0, work, s);
     }
     if (e != hipSuccess) return fail_hip(e, "region copy-in");
-    sv->used += bytes;
+    sv->used += g.bytes;
     sv->st.budget_used = sv->used;
     sv->st.budget_peak = std::max<uint64_t>(sv->st.budget_peak, sv->used);
+    sv->st.blocks_held = sv->blocks.held;
+    sv->st.blocks_held_peak = std::max<uint64_t>(sv->st.blocks_held_peak, sv->blocks.held);
     return ACC_OK;
 }
 
@@ -362,18 +387,27 @@ void admit(accx_server_s *sv)
             }
             size_t work = 0;
             const size_t bytes = footprint(r, &work);
-            if (sv->budget && bytes > sv->budget) {
+            if (sv->budget && BlockCache::round(bytes) > sv->budget) {
                 complete(sv, r, ACC_ERR_OUT_OF_MEMORY, t_submit, sv->now());
                 it = sv->queue.erase(it);
                 continue;
             }
-            if (sv->budget && sv->used + bytes > sv->budget) {
+            // charged: the block it would get (a cached one, or a new one,
+            // for which cached free blocks make room first)
+            bool cached = false;
+            size_t charge = sv->blocks.fit(bytes, &cached);
+            if (sv->budget && sv->used + charge > sv->budget && cached) {
+                cached = false;  // the cached block is too large to fit: allocate an exact one
+                charge = BlockCache::round(bytes);
+            }
+            if (sv->budget && sv->used + charge > sv->budget) {
                 first_blocked = true;  // first requests keep their order
                 ++it;
                 continue;
             }
+            if (sv->budget && !cached) sv->blocks.trim(sv->budget - charge);
             Region g;
-            acc_status s = open_region(sv, r, bytes, work, sv->streams[(size_t)slot], g);
+            acc_status s = open_region(sv, r, bytes, work, cached || !sv->budget, sv->streams[(size_t)slot], g);
             if (s != ACC_OK) {
                 if (g.mem) {
                     // its copy-in may be queued: park the block behind the stream
@@ -533,6 +567,7 @@ acc_status accx_server_stats(accx_server sv, accx_server_stats_t *out)
 {
     if (!sv || !servers().count(sv) || !out) return fail(ACC_ERR_INVALID_ARG, "unknown server or NULL output");
     std::lock_guard<std::mutex> lk(sv->mu);
+    sv->st.blocks_held = sv->blocks.held;
     *out = sv->st;
     return ACC_OK;
 }

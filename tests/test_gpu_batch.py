@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from _util import FP32_REL_FRO_TOL, SEED, rel_fro
+from _util import FP32_REL_FRO_TOL, SEED, rel_fro, tile_samples
 
 pytestmark = pytest.mark.gpu
 
@@ -147,10 +147,12 @@ def test_batch_rejects_bad_items(ax):
         ax.accx_batch_create([])
 
 
-def test_batching_workload_sampled(ax):
+def test_batching_workload_per_item(ax):
     # The batching workload: 512 float32 matmuls, LEN uniform over
     # {64, 128, ..., 1024}, and 256 reductions, n log-uniform in [2^16, 2^24].
-    import torch
+    # Every matmul is held to the bound on its own: the whole matrix up to
+    # LEN = 512, otherwise 64+ entries touching every 64 x 64 tile row and
+    # column (the finest tiling a batch runs).
     lens = synth.lens_uniform(512, [64 * k for k in range(1, 17)], SEED)
     ns = synth.log_uniform_int(256, 1 << 16, 1 << 24, SEED, synth.STREAM_X)
     bt = Batch(ax, list(lens), list(ns), SEED)
@@ -158,14 +160,17 @@ def test_batching_workload_sampled(ax):
     print(info, flush=True)
     ax.accx_batch_launch(bt.handle)
     cs, rs = bt.outputs()
-    g = synth.rng(SEED, 77)
-    got_all, ref_all = [], []
-    for (a, b, *_r, n), c in zip(bt.mats, cs):
-        ii, jj = g.integers(0, n, 8), g.integers(0, n, 8)
-        got_all.append(c[ii, jj])
-        ref_all.append(oracle.matmul_at(a, b, ii, jj))
-        assert np.isfinite(c).all()
-    assert rel_fro(np.concatenate(got_all), np.concatenate(ref_all)) <= FP32_REL_FRO_TOL
+    worst = 0.0
+    for q, ((a, b, *_r, n), c) in enumerate(zip(bt.mats, cs)):
+        assert np.isfinite(c).all(), q
+        if n <= 512:
+            err = rel_fro(c, oracle.matmul_f32(a, b))
+        else:
+            ii, jj = tile_samples(n, n, 64, 64, 64, stream=300 + q)
+            err = rel_fro(c[ii, jj], oracle.matmul_at(a, b, ii, jj))
+        worst = max(worst, err)
+        assert err <= FP32_REL_FRO_TOL, (q, n, err)
+    print("worst per-matmul rel_fro %.3g" % worst)
     for (x, _b, _r, n, init), got in zip(bt.reds, rs):
         ref = oracle.sum_f32(x, init)
         assert abs(got - ref) / ref <= 1e-5, (n, got, ref)

@@ -80,6 +80,8 @@ def test_small_budget_admission(ax):
     print({k: v for k, v in res.items() if k != "reduce_results"})
     assert res["completed_ok"] == len(wl.requests)
     assert res["server"]["budget_peak"] <= budget
+    # device memory actually held (blocks in use and cached free blocks)
+    assert 0 < res["server"]["blocks_held_peak"] <= budget
     ref, ref_out = _collect(ax, serve, wl, pools, alone=True)
     for k in outs:
         assert np.array_equal(outs[k], ref_out[k])
@@ -137,3 +139,14 @@ def test_serving_workload(ax):
     print({k: v for k, v in res.items() if k != "reduce_results"}, flush=True)
     assert res["completed_ok"] == len(wl.requests) and not bad
     assert res["latency_ms"]["p99"] > 0
+    # every reduction request against the oracle (init + the serial sum)
+    nred = 0
+    for q in wl.requests:
+        r = wl.regions[q.region]
+        if r.op != ax.ACC_SERVE_REDUCE:
+            continue
+        x, _ = _region_inputs(ax, pools, r)
+        ref = oracle.sum_f32(x, q.init)
+        assert abs(res["reduce_results"][q.tag] - ref) <= 1e-5 * abs(ref), q.tag
+        nred += 1
+    assert nred > 0
