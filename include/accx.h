@@ -114,6 +114,10 @@ typedef struct acc_region_s *acc_region; /* opaque */
 #define ACC_PREC_CHEAP3 0x20u /* 3 bf16 products: pairs with p+q <= 1 */
 #define ACC_PREC_FIVE 0x30u   /* 5 bf16 products: FULL6 without mid*mid
                                  (|mid*mid| <= 2^-16 |a||b|) */
+#define ACC_PREC_F32MFMA 0x40u /* no split: the float32 operands themselves on the
+                                  float32 matrix cores (v_mfma_f32_32x32x2_f32),
+                                  float32 accumulation: the plain float32 tiled
+                                  kernel the bf16x3 modes are measured against */
 #define ACC_PREC_MASK 0xF0u
 /* int32 on the tiled kernel: limb count (bits 8..11); 0 = probe max |x|. */
 #define ACC_LIMBS_SHIFT 8
@@ -152,6 +156,22 @@ ACCX_API acc_status acc_shutdown(void);
 
 /* Bytes currently charged against the budget (region arrays + workspaces). */
 ACCX_API acc_status acc_budget_used(uint64_t *bytes_out);
+
+/* Memory allocation, the third of the data functions that replace the data
+ * clauses (section 2.3, data-clause step: pointer exchange, copy in/out and
+ * memory allocation), taken from the caller: every device allocation the
+ * library makes (region arrays, library-owned workspaces, autotuner scratch,
+ * batch and serving memory) calls alloc(bytes, ctx) instead of hipMalloc,
+ * and frees with free_(ptr, ctx).  alloc returns device memory of the current
+ * device, aligned to 256 bytes, or NULL (the call then fails with
+ * OUT_OF_MEMORY).  The library frees a block only after the work that uses it
+ * has finished on the device.  Both NULL: back to hipMalloc / hipFree.  A
+ * block always goes back to the allocator that gave it, also after a later
+ * change.  The callbacks run on the thread of the library call that needs
+ * them, under the library's lock: they must not call into the library.
+ * Errors: INVALID_ARG (one of the two NULL). */
+ACCX_API acc_status accx_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*free_)(void *ptr, void *ctx),
+                                       void *ctx);
 
 /* ---- data regions (section 1.3, data-clause step of section 2.3) -------- */
 

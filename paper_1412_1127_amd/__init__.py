@@ -43,6 +43,7 @@ ACC_PREC_AUTO = 0x00
 ACC_PREC_FULL6 = 0x10
 ACC_PREC_CHEAP3 = 0x20
 ACC_PREC_FIVE = 0x30
+ACC_PREC_F32MFMA = 0x40
 ACC_LIMBS_SHIFT = 8
 ACC_ASYNC = 0x1000
 ACC_REDUCE_FAST = 0x0
@@ -139,6 +140,7 @@ _SIGS = {
     "acc_init": [ctypes.c_int, _u64],
     "acc_shutdown": [],
     "acc_budget_used": [ctypes.POINTER(_u64)],
+    "accx_set_allocator": [_vp, _vp, _vp],
     "acc_data_begin": [ctypes.POINTER(acc_clause), ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "acc_data_end": [_vp],
     "acc_wait": [_vp],
@@ -298,6 +300,51 @@ def acc_is_present(host, nbytes: int | None = None) -> bool:
     out = ctypes.c_int(0)
     _check(_lib.acc_is_present(_addr(host), int(nbytes), ctypes.byref(out)), "acc_is_present")
     return bool(out.value)
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = []   # the callbacks stay referenced while the library may call them
+
+
+def accx_set_allocator(alloc=None, free=None) -> None:
+    """Device memory for the library from Python callables: alloc(nbytes) ->
+    device address (int, 256-byte aligned; 0 on failure), free(address).
+    Both None: back to hipMalloc / hipFree."""
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        _check(_lib.accx_set_allocator(None, None, None), "accx_set_allocator")
+        return
+    fa = _ALLOC_FN(lambda nbytes, _ctx: int(alloc(int(nbytes)) or 0))
+    ff = _FREE_FN(lambda ptr, _ctx: free(int(ptr)))
+    _allocator_refs.append((fa, ff))
+    _check(_lib.accx_set_allocator(ctypes.cast(fa, _vp), ctypes.cast(ff, _vp), None), "accx_set_allocator")
+
+
+class TorchAllocator:
+    """Routes the library's device allocations through torch's caching
+    allocator: each block is a uint8 tensor kept alive until the library
+    frees it.  `live` holds the blocks the library currently owns."""
+
+    def __init__(self):
+        self.live = {}
+        self.allocs = 0
+        self.frees = 0
+
+    def alloc(self, nbytes: int) -> int:
+        t = torch.empty(max(1, nbytes), dtype=torch.uint8, device="cuda")
+        self.live[t.data_ptr()] = t
+        self.allocs += 1
+        return t.data_ptr()
+
+    def free(self, ptr: int) -> None:
+        self.live.pop(ptr)
+        self.frees += 1
+
+    def install(self) -> "TorchAllocator":
+        accx_set_allocator(self.alloc, self.free)
+        return self
 
 
 def accx_host_alloc(nbytes: int) -> int:

@@ -263,6 +263,85 @@ __global__ __launch_bounds__(256) void pack_bf16x3_pair(const float *__restrict_
     }
 }
 
+// ---- float32 operands for the float32 matrix cores: one plane of 4-byte
+// elements in the same unit layout (32 rows x 16 elements per unit, chunk c
+// of row r = elements 4c..4c+3 at c*512 + r*16).  A plain copy into the
+// layout; B^T goes through the LDS transpose (a 16-element K unit is one
+// staged tile of TP_ROWS = 16 rows of X).
+static_assert(TP_ROWS == 16, "one float32 K unit per staged tile");
+
+// Rows of A: one thread per (unit, row, chunk), work items id0, id0 + step, ...
+__device__ inline void pack_f32_range(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                      char *__restrict__ out, int64_t nrb, int64_t nkb, int64_t id0, int64_t step)
+{
+    const int64_t total = nrb * nkb * 128;
+    for (int64_t id = id0; id < total; id += step) {
+        const int64_t unit = id >> 7;
+        const int w = (int)(id & 127);
+        const int r = w >> 2, c = w & 3;
+        const int64_t rb = unit / nkb, kb = unit - rb * nkb;
+        const int64_t row = rb * 32 + r, k0 = kb * 16 + c * 4;
+        f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (row < R && k0 + 4 <= K && ((ld & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
+            v = *reinterpret_cast<const f32x4 *>(X + row * ld + k0);
+        } else if (row < R) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[t] = k0 + t < K ? X[row * ld + k0 + t] : 0.0f;
+        }
+        *reinterpret_cast<f32x4 *>(out + unit * PLANE_BYTES + c * 512 + r * 16) = v;
+    }
+}
+
+// B^T for column tile bx of X and K unit kb.
+__device__ inline void pack_f32_cols(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                     char *__restrict__ out, int64_t nrb, int64_t nkb, int64_t bx, int64_t kb,
+                                     uint32_t (*t)[TP_COLS])
+{
+    const int64_t rb0 = bx * (TP_COLS / 32);
+    stage_rows(reinterpret_cast<const uint32_t *>(X), R, K, ld, kb * 16, rb0 * 32, t);
+    __syncthreads();
+    // 8 units x 32 rows x 4 chunks of 4 elements
+#pragma unroll
+    for (int j = 0; j < 8 * 32 * 4 / 256; ++j) {
+        const int q = j * 256 + threadIdx.x;
+        const int r = q & 31, c = (q >> 5) & 3, u = q >> 7;
+        if (rb0 + u >= nrb) continue;
+        const f32x4 v = {__uint_as_float(t[4 * c][u * 32 + r]), __uint_as_float(t[4 * c + 1][u * 32 + r]),
+                         __uint_as_float(t[4 * c + 2][u * 32 + r]), __uint_as_float(t[4 * c + 3][u * 32 + r])};
+        *reinterpret_cast<f32x4 *>(out + ((rb0 + u) * nkb + kb) * PLANE_BYTES + c * 512 + r * 16) = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void pack_f32_a(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                                  char *__restrict__ out, int64_t nrb, int64_t nkb)
+{
+    pack_f32_range(X, R, K, ld, out, nrb, nkb, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+}
+
+// Grid: gbx column tiles of X per K unit.
+__global__ __launch_bounds__(256) void pack_f32_t(const float *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                                  char *__restrict__ out, int64_t nrb, int64_t nkb, int gbx)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
+    pack_f32_cols(X, R, K, ld, out, nrb, nkb, blockIdx.x % gbx, blockIdx.x / gbx, t);
+}
+
+// A and B^T in one launch: workgroups [0, ga) pack A, the others B.
+__global__ __launch_bounds__(256) void pack_f32_pair(const float *__restrict__ A, int64_t M, int64_t lda,
+                                                     char *__restrict__ pa, const float *__restrict__ B, int64_t N,
+                                                     int64_t ldb, char *__restrict__ pb, int64_t K, int ga, int gbx)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
+    const int64_t nkb = (K + 15) / 16;
+    if ((int)blockIdx.x < ga) {
+        pack_f32_range(A, M, K, lda, pa, (M + 31) / 32, nkb, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                       (int64_t)ga * 256);
+    } else {
+        const int64_t b = blockIdx.x - ga;
+        pack_f32_cols(B, N, K, ldb, pb, (N + 31) / 32, nkb, b % gbx, b / gbx, t);
+    }
+}
+
 // int8 digit planes of B^T for column tile bx of X and part by % I8_SPLIT of
 // the 64-element K unit by / I8_SPLIT; returns the thread's max |x|.
 __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
@@ -350,7 +429,7 @@ __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ 
 
 
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          int LAM>
+          int LAM, bool F32MM>
 __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 {
     __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPROD, PL>()];
@@ -371,9 +450,9 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
         const int64_t off = kb0 * (int64_t)P * PLANE_BYTES;
         h.A = g.A + off;
         h.B = g.B + off;
-        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM>(h, tm, tn, lds);
+        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM>(h, tm, tn, lds);
     } else {
-        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM>(g, tm, tn, lds);
+        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM>(g, tm, tn, lds);
     }
 }
 
@@ -567,7 +646,7 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restric
 //           bf16x3 a look-ahead loop (fragments of the next step read during
 //           this step's matrix instructions).
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          int LAM = 0>
+          int LAM = 0, bool F32MM = false>
 hipError_t launch_tile(GemmArgs g, hipStream_t s)
 {
     g.tiles_m = (int)((g.M + BM - 1) / BM);
@@ -580,7 +659,7 @@ hipError_t launch_tile(GemmArgs g, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     const dim3 grid((unsigned)(g.tiles_m * g.tiles_n * (g.ksplit > 1 ? g.ksplit : 1)));
-    hipLaunchKernelGGL((gemm_packed<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM>), grid,
+    hipLaunchKernelGGL((gemm_packed<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM>), grid,
                        dim3(WGM * WGN * 64), 0, s, g);
     return hipGetLastError();
 }
@@ -614,6 +693,27 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
     default: break;
     }
     return launch_tile<INT8, P, 64, 64, 64, 2, 2, 2, NPROD, PL, NACC>(g, s);
+}
+
+// float32 matrix cores: one plane of 4-byte elements, 64-byte K steps (16
+// elements: two fragment pairs, eight matrix instructions per 32 x 32 block),
+// plain loop.  The float32 instructions are sixteen times slower per byte of
+// operand than the bf16 ones, so the loads hide behind them without
+// look-ahead.
+hipError_t run_gemm_f32mm(int tile, const GemmArgs &g, hipStream_t s)
+{
+    constexpr uint64_t PL1 = prod(0, 0, 0, 0);
+    switch (tile) {
+    case GEMM_TILE_256:
+    case GEMM_TILE_256W4:
+        return launch_tile<false, 1, 256, 256, 64, 2, 4, 3, 1, PL1, 1, 0, true>(g, s);
+    case GEMM_TILE_256x128:
+        return launch_tile<false, 1, 256, 128, 64, 2, 2, 3, 1, PL1, 1, 0, true>(g, s);
+    case GEMM_TILE_128:
+        return launch_tile<false, 1, 128, 128, 64, 2, 2, 3, 1, PL1, 1, 0, true>(g, s);
+    default: break;
+    }
+    return launch_tile<false, 1, 64, 64, 64, 2, 2, 2, 1, PL1, 1, 0, true>(g, s);
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -741,6 +841,34 @@ hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const i
     return hipGetLastError();
 }
 
+hipError_t launch_pack_f32(const float *x, int64_t rows, int64_t k, int64_t ld, bool trans, void *out, hipStream_t s)
+{
+    const int64_t nrb = cdiv(rows, 32), nkb = cdiv(k, 16);
+    if (nrb * nkb == 0) return hipSuccess;
+    tmark("pack_f32", s, true);
+    if (trans)
+        hipLaunchKernelGGL(pack_f32_t, dim3((unsigned)(cdiv(rows, TP_COLS) * nkb)), dim3(256), 0, s, x, rows, k, ld,
+                           static_cast<char *>(out), nrb, nkb, (int)cdiv(rows, TP_COLS));
+    else
+        hipLaunchKernelGGL(pack_f32_a, dim3(pack_grid(nrb * nkb)), dim3(256), 0, s, x, rows, k, ld,
+                           static_cast<char *>(out), nrb, nkb);
+    tmark("pack_f32", s, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_f32_pair(const float *a, int64_t m, int64_t lda, const float *b, int64_t n, int64_t ldb,
+                                int64_t k, void *pa, void *pb, hipStream_t s)
+{
+    const int64_t nkb = cdiv(k, 16), ua = cdiv(m, 32) * nkb;
+    const int64_t ga = ua > 0 ? pack_grid(ua) : 0, gbx = cdiv(n, TP_COLS), gb = gbx * nkb;
+    if (ga + gb == 0) return hipSuccess;
+    tmark("pack_f32", s, true);
+    hipLaunchKernelGGL(pack_f32_pair, dim3((unsigned)(ga + gb)), dim3(256), 0, s, a, m, lda, static_cast<char *>(pa),
+                       b, n, ldb, static_cast<char *>(pb), k, (int)ga, (int)std::max<int64_t>(gbx, 1));
+    tmark("pack_f32", s, false);
+    return hipGetLastError();
+}
+
 void tile_dims(int tile, int64_t m, int64_t n, int &bm, int &bn)
 {
     const int t = tile ? tile : default_tile(m, n);
@@ -854,6 +982,32 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
     else
         e = hipErrorInvalidValue;
     tmark(tname, s, false);
+    return e;
+}
+
+hipError_t launch_gemm_f32mm(const void *pa, const void *pb, float *c, const GemmShape &sh, int tile, hipStream_t s,
+                              const SplitK &sk)
+{
+    if (sh.m <= 0 || sh.n <= 0) return hipSuccess;
+    GemmArgs g{};
+    g.A = static_cast<const char *>(pa);
+    g.B = static_cast<const char *>(pb);
+    g.C = c;
+    g.M = sh.m;
+    g.N = sh.n;
+    g.ldc = sh.ldc;
+    g.nkb = cdiv(sh.k * 4, 64);
+    g.nrb_a = cdiv(sh.m, 32);
+    g.nrb_b = cdiv(sh.n, 32);
+    const int t = tile ? tile : default_tile(sh.m, sh.n);
+    if (sk.parts > 1) {
+        int bm, bn;
+        tile_dims(t, sh.m, sh.n, bm, bn);
+        set_split(g, sk, (256 + 4 * cdiv(sh.m, bm) * cdiv(sh.n, bn) + 255) / 256 * 256);
+    }
+    tmark("gemm_f32mm", s, true);
+    const hipError_t e = run_gemm_f32mm(t, g, s);
+    tmark("gemm_f32mm", s, false);
     return e;
 }
 

@@ -118,6 +118,14 @@ hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, cons
 int probe_tiles(int tile, int64_t m, int64_t n);
 // The configuration the size heuristic picks for an m x n result.
 int default_tile(int64_t m, int64_t n);
+// float32 -> one plane of float32 elements in the packed layout (16 elements
+// per 64-byte unit row), for the float32 matrix cores; trans as above.
+hipError_t launch_pack_f32(const float *x, int64_t rows, int64_t k, int64_t ld, bool trans, void *out, hipStream_t s);
+hipError_t launch_pack_f32_pair(const float *a, int64_t m, int64_t lda, const float *b, int64_t n, int64_t ldb,
+                                int64_t k, void *pa, void *pb, hipStream_t s);
+// C = A B on the float32 matrix cores from float32-packed operands.
+hipError_t launch_gemm_f32mm(const void *pa, const void *pb, float *c, const GemmShape &sh, int tile, hipStream_t s,
+                             const SplitK &sk = SplitK());
 // decide (optional): runs only if the device-side digit count is 1 (limbs =
 // 1) or more than 1 (limbs = 4).
 hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,

@@ -140,6 +140,30 @@ template <> struct Mma<true> {
     }
 };
 
+// float32 on the float32 matrix cores (v_mfma_f32_32x32x2_f32: K = 2 per
+// instruction, one float of A and one of B per lane).  A fragment is the
+// 16-byte chunk a lane reads from the packed layout: four consecutive k of
+// one row, the lanes of the upper half one chunk further along K.  The four
+// instructions of one fragment pair take its elements 0..3 in turn, so
+// instruction j sums, for each row and column, k = 8q + j (lower half) and
+// k = 8q + 4 + j (upper half): A and B pair the same k, and the eight k of
+// the chunk pair are covered once each.
+struct MmaF32 {
+    using Frag = f32x4;
+    using Acc = f32x16;
+    using Elem = float;
+    __device__ static inline Acc run(Frag a, Frag b, Acc c)
+    {
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], c, 0, 0, 0);
+    }
+};
+
+template <bool C, typename T, typename F> struct Pick { using type = T; };
+template <typename T, typename F> struct Pick<false, T, F> { using type = F; };
+
 // Product list: entry t = (plane of A, plane of B, accumulator) in 6 bits.
 constexpr uint64_t prod(int t, int p, int q, int acc)
 {
@@ -301,11 +325,14 @@ constexpr int gemm_lds_bytes()
 // hides behind the matrix work of the previous one even with a single
 // wavefront per SIMD.  It costs a second fragment register set and one step
 // of global-load lead (needs NS >= 3).
+// F32MM: float32 operands (one plane of 4-byte elements) on the float32
+// matrix cores (MmaF32) instead of bf16 planes; plain loop only.
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          int LAM = 0>
+          int LAM = 0, bool F32MM = false>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &g, int tm, int tn, char *lds)
 {
-    using M = Mma<INT8>;
+    using M = typename Pick<F32MM, MmaF32, Mma<INT8>>::type;
+    static_assert(!F32MM || (!INT8 && LAM == 0 && P == 1), "float32 matrix cores: one plane, plain loop");
     using Frag = typename M::Frag;
     using Acc = typename M::Acc;
     constexpr int WAVES = WGM * WGN;

@@ -30,6 +30,7 @@
 
 #include "../../include/accx.h"
 #include "kernels.h"
+#include "runtime_internal.h"
 
 namespace {
 
@@ -140,6 +141,66 @@ size_t elem_bytes(int t) { return (t == ACC_FLOAT64 || t == ACC_INT64) ? 8 : 4; 
 bool valid_dtype(int t) { return t == ACC_FLOAT32 || t == ACC_INT32 || t == ACC_FLOAT64 || t == ACC_INT64; }
 bool matmul_dtype(int t) { return t == ACC_FLOAT32 || t == ACC_INT32; }
 
+// Where device memory comes from: hipMalloc, or the caller's allocator
+// (accx_set_allocator).  Each block remembers the allocator that gave it,
+// so that it goes back there even after the allocator has been changed.
+struct Allocator {
+    void *(*alloc)(size_t, void *) = nullptr;  // nullptr: hipMalloc / hipFree
+    void (*free)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+
+Allocator &user_allocator()
+{
+    static auto *a = new Allocator();
+    return *a;
+}
+
+std::map<void *, Allocator> &user_blocks()  // blocks the caller's allocator gave
+{
+    static auto *m = new std::map<void *, Allocator>();
+    return *m;
+}
+
+// Device memory from the current allocator, not charged to any budget.
+acc_status raw_alloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    const Allocator a = user_allocator();
+    if (a.alloc) {
+        void *q = a.alloc(bytes, a.ctx);
+        if (!q) return fail(ACC_ERR_OUT_OF_MEMORY, "the caller's allocator returned NULL");
+        if ((uintptr_t)q & 255u) {
+            a.free(q, a.ctx);
+            return fail(ACC_ERR_OUT_OF_MEMORY, "the caller's allocator returned memory not aligned to 256 bytes");
+        }
+        user_blocks()[q] = a;
+        *p = q;
+        return ACC_OK;
+    }
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(ACC_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return ACC_OK;
+}
+
+void raw_free(void *p)
+{
+    if (!p) return;
+    auto &m = user_blocks();
+    auto it = m.find(p);
+    if (it != m.end()) {
+        const Allocator a = it->second;
+        m.erase(it);
+        a.free(p, a.ctx);
+        return;
+    }
+    (void)hipFree(p);
+}
+
 // Device allocation charged against the budget.
 acc_status dev_alloc(void **p, size_t bytes)
 {
@@ -152,12 +213,8 @@ acc_status dev_alloc(void **p, size_t bytes)
                                                std::to_string(st.budget));
     if (fault_hit(st.fault.allocs, st.fault.alloc_at))
         return fail(ACC_ERR_OUT_OF_MEMORY, "injected allocation fault (ACCX_FAULT)");
-    const hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return fail(ACC_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
+    acc_status s = raw_alloc(p, bytes);
+    if (s != ACC_OK) return s;
     st.used += bytes;
     return ACC_OK;
 }
@@ -165,7 +222,7 @@ acc_status dev_alloc(void **p, size_t bytes)
 void dev_free(void *p, size_t bytes)
 {
     if (!p) return;
-    (void)hipFree(p);
+    raw_free(p);
     State &st = S();
     st.used = st.used >= bytes ? st.used - bytes : 0;
 }
@@ -280,7 +337,8 @@ acc_status validate_flags(uint32_t flags)
     const uint32_t k = flags & ACC_KERNEL_MASK;
     if (k > ACC_KERNEL_TILED) return fail(ACC_ERR_INVALID_ARG, "unknown kernel selector");
     const uint32_t p = flags & ACC_PREC_MASK;
-    if (p != ACC_PREC_AUTO && p != ACC_PREC_FULL6 && p != ACC_PREC_CHEAP3 && p != ACC_PREC_FIVE)
+    if (p != ACC_PREC_AUTO && p != ACC_PREC_FULL6 && p != ACC_PREC_CHEAP3 && p != ACC_PREC_FIVE &&
+        p != ACC_PREC_F32MFMA)
         return fail(ACC_ERR_INVALID_ARG, "unknown precision selector");
     const uint32_t nl = (flags & ACC_LIMBS_MASK) >> ACC_LIMBS_SHIFT;
     if (nl > 4) return fail(ACC_ERR_INVALID_ARG, "limb count must be 0 (probe) or 1..4");
@@ -335,6 +393,12 @@ constexpr size_t kMaxabsBytes = 256;  // int path: two max|x| words, padded
 
 int flag_limbs(uint32_t flags) { return (int)((flags & ACC_LIMBS_MASK) >> ACC_LIMBS_SHIFT); }
 
+bool is_f32mm(uint32_t flags) { return (flags & ACC_PREC_MASK) == ACC_PREC_F32MFMA; }
+
+// Bytes per element of the packed operands the tiled kernel reads: bf16
+// planes, float32 (float32 matrix cores) or int8 digits.
+int kelem_bytes(int t, uint32_t flags) { return t == ACC_INT32 ? 1 : is_f32mm(flags) ? 4 : 2; }
+
 // ACC_PREC_AUTO: relative Frobenius error a tile may show on the probe's 64
 // samples and still keep the cheap (three-product) result (ACCX_PROBE_TAU
 // overrides).  7e-6 = 0.7 x the 1e-5 bound of the float32 path: a tile whose
@@ -386,7 +450,7 @@ SplitPlan split_plan(int t, const GemmShape &sh, uint32_t flags)
     uint32_t f = flags;
     if (t == ACC_FLOAT32 && (flags & ACC_PREC_MASK) == ACC_PREC_AUTO) f = (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3;
     p.tile = resolve_tile(t, sh, f, t == ACC_INT32 ? 1 : 0);
-    const int64_t nkb = t == ACC_FLOAT32 ? (sh.k * 2 + 63) / 64 : (sh.k + 63) / 64;
+    const int64_t nkb = (sh.k * kelem_bytes(t, flags) + 63) / 64;
     p.parts = accx::split_k_parts(p.tile, sh.m, sh.n, nkb);
     p.bytes = accx::split_k_bytes(p.tile, sh.m, sh.n, p.parts);
     return p;
@@ -395,6 +459,7 @@ SplitPlan split_plan(int t, const GemmShape &sh, uint32_t flags)
 size_t matmul_ws_base(int t, const GemmShape &sh, uint32_t flags)
 {
     if (is_plain(flags) || sh.m == 0 || sh.n == 0) return 0;
+    if (t == ACC_FLOAT32 && is_f32mm(flags)) return packed_pair(sh, 4, 1);
     if (t == ACC_FLOAT32 && (flags & ACC_PREC_MASK) == ACC_PREC_AUTO) return probe_offset(sh) + probe_bytes_max(sh);
     if (t == ACC_FLOAT32) return packed_pair(sh, 2, 3);
     if (flag_limbs(flags)) return kMaxabsBytes + packed_pair(sh, 1, flag_limbs(flags));
@@ -424,6 +489,7 @@ int tune_variant(int t, uint32_t flags, int limbs)
     if (t == ACC_FLOAT32) {
         const uint32_t p = flags & ACC_PREC_MASK;
         // AUTO is timed as its dominant kernel, the three-product pass
+        if (p == ACC_PREC_F32MFMA) return 32;
         return (p == ACC_PREC_CHEAP3 || p == ACC_PREC_AUTO) ? 3 : p == ACC_PREC_FIVE ? 5 : 6;
     }
     return limbs;
@@ -476,6 +542,14 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
                          size_t work_bytes, hipStream_t s)
 {
     const accx::SplitK sk = split_for(ACC_FLOAT32, sh, flags, work, work_bytes);
+    if (is_f32mm(flags)) {
+        char *pa = work, *pbt = work + accx::packed_bytes(sh.m, sh.k, 4, 1);
+        hipError_t e = accx::launch_pack_f32_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, pa, pbt, s);
+        if (e != hipSuccess) return fail_hip(e, "pack (float32) launch");
+        return check_launch(
+            accx::launch_gemm_f32mm(pa, pbt, c, sh, resolve_tile(ACC_FLOAT32, sh, flags, 0), s, sk),
+            "gemm (float32 matrix cores) launch");
+    }
     const size_t pb = accx::packed_bytes(sh.m, sh.k, 2, 3);
     char *pa = work, *pbt = work + pb;
     hipError_t e = accx::launch_pack_bf16x3_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, pa, pbt, s);
@@ -896,6 +970,18 @@ acc_status acc_budget_used(uint64_t *bytes_out)
     std::lock_guard<std::recursive_mutex> lk(st.mu);
     if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
     *bytes_out = st.used;
+    return ACC_OK;
+}
+
+acc_status accx_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void *), void *ctx)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    if (!alloc != !free_) return fail(ACC_ERR_INVALID_ARG, "give both alloc and free, or neither");
+    Allocator &a = user_allocator();
+    a.alloc = alloc;
+    a.free = free_;
+    a.ctx = alloc ? ctx : nullptr;
     return ACC_OK;
 }
 
@@ -1477,12 +1563,12 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
     // one scratch input serves as A (m x k) and as B (k x n)
     const int64_t xel = std::max<int64_t>(1, std::max(sh.m * sh.k, sh.k * sh.n));
     const size_t xbytes = (size_t)xel * 4, cbytes = (size_t)std::max<int64_t>(1, sh.m * sh.n) * 4;
-    const size_t pka = (t == ACC_FLOAT32) ? accx::packed_bytes(sh.m, sh.k, 2, 3)
-                                          : accx::packed_bytes(sh.m, sh.k, 1, limbs);
-    const size_t pk2b = std::max<size_t>(256, pka + ((t == ACC_FLOAT32) ? accx::packed_bytes(sh.n, sh.k, 2, 3)
-                                                                      : accx::packed_bytes(sh.n, sh.k, 1, limbs)));
+    const bool f32mm = t == ACC_FLOAT32 && is_f32mm(flags);
+    const int eb = kelem_bytes(t, flags), planes = t == ACC_INT32 ? limbs : f32mm ? 1 : 3;
+    const size_t pka = accx::packed_bytes(sh.m, sh.k, eb, planes);
+    const size_t pk2b = std::max<size_t>(256, pka + accx::packed_bytes(sh.n, sh.k, eb, planes));
     // each candidate runs with the split K the library would give it
-    const int64_t nkb = t == ACC_FLOAT32 ? (sh.k * 2 + 63) / 64 : (sh.k + 63) / 64;
+    const int64_t nkb = (sh.k * eb + 63) / 64;
     size_t splitb = 0;
     for (int tile = 1; tile < accx::GEMM_TILE_COUNT; ++tile)
         if (limbs <= 1)
@@ -1504,7 +1590,12 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
     // (one limb); constant operands run the matrix cores at a higher clock
     // than real data and would mislead the choice.
     if ((he = accx::launch_fill_hash(x, xel, t == ACC_INT32, stream)) != hipSuccess) goto hip_out;
-    if (t == ACC_FLOAT32) {
+    if (f32mm) {
+        he = accx::launch_pack_f32(static_cast<float *>(x), sh.m, sh.k, sh.k, false, pk2, stream);
+        if (he == hipSuccess)
+            he = accx::launch_pack_f32(static_cast<float *>(x), sh.n, sh.k, sh.n, true, static_cast<char *>(pk2) + pka,
+                                       stream);
+    } else if (t == ACC_FLOAT32) {
         he = accx::launch_pack_bf16x3(static_cast<float *>(x), sh.m, sh.k, sh.k, false, pk2, stream);
         if (he == hipSuccess)
             he = accx::launch_pack_bf16x3(static_cast<float *>(x), sh.n, sh.k, sh.n, true,
@@ -1527,6 +1618,9 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
                 sk.parts = accx::split_k_parts(tile, sh.m, sh.n, nkb);
                 sk.work = spl;
             }
+            if (f32mm)
+                return accx::launch_gemm_f32mm(pk2, static_cast<char *>(pk2) + pka, static_cast<float *>(c), csh,
+                                               tile, stream, sk);
             return (t == ACC_FLOAT32)
                        ? accx::launch_gemm_bf16x3(pk2, static_cast<char *>(pk2) + pka, static_cast<float *>(c), csh,
                                                   tune_variant(t, flags, 0), false, tile, stream, nullptr, sk)
@@ -1725,6 +1819,16 @@ acc_status reduce(int t, const void *x, int64_t n, const void *init, void *resul
     return run_reduce(t, x, n, init, result, flags, work, s);
 }
 std::recursive_mutex &lock() { return S().mu; }
+acc_status device_alloc(void **p, size_t bytes)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    return raw_alloc(p, bytes);
+}
+void device_free(void *p)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    raw_free(p);
+}
 }  // namespace rt
 }  // namespace accx
 

@@ -25,5 +25,10 @@ acc_status matmul(int t, const void *a, const void *b, void *c, int64_t len, uin
 acc_status reduce(int t, const void *x, int64_t n, const void *init, void *result, uint32_t flags, void *work,
                   hipStream_t s);
 std::recursive_mutex &lock();  // the runtime's state lock
+// Device memory from the allocator in effect (accx_set_allocator, else
+// hipMalloc), not charged to the library's budget; device_free returns a
+// block to the allocator that gave it.
+acc_status device_alloc(void **p, size_t bytes);
+void device_free(void *p);
 }  // namespace rt
 }  // namespace accx

@@ -62,7 +62,8 @@ struct Region {
 };
 
 // Device block cache: a cached block serves a request when it is at most
-// twice the request's size; otherwise a block is allocated with hipMalloc.
+// twice the request's size; otherwise a block is allocated (hipMalloc, or the
+// caller's allocator when one is set).
 // `held` counts every byte the cache holds, in use or free.  Under a budget
 // the server charges each region the size of the block it was given and
 // frees cached blocks before an allocation would take `held` past the
@@ -91,7 +92,7 @@ struct BlockCache {
     {
         while (held > limit && !free.empty()) {
             auto it = std::prev(free.end());
-            (void)hipFree(it->second);
+            accx::rt::device_free(it->second);
             held -= it->first;
             size.erase(it->second);
             free.erase(it);
@@ -108,13 +109,9 @@ struct BlockCache {
             return p;
         }
         void *p = nullptr;
-        if (hipMalloc(&p, want) != hipSuccess) {
-            (void)hipGetLastError();
+        if (accx::rt::device_alloc(&p, want) != ACC_OK) {
             trim(0);  // drop every cached block and retry once
-            if (hipMalloc(&p, want) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
+            if (accx::rt::device_alloc(&p, want) != ACC_OK) return nullptr;
         }
         size[p] = want;
         held += want;
@@ -131,7 +128,7 @@ struct BlockCache {
     }
     void release_all()
     {
-        for (auto &kv : size) (void)hipFree(kv.first);
+        for (auto &kv : size) accx::rt::device_free(kv.first);
         free.clear();
         size.clear();
         held = 0;
@@ -331,13 +328,15 @@ void retire(accx_server_s *sv)
         }
         acc_status status = f.status;
         if (q != hipSuccess && status == ACC_OK) status = fail_hip(q, "request");
+        // The result first, whatever became of the region: the flights are
+        // scanned in no particular order, so the region's last request may
+        // have retired (and closed it) earlier in this same pass.
+        if (status == ACC_OK && f.r.op == ACC_SERVE_REDUCE) std::memcpy(f.r.c, sv->staging + f.slot, 4);
         auto it = sv->regions.find(f.r.region);
         if (it != sv->regions.end()) {
             Region &g = it->second;
             if (g.last == f.done) g.last = nullptr;
             g.inflight--;
-            if (status == ACC_OK && f.r.op == ACC_SERVE_REDUCE)
-                std::memcpy(f.r.c, sv->staging + f.slot, 4);
             if (f.r.last || (g.close_on_idle && g.inflight == 0)) {
                 // the last request's event has fired: nothing queued touches
                 // the region's memory any more

@@ -65,7 +65,7 @@ def test_no_device_no_fallback():
 def test_argument_validation_without_device():
     import paper_1412_1127_amd as ax
     for bad in [(ax.ACC_FLOAT32, 0, 0), (ax.ACC_FLOAT32, 65537, 0), (7, 16, 0),
-                (ax.ACC_FLOAT32, 16, 0x4), (ax.ACC_FLOAT32, 16, 0x40), (ax.ACC_INT32, 16, ax.ACC_LIMBS(5))]:
+                (ax.ACC_FLOAT32, 16, 0x4), (ax.ACC_FLOAT32, 16, 0x50), (ax.ACC_INT32, 16, ax.ACC_LIMBS(5))]:
         with pytest.raises(ax.AccxError) as e:
             ax.accx_matmul_workspace_size(*bad)
         assert e.value.status == ax.ACC_ERR_INVALID_ARG, bad
@@ -75,6 +75,15 @@ def test_argument_validation_without_device():
     assert e.value.status == ax.ACC_ERR_INVALID_ARG
     assert ax.accx_reduce_workspace_size(ax.ACC_FLOAT32, 1 << 20, 0) > 256
     assert ax.accx_reduce_workspace_size(ax.ACC_INT32, 1000, ax.ACC_REDUCE_PLAIN) == 4 * 4
+
+
+def test_set_allocator_needs_both_or_neither():
+    import ctypes
+
+    import paper_1412_1127_amd as ax
+    fa = ax._ALLOC_FN(lambda n, c: 0)
+    assert ax._lib.accx_set_allocator(ctypes.cast(fa, ctypes.c_void_p), None, None) == ax.ACC_ERR_INVALID_ARG
+    ax.accx_set_allocator(None, None)                  # back to hipMalloc: always valid
 
 
 def test_gemm_shape_validation_without_device():
