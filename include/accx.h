@@ -344,6 +344,26 @@ ACCX_API acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, cons
                                     const void *init, void *dResult, uint32_t flags, void *dWork, size_t work_bytes,
                                     void *hip_stream);
 
+/* accx_reduce_dev for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bitwise those of accx_reduce_dev with
+ * the same t, n, vars and flags), but the per-workgroup partials go to a
+ * static device array of 128 KiB per GPU instead of a workspace: the call
+ * allocates nothing (no hipMalloc / hipFree, no library allocation), and each
+ * GPU the library runs on holds that array until the process ends.  Its
+ * device address is taken once per device by acc_init.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (different streams
+ * or threads with no ordering between them) race and give wrong results;
+ * calls ordered on one stream are safe (no contents need to start at zero;
+ * each call overwrites the partials it reads).  Limit: 128 KiB of partials,
+ * which holds every ACC_REDUCE_FAST reduction (any n, 1..4 variables) and
+ * ACC_REDUCE_PLAIN for n <= 8388608; a larger need is INVALID_ARG.
+ * (With accx_timing_enable(1) the timing facility still creates its host
+ * event objects.)  Errors: INVALID_ARG, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_reduce_dev_noalloc(acc_dtype t, const void *dX, int64_t n, const acc_reduce_var *vars,
+                                            int nvars, const void *init, void *dResult, uint32_t flags,
+                                            void *hip_stream);
+
 /* ---- batched launch --------------------------------------------------------
  * Many independent float32 loop-nest matmuls and reductions on device
  * pointers, run by one hipGraph of two kernels: a packing kernel for every

@@ -163,6 +163,8 @@ _SIGS = {
                                         ctypes.POINTER(_sz)],
     "accx_reduce_dev": [ctypes.c_int, _vp, _i64, ctypes.POINTER(acc_reduce_var), ctypes.c_int, _vp, _vp, _u32, _vp,
                         _sz, _vp],
+    "accx_reduce_dev_noalloc": [ctypes.c_int, _vp, _i64, ctypes.POINTER(acc_reduce_var), ctypes.c_int, _vp, _vp,
+                                _u32, _vp],
     "accx_packed_size": [ctypes.c_int, _i64, _i64, ctypes.c_int, ctypes.POINTER(_sz)],
     "accx_pack_dev": [ctypes.c_int, _vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _sz, _vp],
     "accx_batch_create": [ctypes.POINTER(accx_batch_item), ctypes.c_int, _u32, ctypes.POINTER(_vp)],
@@ -448,6 +450,14 @@ def accx_reduce_dev(dtype: int, dX, n: int, vars_, init, dResult, flags: int = 0
     iv = _values(dtype, init)
     _check(_lib.accx_reduce_dev(int(dtype), _addr(dX), int(n), v, len(v), iv, _addr(dResult), int(flags),
                                 _addr(work), int(work_bytes), _stream(stream)), "accx_reduce_dev")
+
+
+def accx_reduce_dev_noalloc(dtype: int, dX, n: int, vars_, init, dResult, flags: int = 0, stream=None) -> None:
+    """accx_reduce_dev with the library's static device scratch instead of a workspace (allocates nothing)."""
+    v = _vars(vars_)
+    iv = _values(dtype, init)
+    _check(_lib.accx_reduce_dev_noalloc(int(dtype), _addr(dX), int(n), v, len(v), iv, _addr(dResult), int(flags),
+                                        _stream(stream)), "accx_reduce_dev_noalloc")
 
 
 def accx_reduce_sum_dev(dtype: int, dX, n: int, init, dResult, flags: int = 0, work=None, work_bytes: int = 0,

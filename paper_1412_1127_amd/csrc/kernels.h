@@ -45,6 +45,13 @@ struct RedVars {
 };
 // Workspace: RED_MAX_VARS x 4096 partial words of 8 bytes, any contents.
 size_t reduce_vars_workspace_bytes();
+// Static device scratch (reduce.hip) for the entry point that allocates
+// nothing: NOALLOC_SCRATCH_BYTES per GPU.  noalloc_scratch_setup(device)
+// takes the array's device address on `device` (which must be current) once;
+// noalloc_scratch(device) returns it, or NULL before the setup.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 128 * 1024;
+hipError_t noalloc_scratch_setup(int device);
+void *noalloc_scratch(int device);
 // dtype: 0 float32, 1 int32, 2 float64, 3 int64; result: nvars elements.
 hipError_t launch_reduce_vars(int dtype, const void *x, int64_t n, const RedVars &vars, void *result, void *work,
                               hipStream_t s);

@@ -493,6 +493,38 @@ hipError_t launch_vars(const E *x, int64_t n, const RedVars &vars, E *result, vo
 
 size_t reduce_vars_workspace_bytes() { return sizeof(uint64_t) * RED_MAX_VARS * MAX_BLOCKS; }
 
+// ---- static scratch for callers that cannot allocate -----------------------
+//
+// The per-workgroup partials of the reductions, in a device array of fixed
+// size instead of an allocated workspace.  Each GPU holds its own copy of
+// the array, at its own address, for the life of the process; host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol), only the device address hipGetSymbolAddress gave
+// for that device.  No call needs its contents to start at zero: every
+// reduction overwrites the partials it later reads.
+namespace {
+static __device__ __align__(256) uint64_t scratch[NOALLOC_SCRATCH_BYTES / sizeof(uint64_t)];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+void *scratch_ptr[NOALLOC_MAX_DEVICES];  // set once per device, never cleared
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    if (scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device)
+{
+    return device >= 0 && device < NOALLOC_MAX_DEVICES ? scratch_ptr[device] : nullptr;
+}
+
 hipError_t launch_reduce_vars(int dtype, const void *x, int64_t n, const RedVars &vars, void *result, void *work,
                               hipStream_t s)
 {

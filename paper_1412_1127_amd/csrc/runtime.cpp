@@ -931,6 +931,9 @@ acc_status acc_init(int device, uint64_t hbm_budget_bytes)
         return fail(ACC_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", libaccx is built for gfx950");
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    // device address of the static scratch on this device (once per device)
+    e = accx::noalloc_scratch_setup(device);
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress (static reduction scratch)");
     st.init = true;
     st.device = device;
     st.budget = hbm_budget_bytes;
@@ -1441,10 +1444,10 @@ acc_status accx_reduce_vars_workspace_size(acc_dtype t, int64_t n, const acc_red
 }
 
 namespace {
-acc_status dev_reduce(int t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars, const void *init,
-                      void *dResult, uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream)
+// Checks shared by the device-pointer reductions.
+acc_status dev_reduce_args(int t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars, const void *init,
+                           const void *dResult, uint32_t flags)
 {
-    State &st = S();
     acc_status s = check_ready();
     if (s != ACC_OK) return s;
     if ((s = validate_vars(t, n, vars, nvars, flags)) != ACC_OK) return s;
@@ -1453,6 +1456,15 @@ acc_status dev_reduce(int t, const void *dX, int64_t n, const acc_reduce_var *va
     const uintptr_t am = elem_bytes(t) - 1;
     if (((uintptr_t)dX | (uintptr_t)dResult) & am)
         return fail(ACC_ERR_INVALID_ARG, "pointers must be aligned to the element size");
+    return ACC_OK;
+}
+
+acc_status dev_reduce(int t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars, const void *init,
+                      void *dResult, uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream)
+{
+    State &st = S();
+    acc_status s = dev_reduce_args(t, dX, n, vars, nvars, init, dResult, flags);
+    if (s != ACC_OK) return s;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     const bool legacy = legacy_sum(t, vars, nvars);
     const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
@@ -1482,6 +1494,24 @@ acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, const acc_red
 {
     std::lock_guard<std::recursive_mutex> lk(S().mu);
     return dev_reduce(t, dX, n, vars, nvars, init, dResult, flags, dWork, work_bytes, hip_stream);
+}
+
+acc_status accx_reduce_dev_noalloc(acc_dtype t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars,
+                                   const void *init, void *dResult, uint32_t flags, void *hip_stream)
+{
+    State &st = S();
+    std::lock_guard<std::recursive_mutex> lk(st.mu);
+    acc_status s = dev_reduce_args(t, dX, n, vars, nvars, init, dResult, flags);
+    if (s != ACC_OK) return s;
+    const size_t need = vars_ws_bytes(t, n, vars, nvars, flags);
+    if (need > accx::NOALLOC_SCRATCH_BYTES)
+        return fail(ACC_ERR_INVALID_ARG, "the reduction needs " + std::to_string(need) +
+                                             " bytes of scratch; the static scratch holds " +
+                                             std::to_string(accx::NOALLOC_SCRATCH_BYTES) +
+                                             " (ACC_REDUCE_PLAIN: n <= 8388608)");
+    void *scratch = accx::noalloc_scratch(st.device);
+    if (!scratch) return fail(ACC_ERR_DEVICE, "static reduction scratch has no device address");
+    return run_reduce_vars(t, dX, n, vars, nvars, init, dResult, flags, scratch, static_cast<hipStream_t>(hip_stream));
 }
 
 namespace {
