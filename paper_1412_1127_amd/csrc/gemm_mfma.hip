@@ -80,16 +80,14 @@ __device__ inline void block_max_record(uint32_t mx, uint32_t *maxabs)
     }
 }
 
-// int32 -> P balanced base-256 digit planes (int8), 16 K elements per thread.
-// Element addressing as for the bf16x3 pack (leading dimension ld).
-// maxabs (optional): max |x| over the operand as block_max_record leaves it.
-// decide (optional): the two max|x| words of a finished probe pass; the
-// kernel then packs only if limb_gate(decide, expect) holds.
+// int32 -> the first `nplanes` balanced base-256 digit planes (int8) of a
+// packed operand whose units hold `pstride` planes, 16 K elements per
+// thread.  Element addressing as for the bf16x3 pack (leading dimension ld).
 // Work item id in [id0, total) by `step`; returns the thread's max |x|.
 template <bool TRANS>
 __device__ inline uint32_t pack_i8_items(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
-                                         char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int64_t id0,
-                                         int64_t step)
+                                         char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int pstride,
+                                         int64_t id0, int64_t step)
 {
     const int64_t total = nrb * nkb * 128;
     uint32_t mx = 0;
@@ -127,7 +125,7 @@ __device__ inline uint32_t pack_i8_items(const int32_t *__restrict__ X, int64_t 
             const uint32_t a = v[t] < 0 ? (uint32_t)0 - (uint32_t)v[t] : (uint32_t)v[t];
             mx = a > mx ? a : mx;
         }
-        char *u = out + unit * ((int64_t)nplanes * PLANE_BYTES) + c * 512 + r * 16;
+        char *u = out + unit * ((int64_t)pstride * PLANE_BYTES) + c * 512 + r * 16;
         if (nplanes == 1) {  // one digit: the low bytes, no carries to follow
             *reinterpret_cast<i32x4 *>(u) = i32x4{low_bytes4(v[0], v[1], v[2], v[3]), low_bytes4(v[4], v[5], v[6], v[7]),
                                                   low_bytes4(v[8], v[9], v[10], v[11]),
@@ -151,14 +149,13 @@ __device__ inline uint32_t pack_i8_items(const int32_t *__restrict__ X, int64_t 
     return mx;
 }
 
+// maxabs (optional): max |x| over the operand as block_max_record leaves it.
 template <bool TRANS>
 __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
                                                char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
-                                               uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
-                                               int expect)
+                                               uint32_t *__restrict__ maxabs)
 {
-    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
-    const uint32_t mx = pack_i8_items<TRANS>(X, R, K, ld, out, nrb, nkb, nplanes,
+    const uint32_t mx = pack_i8_items<TRANS>(X, R, K, ld, out, nrb, nkb, nplanes, nplanes,
                                              (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
     if (maxabs) block_max_record(mx, maxabs);
 }
@@ -342,11 +339,12 @@ __global__ __launch_bounds__(256) void pack_f32_pair(const float *__restrict__ A
     }
 }
 
-// int8 digit planes of B^T for column tile bx of X and part by % I8_SPLIT of
-// the 64-element K unit by / I8_SPLIT; returns the thread's max |x|.
+// The first `nplanes` int8 digit planes (of `pstride` per unit) of B^T for
+// column tile bx of X and part by % I8_SPLIT of the 64-element K unit
+// by / I8_SPLIT; returns the thread's max |x|.
 __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
-                                        char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int64_t bx,
-                                        int64_t by, uint32_t (*t)[TP_COLS])
+                                        char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int pstride,
+                                        int64_t bx, int64_t by, uint32_t (*t)[TP_COLS])
 {
     constexpr int CPT = TP_ROWS / 16;  // 16-element chunks per row per tile
     const int64_t kb = by / I8_SPLIT, rb0 = bx * (TP_COLS / 32);
@@ -367,7 +365,7 @@ __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R
             const uint32_t a = x[e] < 0 ? (uint32_t)0 - (uint32_t)x[e] : (uint32_t)x[e];
             mx = a > mx ? a : mx;
         }
-        char *o = out + ((rb0 + u) * nkb + kb) * ((int64_t)nplanes * PLANE_BYTES) + (part * CPT + c) * 512 + r * 16;
+        char *o = out + ((rb0 + u) * nkb + kb) * ((int64_t)pstride * PLANE_BYTES) + (part * CPT + c) * 512 + r * 16;
         if (nplanes == 1) {  // one digit: the low bytes
             *reinterpret_cast<i32x4 *>(o) = i32x4{low_bytes4(x[0], x[1], x[2], x[3]), low_bytes4(x[4], x[5], x[6], x[7]),
                                                   low_bytes4(x[8], x[9], x[10], x[11]),
@@ -392,37 +390,48 @@ __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R
 }
 
 // Grid: gbx column tiles of X per K tile, I8_SPLIT K tiles per K unit.
-// maxabs / decide as for pack_i8.
+// maxabs as for pack_i8.
 __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
                                                  char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
-                                                 uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide,
-                                                 int expect, int gbx)
+                                                 uint32_t *__restrict__ maxabs, int gbx)
 {
-    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
     __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
-    const uint32_t mx = pack_i8_cols(X, R, K, ld, out, nrb, nkb, nplanes, blockIdx.x % gbx, blockIdx.x / gbx, t);
+    const uint32_t mx =
+        pack_i8_cols(X, R, K, ld, out, nrb, nkb, nplanes, nplanes, blockIdx.x % gbx, blockIdx.x / gbx, t);
     if (maxabs) block_max_record(mx, maxabs);
 }
 
 // A and B^T of one product in one launch: workgroups [0, ga) pack the rows of
-// A (max |x| into maxabs[0]), the others column tiles of B (gbx per K tile;
-// maxabs[1]).  maxabs (optional) / decide as for pack_i8.
+// A (max |x| into maxabs[0]), the others the gb column tiles of B (gbx per K
+// tile, taken grid-stride; maxabs[1]).  Units hold `pstride` planes, of
+// which `nplanes` are written.  maxabs (optional) as for pack_i8.
+// decide (optional): the two max|x| words of a finished one-digit pass; the
+// launch is then the multi-digit pass: it runs only if more than one digit
+// is needed and writes that many planes (nplanes is ignored).
 __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ A, int64_t M, int64_t lda,
                                                     char *__restrict__ pa, const int32_t *__restrict__ B, int64_t N,
-                                                    int64_t ldb, char *__restrict__ pb, int64_t K, int nplanes, int ga,
-                                                    int gbx, uint32_t *__restrict__ maxabs,
-                                                    const uint32_t *__restrict__ decide, int expect)
+                                                    int64_t ldb, char *__restrict__ pb, int64_t K, int nplanes,
+                                                    int pstride, int ga, int gbx, int64_t gb,
+                                                    uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide)
 {
-    if (decide && !limb_gate(decide, expect)) return;  // uniform: the whole grid exits
+    int np = nplanes;
+    if (decide) {
+        np = limbs_needed(decide);
+        if (np == 1) return;  // uniform: the whole grid exits
+    }
     __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
     const int64_t nkb = (K + 63) / 64;
-    uint32_t mx;
+    uint32_t mx = 0;
     if ((int)blockIdx.x < ga) {
-        mx = pack_i8_items<false>(A, M, K, lda, pa, (M + 31) / 32, nkb, nplanes,
+        mx = pack_i8_items<false>(A, M, K, lda, pa, (M + 31) / 32, nkb, np, pstride,
                                   (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)ga * 256);
     } else {
-        const int64_t b = blockIdx.x - ga;
-        mx = pack_i8_cols(B, N, K, ldb, pb, (N + 31) / 32, nkb, nplanes, b % gbx, b / gbx, t);
+        // the staging buffer is reused: a barrier before each refill
+        for (int64_t b = blockIdx.x - ga; b < gb; b += gridDim.x - ga) {
+            const uint32_t m = pack_i8_cols(B, N, K, ldb, pb, (N + 31) / 32, nkb, np, pstride, b % gbx, b / gbx, t);
+            mx = m > mx ? m : mx;
+            __syncthreads();
+        }
     }
     if (maxabs) block_max_record(mx, maxabs + ((int)blockIdx.x < ga ? 0 : 1));
 }
@@ -456,8 +465,39 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
     }
 }
 
-
-// ---------------------------------------------------------- tile configs --
+// int32 with several int8 digits per operand (packed units of P planes), on
+// 128 x 128 tiles of 8 wavefronts (64 x 32 each, one int32 accumulator set
+// per shift group), two LDS stages.  A persistent grid takes the tiles
+// grid-stride, so that the launch costs little when it exits at once.  The
+// digit count comes from the device (g.decide: the max|x| words of the
+// one-digit pass; the kernel exits when one digit is enough) or from the
+// caller (g.expect).  Digit pairs (k, m) below the count with k + m <= 3:
+// 4 products for two digits, 8 for three, 10 for four.
+template <int P>
+__global__ __launch_bounds__(512) void gemm_i8_multi(GemmArgs g)
+{
+    constexpr int BM = 128, BN = 128, KBK = 64, WGM = 2, WGN = 4, NS = 2;
+    constexpr uint64_t PLMAX = P >= 4 ? PL_L4 : P == 3 ? PL_L3 : PL_L2;
+    constexpr int NPMAX = P >= 4 ? 10 : P == 3 ? 8 : 4;
+    __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPMAX, PLMAX>()];
+    const int nd = g.decide ? limbs_needed(g.decide) : g.expect;
+    if (nd < 2) return;  // uniform: the whole grid exits
+    const int T = g.tiles_m * g.tiles_n;
+    for (int t = blockIdx.x; t < T; t += gridDim.x) {
+        int tm, tn;
+        tile_of(t, g.tiles_m, g.tiles_n, tm, tn);
+        if (nd == 2) {
+            gemm_tile<true, P, BM, BN, KBK, WGM, WGN, NS, 4, PL_L2, 3>(g, tm, tn, lds);
+        } else if constexpr (P >= 3) {
+            if (P == 3 || nd == 3) {
+                gemm_tile<true, P, BM, BN, KBK, WGM, WGN, NS, 8, PL_L3, 4>(g, tm, tn, lds);
+            } else if constexpr (P >= 4) {
+                gemm_tile<true, P, BM, BN, KBK, WGM, WGN, NS, 10, PL_L4, 4>(g, tm, tn, lds);
+            }
+        }
+        __syncthreads();  // every wavefront is done with the LDS stages before the next tile's loads
+    }
+}
 
 // ------------------------------------------------------- float64 probe --
 
@@ -639,7 +679,8 @@ __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restric
 //           two workgroups per CU that do not share barriers.
 //  T128     128 x 128, 4 waves (2x2), 32 B, 3 stages: 72 KB (bf16x3);
 //           first-product look-ahead for bf16x3.
-//  T64       64 x 64,  4 waves (2x2), 64 B, 2 stages (several int8 planes).
+//  T64       64 x 64,  4 waves (2x2), 64 B, 2 stages.
+// (Several int8 digits per operand: gemm_i8_multi's own 128 x 128 tile.)
 //  T256W4   256 x 256, 4 waves (2x2, 128 x 128 each), 32 B / 64 B, 3
 //           stages: a third less LDS read traffic per matrix instruction
 //           than T256, one wavefront per SIMD, accumulators in AGPRs; for
@@ -664,13 +705,13 @@ hipError_t launch_tile(GemmArgs g, hipStream_t s)
     return hipGetLastError();
 }
 
+// Tiled GEMM of one plane set: bf16x3 (P = 3) or one int8 digit (P = 1);
+// several int8 digits run gemm_i8_multi.
 template <bool INT8, int P, int NPROD, uint64_t PL, int NACC>
 hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
 {
-    // Several int8 limb planes need up to 4 accumulator sets: small tiles only.
-    constexpr bool multi = INT8 && P > 1;
-    constexpr int KS = multi ? 64 : (P == 3 ? 32 : 64);  // K-step bytes of the big tiles
-    if (multi) tile = GEMM_TILE_64;
+    static_assert(!INT8 || P == 1, "several int8 digits: gemm_i8_multi");
+    constexpr int KS = P == 3 ? 32 : 64;  // K-step bytes of the big tiles
     switch (tile) {
     case GEMM_TILE_256:
         // Look-ahead: full for the one-digit int8 tile (two fragment sets of
@@ -678,21 +719,31 @@ hipError_t run_gemm(int tile, const GemmArgs &g, hipStream_t s)
         // only for bf16x3, whose three planes leave no room for a second full
         // set at two wavefronts per SIMD.  (A fourth stage, which fits for a
         // two-plane pass, measured 4 % slower: the loads are not the limit.)
-        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, multi ? 2 : 4, multi ? 2 : 3, NPROD, PL,
-                           NACC, multi ? 0 : INT8 ? 1 : 2>(g, s);
+        return launch_tile<INT8, P, 256, 256, KS, 2, 4, 3, NPROD, PL, NACC, INT8 ? 1 : 2>(g, s);
     case GEMM_TILE_256W4:
         // look-ahead for bf16x3 only: the int8 tile (two K sub-steps per
         // stage) would need more registers than a wavefront has
-        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 256, KS, 2, 2, multi ? 2 : 3, NPROD, PL, NACC,
-                           INT8 ? 0 : 1>(g, s);
+        return launch_tile<INT8, P, 256, 256, KS, 2, 2, 3, NPROD, PL, NACC, INT8 ? 0 : 1>(g, s);
     case GEMM_TILE_256x128:
-        return launch_tile<INT8, P, multi ? 64 : 256, multi ? 64 : 128, KS, 2, 2, 2, NPROD, PL, NACC>(g, s);
+        return launch_tile<INT8, P, 256, 128, KS, 2, 2, 2, NPROD, PL, NACC>(g, s);
     case GEMM_TILE_128:
-        return launch_tile<INT8, P, multi ? 64 : 128, multi ? 64 : 128, multi ? 64 : 32, 2, 2, multi ? 2 : 3, NPROD,
-                           PL, NACC, INT8 ? 0 : 2>(g, s);
+        return launch_tile<INT8, P, 128, 128, 32, 2, 2, 3, NPROD, PL, NACC, INT8 ? 0 : 2>(g, s);
     default: break;
     }
     return launch_tile<INT8, P, 64, 64, 64, 2, 2, 2, NPROD, PL, NACC>(g, s);
+}
+
+// Multi-digit int8 GEMM: one 128 KB workgroup per CU, at most one per tile.
+template <int P>
+hipError_t launch_i8_multi(GemmArgs g, hipStream_t s)
+{
+    g.tiles_m = (int)((g.M + 127) / 128);
+    g.tiles_n = (int)((g.N + 127) / 128);
+    g.ksplit = 1;
+    const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, device_cu_count()));
+    hipLaunchKernelGGL(gemm_i8_multi<P>, dim3(grid), dim3(512), 0, s, g);
+    return hipGetLastError();
 }
 
 // float32 matrix cores: one plane of 4-byte elements, 64-byte K steps (16
@@ -796,7 +847,7 @@ hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, int64_t l
 }
 
 hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld, bool trans, int planes, void *out,
-                          uint32_t *maxabs, hipStream_t s, const uint32_t *decide, int expect)
+                          uint32_t *maxabs, hipStream_t s)
 {
     const int64_t nrb = cdiv(rows, 32), nkb = cdiv(k, 64);
     if (nrb * nkb == 0) return hipSuccess;
@@ -804,11 +855,10 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld,
     tmark("pack_i8", s, true);
     if (trans)
         hipLaunchKernelGGL(pack_i8_t, dim3((unsigned)(cdiv(rows, TP_COLS) * I8_SPLIT * nkb)), dim3(256), 0, s, x, rows,
-                           k, ld, static_cast<char *>(out), nrb, nkb, planes, maxabs, decide, expect,
-                           (int)cdiv(rows, TP_COLS));
+                           k, ld, static_cast<char *>(out), nrb, nkb, planes, maxabs, (int)cdiv(rows, TP_COLS));
     else
         hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out), nrb,
-                           nkb, planes, maxabs, decide, expect);
+                           nkb, planes, maxabs);
     tmark("pack_i8", s, false);
     return hipGetLastError();
 }
@@ -828,15 +878,24 @@ hipError_t launch_pack_bf16x3_pair(const float *a, int64_t m, int64_t lda, const
 
 hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const int32_t *b, int64_t n, int64_t ldb,
                                int64_t k, int planes, void *pa, void *pb, uint32_t *maxabs, hipStream_t s,
-                               const uint32_t *decide, int expect)
+                               const uint32_t *decide)
 {
     const int64_t nkb = cdiv(k, 64), ua = cdiv(m, 32) * nkb;
-    const int64_t ga = ua > 0 ? pack_grid(ua) : 0, gbx = cdiv(n, TP_COLS), gb = gbx * I8_SPLIT * nkb;
-    if (ga + gb == 0) return hipSuccess;
+    int64_t ga = ua > 0 ? pack_grid(ua) : 0;
+    const int64_t gbx = cdiv(n, TP_COLS), gb = gbx * I8_SPLIT * nkb;
+    int64_t gbl = gb;  // workgroups for B's column tiles
+    if (decide) {
+        // the multi-digit pass usually exits at once: a grid of a few
+        // workgroups per CU, each looping, keeps that exit cheap
+        const int64_t cap = (int64_t)device_cu_count() * 2;
+        ga = std::min<int64_t>(ga, cap);
+        gbl = std::min<int64_t>(gbl, cap);
+    }
+    if (ga + gbl == 0) return hipSuccess;
     tmark("pack_i8", s, true);
-    hipLaunchKernelGGL(pack_i8_pair, dim3((unsigned)(ga + gb)), dim3(256), 0, s, a, m, lda, static_cast<char *>(pa), b,
-                       n, ldb, static_cast<char *>(pb), k, planes, (int)ga, (int)std::max<int64_t>(gbx, 1), maxabs,
-                       decide, expect);
+    hipLaunchKernelGGL(pack_i8_pair, dim3((unsigned)(ga + gbl)), dim3(256), 0, s, a, m, lda, static_cast<char *>(pa),
+                       b, n, ldb, static_cast<char *>(pb), k, planes, decide ? 4 : planes, (int)ga,
+                       (int)std::max<int64_t>(gbx, 1), gb, maxabs, decide);
     tmark("pack_i8", s, false);
     return hipGetLastError();
 }
@@ -1037,9 +1096,9 @@ hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const Gemm
     tmark("gemm_i8", s, true);
     switch (limbs) {
     case 1: e = run_gemm<true, 1, 1, PL_L1, 1>(t, g, s); break;
-    case 2: e = run_gemm<true, 2, 4, PL_L2, 3>(GEMM_TILE_64, g, s); break;
-    case 3: e = run_gemm<true, 3, 8, PL_L3, 4>(GEMM_TILE_64, g, s); break;
-    case 4: e = run_gemm<true, 4, 10, PL_L4, 4>(GEMM_TILE_64, g, s); break;
+    case 2: e = launch_i8_multi<2>(g, s); break;
+    case 3: e = launch_i8_multi<3>(g, s); break;
+    case 4: e = launch_i8_multi<4>(g, s); break;
     default: e = hipErrorInvalidValue;
     }
     tmark("gemm_i8", s, false);

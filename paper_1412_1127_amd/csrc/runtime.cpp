@@ -588,19 +588,19 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const G
     hipError_t e;
     if (nl == 0) {
         // Probe on the device, no host round trip: one pass writes digit 0 of
-        // both operands and max|x|; a four-digit pass and the four-digit GEMM
-        // run only if the maxima call for more than one digit, the one-digit
-        // GEMM only if they do not (each kernel reads the decision and exits
-        // at once otherwise).  Two or three digits are served by the
-        // four-digit kernels: the extra digits are zero.
+        // both operands and max|x|; the multi-digit pass and GEMM run only if
+        // the maxima call for more than one digit (with as many digits as
+        // they call for: two, three or four), the one-digit GEMM only if
+        // they do not (each kernel reads the decision and exits at once
+        // otherwise; the multi-digit kernels on small persistent grids, so
+        // that their exit costs little).
         const size_t pa1 = accx::packed_bytes(sh.m, sh.k, 1, 1), pa4 = accx::packed_bytes(sh.m, sh.k, 1, 4);
         char *p4 = pa + packed_pair(sh, 1, 1);
         e = accx::launch_zero_u32(maxabs, 2, s);
         if (e == hipSuccess)
             e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 1, pa, pa + pa1, maxabs, s);
         if (e == hipSuccess)
-            e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 4, p4, p4 + pa4, nullptr, s, maxabs,
-                                          4);
+            e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 4, p4, p4 + pa4, nullptr, s, maxabs);
         if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
         e = accx::launch_gemm_i8(pa, pa + pa1, c, sh, 1, resolve_tile(ACC_INT32, sh, flags, 1), s, maxabs, sk);
         if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pa4, c, sh, 4, 0, s, maxabs);

@@ -115,6 +115,39 @@ def test_i32_bit_exact_probe(ax, limbs, n):
     assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED | ax.ACC_LIMBS(limbs)), ref)
 
 
+# The device picks the digit count from max |x|: one digit holds [-128, 127]
+# (taken for |x| <= 127), two [-32896, 32639], three [-8421504, 8355711].
+# One element at each side of each threshold, in A or in B, on small values
+# elsewhere; 130 = two 128-row tiles of the multi-digit kernel plus a ragged one.
+@pytest.mark.parametrize("v", [127, -127, 128, -128, 32639, 32640, -32896, -32897, 8355711, 8355712, -8421504,
+                               -8421505, 2 ** 31 - 1, -(2 ** 31)])
+@pytest.mark.parametrize("where", ["a", "b"])
+def test_i32_digit_count_thresholds(ax, v, where):
+    n = 130
+    a = synth.int_uniform_i32((n, n), -100, 100, SEED, synth.STREAM_A)
+    b = synth.int_uniform_i32((n, n), -100, 100, SEED, synth.STREAM_B)
+    (a if where == "a" else b)[n - 1, 57] = v
+    assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED), oracle.matmul_i32(a, b))
+
+
+# More output tiles than the multi-digit kernel has workgroups (one per CU):
+# every workgroup takes several tiles in turn.
+@pytest.mark.parametrize("bound", [32639, 8355711, None])
+def test_i32_multi_digit_many_tiles(ax, bound):
+    n = 2100
+    if bound is None:
+        a = synth.full_range_i32((n, n), SEED, 41)
+        b = synth.full_range_i32((n, n), SEED, 42)
+    else:
+        a = synth.int_uniform_i32((n, n), -bound, bound, SEED, 41)
+        b = synth.int_uniform_i32((n, n), -bound, bound, SEED, 42)
+    ref = oracle.matmul_i32(a, b)
+    assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED), ref)
+    if bound is not None:
+        limbs = 2 if bound == 32639 else 3
+        assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED | ax.ACC_LIMBS(limbs)), ref)
+
+
 def test_i32_wraparound(ax):
     n = 48
     a = np.full((n, n), 2 ** 31 - 1, np.int32)
