@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
 PEAK_INT8_TOPS = 5000.0     # MI355X dense int8 matrix peak
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3    # MI355X float32 matrix / vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -171,10 +172,14 @@ def ingest_counters(root: str, prec: str) -> int:
 
 
 def _onbox(torch, x):
-    """Reference points measured on this GPU outside the timed region: a
-    plain device copy of the 1 GiB reduction input (read + write bytes), and
-    the vendor library's bf16 and float32 GEMMs at LEN=4096 (torch.matmul,
-    hipBLASLt), beside the datasheet peaks the roofline fractions use."""
+    """Reference points measured on this GPU outside the timed region, beside
+    the datasheet peaks the roofline fractions use: the measured ceilings
+    (library kernels doing nothing but matrix instructions, bf16 and int8,
+    on every CU; a read-only stream of the 1 GiB reduction input), a plain
+    device copy of that input (read + write bytes), and the vendor library's
+    bf16 and float32 GEMMs at LEN=4096 (torch.matmul, hipBLASLt)."""
+    import paper_1412_1127_amd as ax
+
     def timed(fn, reps):
         fn()
         torch.cuda.synchronize()
@@ -186,6 +191,16 @@ def _onbox(torch, x):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
     out = {"datasheet": {"bf16_tflops": PEAK_BF16_TFLOPS, "int8_tops": PEAK_INT8_TOPS, "hbm_gbs": PEAK_HBM_GBS}}
+    stream = torch.cuda.current_stream()
+    # a ceiling is the best of three timings (the clock under load drifts)
+    for name, kind in (("measured_bf16_mfma_tflops", 0), ("measured_int8_mfma_tops", 1)):
+        ops = ax.accx_onbox_mfma(kind, 5000, stream)            # about 1.5 ms per launch
+        timed(lambda: ax.accx_onbox_mfma(kind, 5000, stream), 3)  # clocks to their loaded state
+        out[name] = max(ops / (timed(lambda: ax.accx_onbox_mfma(kind, 5000, stream), 5) * 1e-3) / 1e12
+                        for _ in range(3))
+    nbytes = x.numel() * x.element_size()
+    out["measured_hbm_read_gbs"] = max(
+        nbytes / (timed(lambda: ax.accx_onbox_read(x, nbytes, stream), 10) * 1e-3) / 1e9 for _ in range(3))
     dst = torch.empty_like(x)
     ms = timed(lambda: dst.copy_(x), 10)
     out["copy_gbs"] = 2.0 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9
@@ -374,6 +389,14 @@ def run_scale(args) -> int:
         accuracy["reduce_rel_err"] = abs(float(dr.item()) - sref) / sref
 
     onbox = None if args.no_onbox else _onbox(torch, dx)
+    if onbox:
+        mb = onbox["measured_bf16_mfma_tflops"]
+        roofline["measured_peak"] = mb
+        roofline["measured_frac"] = achieved / mb if achieved else None
+        gi = components["i32_matmul"]["tops_int32_equiv_gemm"]
+        components["i32_matmul"]["frac_measured_int8_gemm"] = gi / onbox["measured_int8_mfma_tops"] if gi else None
+        gb = components["reduce"]["gbs"]
+        components["reduce"]["frac_measured_read"] = gb / onbox["measured_hbm_read_gbs"] if gb else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -501,8 +524,10 @@ def run_precision(args) -> int:
     ax.accx_autotune(ax.ACC_FLOAT32, n, ax.ACC_PREC_FULL6)
     ax.accx_timing_enable(True)
     out = {}
+    ax.accx_autotune(ax.ACC_FLOAT32, n, ax.ACC_PREC_F32MFMA)
     for name, flags, reps in [("bf16x3_full6", ax.ACC_KERNEL_TILED | ax.ACC_PREC_FULL6, args.steps),
                               ("bf16x3_auto", ax.ACC_KERNEL_TILED | ax.ACC_PREC_AUTO, args.steps),
+                              ("f32_mfma_tiled", ax.ACC_KERNEL_TILED | ax.ACC_PREC_F32MFMA, args.steps),
                               ("plain_f32", ax.ACC_KERNEL_PLAIN, 1)]:
         ax.accx_timing_read(reset=True)
         ts = _event_times(lambda: ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, flags), reps,
@@ -518,6 +543,13 @@ def run_precision(args) -> int:
     f = out["bf16x3_full6"]
     gm = f["kernels"].get("gemm_bf16x3")
     achieved = 6 * 2.0 * n ** 3 / (gm * 1e-3) / 1e12 if gm else None
+    # the float32 tiled comparator against the float32 matrix-core peak
+    fm = out["f32_mfma_tiled"]["kernels"].get("gemm_f32mm")
+    out["f32_mfma_tiled"]["roofline"] = {
+        "kernel": "gemm_f32mm", "bound": "mfma", "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+        "achieved": 2.0 * n ** 3 / (fm * 1e-3) / 1e12 if fm else None,
+        "frac": 2.0 * n ** 3 / (fm * 1e-3) / 1e12 / PEAK_FP32_TFLOPS if fm else None}
+    out["bf16x3_speedup_over_f32_mfma"] = out["f32_mfma_tiled"]["ms"] / f["ms"]
     print(json.dumps(_common(
         args, "matmul TFLOP/s (bf16x3, LEN=8192) at <=1e-5 rel err", f["tflops_fp32_equiv"], "TFLOP/s", f["ms"],
         {"workload": "precision: LEN=8192 float32 N(0,1) x 2^U(-8,8) per row", "len": n},

@@ -574,6 +574,27 @@ ACCX_API acc_status accx_timing_filter(const char *names);
  * reset != 0 clears the totals afterwards.  Errors: INVALID_ARG. */
 ACCX_API acc_status accx_timing_read(accx_kernel_time *out, int cap, int *n_out, int reset);
 
+/* ---- measured ceilings ----------------------------------------------------
+ * The paper compares kernel times measured on its GPU (section 3,
+ * "Performance evaluations").  A kernel's fraction of roofline is stated
+ * against the datasheet peak; these two calls measure what this GPU reaches
+ * with nothing but the bounding resource, so the fraction can also be given
+ * against the measured ceiling.  Both enqueue one kernel on `hip_stream`
+ * (NULL = the null stream) and allocate nothing; time them with events. */
+
+/* Matrix instructions only: every CU runs two wavefronts per SIMD, each
+ * issuing `rounds` rounds of 8 independent 32x32 matrix instructions from
+ * operands in registers (kind 0: v_mfma_f32_32x32x16_bf16; kind 1:
+ * v_mfma_i32_32x32x32_i8).  *ops_out = operations of the launch (2 per
+ * multiply-add).  Errors: INVALID_ARG (kind not 0 or 1, rounds outside
+ * [1, 2^30], ops_out NULL), DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_onbox_mfma(int kind, int64_t rounds, double *ops_out, void *hip_stream);
+
+/* Read-only stream of `bytes` of device memory at dX (16-byte aligned,
+ * bytes a positive multiple of 16), three workgroups per CU.
+ * Errors: INVALID_ARG, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_onbox_read(const void *dX, int64_t bytes, void *hip_stream);
+
 /* ---- strings ------------------------------------------------------------ */
 ACCX_API const char *acc_status_string(acc_status s);
 ACCX_API const char *acc_last_error_string(void);

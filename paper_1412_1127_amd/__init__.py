@@ -165,6 +165,8 @@ _SIGS = {
                         _sz, _vp],
     "accx_reduce_dev_noalloc": [ctypes.c_int, _vp, _i64, ctypes.POINTER(acc_reduce_var), ctypes.c_int, _vp, _vp,
                                 _u32, _vp],
+    "accx_onbox_mfma": [ctypes.c_int, _i64, ctypes.POINTER(ctypes.c_double), _vp],
+    "accx_onbox_read": [_vp, _i64, _vp],
     "accx_packed_size": [ctypes.c_int, _i64, _i64, ctypes.c_int, ctypes.POINTER(_sz)],
     "accx_pack_dev": [ctypes.c_int, _vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _sz, _vp],
     "accx_batch_create": [ctypes.POINTER(accx_batch_item), ctypes.c_int, _u32, ctypes.POINTER(_vp)],
@@ -450,6 +452,18 @@ def accx_reduce_dev(dtype: int, dX, n: int, vars_, init, dResult, flags: int = 0
     iv = _values(dtype, init)
     _check(_lib.accx_reduce_dev(int(dtype), _addr(dX), int(n), v, len(v), iv, _addr(dResult), int(flags),
                                 _addr(work), int(work_bytes), _stream(stream)), "accx_reduce_dev")
+
+
+def accx_onbox_mfma(kind: int, rounds: int, stream=None) -> float:
+    """Enqueue the matrix-instruction-only loop (0: bf16, 1: int8); returns its operation count."""
+    ops = ctypes.c_double(0.0)
+    _check(_lib.accx_onbox_mfma(int(kind), int(rounds), ctypes.byref(ops), _stream(stream)), "accx_onbox_mfma")
+    return float(ops.value)
+
+
+def accx_onbox_read(dX, nbytes: int, stream=None) -> None:
+    """Enqueue a read-only stream of nbytes at dX."""
+    _check(_lib.accx_onbox_read(_addr(dX), int(nbytes), _stream(stream)), "accx_onbox_read")
 
 
 def accx_reduce_dev_noalloc(dtype: int, dX, n: int, vars_, init, dResult, flags: int = 0, stream=None) -> None:

@@ -25,6 +25,7 @@ SOURCES = [
     "reduce.hip",
     "gemm_mfma.hip",
     "batch.hip",
+    "onbox.hip",
 ]
 
 ARCH = "gfx950"

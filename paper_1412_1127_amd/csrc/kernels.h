@@ -144,6 +144,13 @@ hipError_t launch_gemm_f32mm(const void *pa, const void *pb, float *c, const Gem
 hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,
                           hipStream_t s, const uint32_t *decide = nullptr, const SplitK &sk = SplitK());
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
+
+// ---- measurement kernels (onbox.hip) ---------------------------------------
+// Matrix instructions only (kind 0: bf16 32x32x16, 1: int8 32x32x32) on
+// every CU; *ops = the operations the launch performs.
+hipError_t launch_onbox_mfma(int kind, int64_t rounds, double *ops, hipStream_t s);
+// Read-only stream of `bytes` (a multiple of 16, 16-byte aligned) at x.
+hipError_t launch_onbox_read(const void *x, int64_t bytes, hipStream_t s);
 // n pseudo-random 32-bit words for timing runs: float32 in [-1, 1) or int32 in [-16, 16].
 hipError_t launch_fill_hash(void *p, int64_t n, bool as_int, hipStream_t s);
 

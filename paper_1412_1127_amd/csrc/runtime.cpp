@@ -1496,6 +1496,28 @@ acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, const acc_red
     return dev_reduce(t, dX, n, vars, nvars, init, dResult, flags, dWork, work_bytes, hip_stream);
 }
 
+acc_status accx_onbox_mfma(int kind, int64_t rounds, double *ops_out, void *hip_stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if ((kind != 0 && kind != 1) || rounds < 1 || rounds > ((int64_t)1 << 30) || !ops_out)
+        return fail(ACC_ERR_INVALID_ARG, "kind must be 0 or 1, rounds in [1, 2^30], ops_out non-NULL");
+    return check_launch(accx::launch_onbox_mfma(kind, rounds, ops_out, static_cast<hipStream_t>(hip_stream)),
+                        "matrix-instruction loop launch");
+}
+
+acc_status accx_onbox_read(const void *dX, int64_t bytes, void *hip_stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if (!dX || bytes <= 0 || (bytes & 15) || ((uintptr_t)dX & 15))
+        return fail(ACC_ERR_INVALID_ARG, "dX must be 16-byte aligned and bytes a positive multiple of 16");
+    return check_launch(accx::launch_onbox_read(dX, bytes, static_cast<hipStream_t>(hip_stream)),
+                        "read stream launch");
+}
+
 acc_status accx_reduce_dev_noalloc(acc_dtype t, const void *dX, int64_t n, const acc_reduce_var *vars, int nvars,
                                    const void *init, void *dResult, uint32_t flags, void *hip_stream)
 {
