@@ -58,6 +58,8 @@ def _args():
                         "configurations (LEN=256 plain method, LEN=8192 precision, batching, serving) and "
                         "one GPU's 512-row block of the LEN=4096 product (rowblock)")
     p.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    p.add_argument("--batch-prec", choices=["auto", "full6"], default="auto",
+                   help="batch: ACC_BATCH_PREC_AUTO (three products, per-tile probe and correction) or six products")
     p.add_argument("--streams", type=int, choices=[1, 2], default=1,
                    help="scale: 2 runs the int32 matmul and the reduction on a second stream, overlapped "
                         "with the float32 matmul")
@@ -587,7 +589,8 @@ def run_batch(args) -> int:
         reds.append((x, dx, r))
         items.append(ax.batch_reduce(dx, int(n), r))
     t0 = time.time()
-    bh = ax.accx_batch_create(items, ax.ACC_BATCH_AUTOTUNE)
+    auto = args.batch_prec == "auto"
+    bh = ax.accx_batch_create(items, ax.ACC_BATCH_AUTOTUNE | (ax.ACC_BATCH_PREC_AUTO if auto else 0))
     create_s = time.time() - t0
     info = ax.accx_batch_info(bh)
     ts = _event_times(lambda: ax.accx_batch_launch(bh), args.steps, args.warmup)
@@ -602,7 +605,8 @@ def run_batch(args) -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for (_a, _b, da, db, dc, n) in mats:
-        ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, ax.ACC_KERNEL_TILED | ax.ACC_PREC_FULL6)
+        ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n,
+                           ax.ACC_KERNEL_TILED | (ax.ACC_PREC_AUTO if auto else ax.ACC_PREC_FULL6))
     for (x, dx, r) in reds:
         ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, x.size, 0.0, r)
     torch.cuda.synchronize()
@@ -610,11 +614,12 @@ def run_batch(args) -> int:
     ax.accx_batch_launch(bh)
     torch.cuda.synchronize()
     g = synth.rng(seed, 77)
-    got, ref = [], []
+    got, ref, per_item = [], [], []
     for (a, b, _da, _db, dc, n) in mats:
-        ii, jj = g.integers(0, n, 8), g.integers(0, n, 8)
+        ii, jj = g.integers(0, n, 64), g.integers(0, n, 64)
         got.append(dc.cpu().numpy()[ii, jj])
         ref.append(oracle.matmul_at(a, b, ii, jj))
+        per_item.append(float(np.linalg.norm(got[-1] - ref[-1]) / np.linalg.norm(ref[-1])))
     got, ref = np.concatenate(got), np.concatenate(ref)
     red_err = max(abs(float(r.item()) - oracle.sum_f32(x)) / oracle.sum_f32(x) for (x, _dx, r) in reds)
     ax.accx_batch_destroy(bh)
@@ -624,11 +629,12 @@ def run_batch(args) -> int:
     print(json.dumps(_common(
         args, "batched matmul TFLOP/s (one graph launch: 512 matmuls + 256 reductions)", tf, "TFLOP/s", ms,
         {"workload": "batching: 512 float32 matmuls LEN in {64..1024} + 256 float32 reductions n in [2^16, 2^24]",
-         "tile_threshold": info["tile_threshold"]},
+         "tile_threshold": info["tile_threshold"], "precision": args.batch_prec},
         batch=info, create_s=create_s, mfma_tflops=mfma, mfma_frac=mfma / PEAK_BF16_TFLOPS,
         reduce_gbs_if_alone=info["reduce_bytes"] / (ms * 1e-3) / 1e9, eager_kernels_ms=kt,
         one_call_per_item_ms=per_item_ms,
         accuracy={"matmul_rel_fro_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                  "matmul_rel_fro_max_per_item_64_samples": max(per_item),
                   "reduce_max_rel_err": red_err})))
     return 0
 

@@ -56,6 +56,10 @@ typedef enum {
     ACC_ERR_OUT_OF_MEMORY = -4,   /* HBM budget exceeded or allocation failed */
     ACC_ERR_DEVICE = -5,          /* HIP runtime or kernel launch error */
     ACC_ERR_NO_DEVICE = -6,       /* no gfx950 device, or acc_init not called */
+    /* not statuses: they make every int32 a value of the type, so that any
+     * int a caller passes through the ABI is well defined */
+    ACC_STATUS_RANGE_MIN_ = -0x7fffffff - 1,
+    ACC_STATUS_RANGE_MAX_ = 0x7fffffff
 } acc_status;
 
 /* Data clauses (section 1.3): copy = copy in at region entry and out at exit;
@@ -84,7 +88,17 @@ typedef enum {
 
 /* Element types.  The matmul takes ACC_FLOAT32 and ACC_INT32; data clauses
  * and reductions take all four. */
-typedef enum { ACC_FLOAT32 = 0, ACC_INT32 = 1, ACC_FLOAT64 = 2, ACC_INT64 = 3 } acc_dtype;
+typedef enum {
+    ACC_FLOAT32 = 0,
+    ACC_INT32 = 1,
+    ACC_FLOAT64 = 2,
+    ACC_INT64 = 3,
+    /* not element types: they make every int32 a value of the type, so that
+     * a caller's invalid dtype is a defined value the library rejects with
+     * ACC_ERR_INVALID_ARG */
+    ACC_DTYPE_RANGE_MIN_ = -0x7fffffff - 1,
+    ACC_DTYPE_RANGE_MAX_ = 0x7fffffff
+} acc_dtype;
 
 /* One data clause: host[start : start+n) in elements of `dtype` ("[start:n]
  * means n elements from element start", section 1.3).  `host` is the base of
@@ -371,9 +385,12 @@ ACCX_API acc_status accx_reduce_dev_noalloc(acc_dtype t, const void *dX, int64_t
  * output tiles and reduction chunks from one shared queue.  A matmul runs
  * 128 x 128 tiles when its LEN reaches a threshold, else 64 x 64 (or the
  * tile its flags force); ACC_BATCH_AUTOTUNE picks the threshold by timing
- * the batch itself, otherwise it is 512.  Matmuls in a batch use the six-product bf16x3 split; a matmul's
- * result is bitwise that of accx_matmul_dev with ACC_PREC_FULL6 and the same
- * tile, run unsplit (a workspace without the split area).  Reductions are deterministic (fixed chunking, chunk-order combine). */
+ * the batch itself, otherwise it is 512.  Matmuls in a batch use the
+ * six-product bf16x3 split (or ACC_PREC_AUTO's steps, ACC_BATCH_PREC_AUTO);
+ * a matmul's result is bitwise that of accx_matmul_dev with ACC_PREC_FULL6
+ * (ACC_PREC_AUTO) and the same tile, run unsplit (a workspace without the
+ * split area).  Reductions are deterministic (fixed chunking, chunk-order
+ * combine). */
 #define ACC_BATCH_MATMUL 0
 #define ACC_BATCH_REDUCE 1
 typedef struct {
@@ -390,6 +407,12 @@ typedef struct {
 typedef struct accx_batch_s *accx_batch; /* opaque */
 
 #define ACC_BATCH_AUTOTUNE 0x1u /* create: time the tile policies on this batch, keep the fastest */
+#define ACC_BATCH_PREC_AUTO 0x2u /* create: matmuls take ACC_PREC_AUTO's steps per tile (the
+                                    three-product pass, the float64 probe of the tile, and the
+                                    correction products if the probe marks it) instead of six
+                                    products; a matmul's result is then bitwise that of
+                                    accx_matmul_dev with ACC_PREC_AUTO and the same tile, run
+                                    unsplit */
 
 typedef struct {
     int64_t units;        /* queue entries: matmul tiles + reduction chunks */
@@ -400,7 +423,7 @@ typedef struct {
     int32_t pad;
     uint64_t device_bytes;/* descriptors, packed operands, partials */
     double flops;         /* sum of 2 n^3 over the matmuls */
-    double mfma_flops;    /* bf16 matrix-core flops actually executed (6 products) */
+    double mfma_flops;    /* bf16 matrix-core flops of the matmuls' main pass (6 or 3 products) */
     double reduce_bytes;  /* sum of 4 n over the reductions */
 } accx_batch_info_t;
 

@@ -19,6 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _HDR = os.path.join(_HERE, "oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A prebuilt oracle library to load instead (the sanitizer test's
+# AddressSanitizer / UndefinedBehaviorSanitizer build of oracle.c).
+_LIB_OVERRIDE = os.environ.get("ACCX_ORACLE_LIB")
 
 _lib = None
 
@@ -39,8 +42,7 @@ def build(force: bool = False) -> str:
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_LIB_OVERRIDE or build())
         i64, i32, f64, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
         sig = {
             "oracle_set_threads": (None, [ctypes.c_int]),

@@ -17,7 +17,9 @@ import os
 import torch  # noqa: F401  (HIP runtime shared with libaccx)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libaccx.so")
+# ACCX_LIB: another build of the same library to load instead (the sanitizer
+# test's build with AddressSanitizer / UndefinedBehaviorSanitizer host code).
+LIB_PATH = os.environ.get("ACCX_LIB") or os.path.join(_HERE, "libaccx.so")
 
 # ---- constants (mirror include/accx.h) ------------------------------------
 ACC_OK = 0
@@ -59,6 +61,7 @@ ACC_SERVE_REDUCE = 1
 ACC_BATCH_MATMUL = 0
 ACC_BATCH_REDUCE = 1
 ACC_BATCH_AUTOTUNE = 0x1
+ACC_BATCH_PREC_AUTO = 0x2
 ACC_TILE_256W4 = 0x50000
 TILES = {"256": ACC_TILE_256, "256x128": ACC_TILE_256x128, "128": ACC_TILE_128, "64": ACC_TILE_64,
          "256w4": ACC_TILE_256W4}

@@ -16,8 +16,16 @@
 // its last chunk (atomic ticket), in chunk order, so results do not depend
 // on which workgroup ran what.  A matmul tile is computed by one workgroup in
 // fixed K order, bitwise as by the standalone kernel in the same tile
-// configuration when that one runs unsplit (no split K).  The last workgroup to leave resets the queue counters, so
-// the graph can be replayed with no memset node.
+// configuration when that one runs unsplit (no split K).  The last workgroup
+// to leave resets the queue counters, so the graph can be replayed with no
+// memset node.
+//
+// Precision: six products (FULL6), or AUTO: the three-product pass of the
+// tile, then the same workgroup probes that tile in float64 (probe_tile,
+// the standalone probe's samples and summation order) and, if the tile is
+// marked, adds the three correction products over its 64 x 64 sub-tiles --
+// the standalone AUTO path's steps for that tile, done in place, so no other
+// workgroup and no other launch is involved.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -32,15 +40,15 @@ constexpr int BT = 256;              // threads per workgroup (both kernels)
 constexpr int WG_PER_CU = 2;         // persistent workgroups per CU (LDS: 2 x 72 KB)
 constexpr uint32_t UNIT_RED = 0x80000000u;
 
-// Tile variants the persistent kernel carries: T128 (first-product
-// look-ahead) and T64, six products (FULL6).  More variants in one kernel
-// push its register need past the 256 that two wavefronts per SIMD allow.
+// Tile variants the persistent kernels carry: T128 (first-product
+// look-ahead) and T64; six products (FULL6), or three (CHEAP3) plus the
+// correction products on T64 (AUTO), one kernel per precision.
 #define ACCX_T128(NP, PLIST) false, 3, 128, 128, 32, 2, 2, 3, NP, PLIST, 1, 2
 #define ACCX_T64(NP, PLIST) false, 3, 64, 64, 64, 2, 2, 2, NP, PLIST, 1
 
-constexpr int LDS_T128_FULL = gemm_lds_bytes<128, 128, 32, 3, 6, PL_FULL6>();
-constexpr int LDS_T64_FULL = gemm_lds_bytes<64, 64, 64, 2, 6, PL_FULL6>();
-constexpr int LDS_MAX = LDS_T128_FULL > LDS_T64_FULL ? LDS_T128_FULL : LDS_T64_FULL;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int LDS_MAX = cmax(cmax(gemm_lds_bytes<128, 128, 32, 3, 6, PL_FULL6>(), gemm_lds_bytes<64, 64, 64, 2, 6, PL_FULL6>()),
+                             (int)sizeof(ProbeLds));
 static_assert(LDS_MAX * WG_PER_CU <= 160 * 1024, "persistent kernel LDS");
 
 __global__ __launch_bounds__(BT) void batch_pack(const BatchPackJob *__restrict__ jobs)
@@ -123,7 +131,9 @@ __device__ __attribute__((always_inline)) inline void reduce_chunk(const BatchRe
     }
 }
 
-__device__ __attribute__((always_inline)) inline void matmul_unit(const BatchMat &m, uint32_t tile, char *lds)
+template <bool AUTO>
+__device__ __attribute__((always_inline)) inline void matmul_unit(const BatchMat &m, uint32_t tile, char *lds,
+                                                                  double tau2)
 {
     GemmArgs g{};
     g.A = m.pa;
@@ -135,12 +145,44 @@ __device__ __attribute__((always_inline)) inline void matmul_unit(const BatchMat
     g.tiles_m = m.tiles_m;
     g.tiles_n = m.tiles_n;
     const int tm = (int)(tile / (uint32_t)m.tiles_n), tn = (int)(tile % (uint32_t)m.tiles_n);
-    if (m.tile == GEMM_TILE_128)
-        gemm_tile<ACCX_T128(6, PL_FULL6)>(g, tm, tn, lds);
-    else
-        gemm_tile<ACCX_T64(6, PL_FULL6)>(g, tm, tn, lds);
+    const bool t128 = m.tile == GEMM_TILE_128;
+    if constexpr (!AUTO) {
+        if (t128)
+            gemm_tile<ACCX_T128(6, PL_FULL6)>(g, tm, tn, lds);
+        else
+            gemm_tile<ACCX_T64(6, PL_FULL6)>(g, tm, tn, lds);
+    } else {
+        if (t128)
+            gemm_tile<ACCX_T128(3, PL_CHEAP3)>(g, tm, tn, lds);
+        else
+            gemm_tile<ACCX_T64(3, PL_CHEAP3)>(g, tm, tn, lds);
+        // This tile of C is read back only by this workgroup (probe, then the
+        // correction's read-modify-write), so the barrier's workgroup-scope
+        // release and acquire make it visible; a device-scope fence here
+        // would write back the L2 after every tile.  The LDS stages are free
+        // after the barrier too.
+        __syncthreads();
+        const int bt = t128 ? 128 : 64;
+        if (!probe_tile<BT>(m.pa, m.pb, m.c, m.len, m.len, m.len, m.len, bt, bt, tile, tm, tn, m.nkb, tau2, nullptr,
+                            *reinterpret_cast<ProbeLds *>(lds)))
+            return;
+        // marked: C += the three correction products, on the 64 x 64 tiles
+        // inside this one (those that lie in C), as the standalone correction
+        GemmArgs h = g;
+        h.accumulate = 1;
+        h.tiles_m = h.tiles_n = (int)((m.len + 63) / 64);
+        const int sub = bt / 64;
+        for (int i = 0; i < sub; ++i)
+            for (int j = 0; j < sub; ++j) {
+                const int sm = tm * sub + i, sn = tn * sub + j;
+                if (sm >= h.tiles_m || sn >= h.tiles_n) continue;
+                __syncthreads();  // the LDS stages are reused
+                gemm_tile<ACCX_T64(3, PL_CORR3)>(h, sm, sn, lds);
+            }
+    }
 }
 
+template <bool AUTO>
 __global__ __launch_bounds__(BT, WG_PER_CU) void batch_persistent(BatchQueue q)
 {
     __shared__ __attribute__((aligned(1024))) char lds[LDS_MAX];
@@ -157,7 +199,7 @@ __global__ __launch_bounds__(BT, WG_PER_CU) void batch_persistent(BatchQueue q)
         if (w.item & UNIT_RED)
             reduce_chunk(q.reds[w.item & ~UNIT_RED], w.sub, red4, &is_last);
         else
-            matmul_unit(q.mats[w.item], w.sub, lds);
+            matmul_unit<AUTO>(q.mats[w.item], w.sub, lds, q.tau2);
         __syncthreads();  // LDS and shared scalars are reused by the next unit
     }
     // The last workgroup out resets the queue for the next launch.
@@ -188,7 +230,10 @@ hipError_t launch_batch_pack(const BatchPackJob *jobs, int njobs, hipStream_t s)
 hipError_t launch_batch_persistent(const BatchQueue &q, hipStream_t s)
 {
     tmark("batch_persistent", s, true);
-    hipLaunchKernelGGL(batch_persistent, dim3((unsigned)batch_workgroups()), dim3(BT), 0, s, q);
+    if (q.auto_prec)
+        hipLaunchKernelGGL(batch_persistent<true>, dim3((unsigned)batch_workgroups()), dim3(BT), 0, s, q);
+    else
+        hipLaunchKernelGGL(batch_persistent<false>, dim3((unsigned)batch_workgroups()), dim3(BT), 0, s, q);
     tmark("batch_persistent", s, false);
     return hipGetLastError();
 }

@@ -502,172 +502,19 @@ __global__ __launch_bounds__(512) void gemm_i8_multi(GemmArgs g)
 // ------------------------------------------------------- float64 probe --
 
 
-// bf16 element (plane p, operand row r, element k) of a packed bf16x3 operand
-// with nkb 64-byte units per row.
-__device__ inline float packed_bf16(const char *base, int64_t nkb, int p, int64_t r, int64_t k)
-{
-    const int64_t unit = (r >> 5) * nkb + (k >> 5);
-    const uint16_t h = *reinterpret_cast<const uint16_t *>(base + unit * (3 * PLANE_BYTES) + p * PLANE_BYTES +
-                                                           ((k & 31) >> 3) * 512 + (r & 31) * 16 + (k & 7) * 2);
-    return __uint_as_float((uint32_t)h << 16);
-}
-
-constexpr int PS = PROBE_SIDE;  // sampled rows (and columns) per tile
-
-// The k-th of PS consecutive positions in [0, extent), starting at a hashed
-// multiple of PS (salt 0: rows, 1: columns); clamped at a ragged edge.  PS
-// consecutive rows of a packed operand share each 128-byte line of a 16-byte
-// K chunk (rows are 16 bytes apart in a unit), so the probe reads whole
-// lines; rows spread over the tile would use 16 bytes of each.
-__device__ inline int probe_pick(int64_t tile, int k, int extent, int salt)
-{
-    const int blocks = (extent + PS - 1) / PS;
-    const int b = (int)(hash32((uint32_t)(tile * 2 + salt) * 2654435761u + 977u) % (uint32_t)blocks);
-    const int v = b * PS + k;
-    return v < extent ? v : extent - 1;
-}
-
-// One workgroup per output tile of the cheap pass.  It takes PS consecutive
-// rows and PS consecutive columns of the tile (hashed block positions),
-// computes the PS x PS dot products in float64 from the exact operands (each
-// float32 x float32 product is exact in float64), compares them with the
-// cheap result C, and marks the tile for correction when the sampled relative
-// Frobenius error exceeds tau (or the samples are all zero but C is not).
-//
-// K runs in passes of PK elements: the workgroup first rebuilds the PS rows
-// of A and PS rows of B^T for the pass as exact float32 in LDS (each thread
-// loads 16-byte chunks of the three planes; eight neighbouring lanes read
-// one 128-byte line), then thread t adds products for sample t % 64 over the
-// t / 64-th eighth of the pass.  The eight partial sums of a sample are added
-// in eighth order at the end.
+// One workgroup per output tile of the cheap pass: probe_tile (mfma_tile.h)
+// with 512 threads, records written for the correction launch.
 constexpr int PROBE_THREADS = 512;
-constexpr int PK = 1024;             // K elements per pass
-constexpr int PKS = PK + 4;          // LDS row stride (floats): rows fall in different banks
 
 __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restrict__ pa, const char *__restrict__ pb,
                                                            const float *__restrict__ C, GemmShape sh, int bm, int bn,
                                                            int tiles_n, int64_t nkb, double tau2,
                                                            ProbeRecord *__restrict__ rec)
 {
-    constexpr int NW = PROBE_THREADS / 64;                // K slices per pass (one per wavefront)
-    constexpr int CH = PK / 8;                            // 16-byte chunks per row per pass
-    static_assert(PS * PS == 64 && PS == 8, "8 x 8 samples, one per lane");
-    static_assert((2 * PS * CH) % PROBE_THREADS == 0, "chunks divide over the threads");
-    __shared__ __attribute__((aligned(16))) float xs[2][PS][PKS];  // [A / B^T][sample row][k in pass]
-    __shared__ double part[NW][PS * PS];
+    __shared__ __attribute__((aligned(16))) ProbeLds L;
     const int64_t tile = blockIdx.x;
-    const int tm = (int)(tile / tiles_n), tn = (int)(tile % tiles_n);
-    const int64_t row0 = (int64_t)tm * bm, col0 = (int64_t)tn * bn;
-    const int rext = (int)min<int64_t>(bm, sh.m - row0), cext = (int)min<int64_t>(bn, sh.n - col0);
-    const int q = threadIdx.x & 63, slice = threadIdx.x >> 6;
-    const int u = q / PS, v = q % PS;
-    const int64_t kpad = nkb * 32;                        // elements the packed operands hold per row
-    double acc = 0.0;
-    // The raw plane words of the next pass are loaded while this pass is
-    // staged and summed (double buffering in registers); the barriers are raw
-    // s_barrier after an LDS-only wait, since a full workgroup fence would
-    // also wait for those loads.
-    constexpr int PER = 2 * PS * CH / PROBE_THREADS;  // 16-byte chunks per thread per pass
-    constexpr int LGKM0 = 0xF | (7 << 4) | (3 << 14);  // s_waitcnt lgkmcnt(0)
-    // chunk j of this thread: operand ab, sample row r, chunk ch of a pass
-    const char *src[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int id = threadIdx.x + j * PROBE_THREADS;
-        const int r = id % PS, ab = id / (PS * CH);
-        const int64_t rr = ab == 0 ? row0 + probe_pick(tile, r, rext, 0) : col0 + probe_pick(tile, r, cext, 1);
-        src[j] = (ab == 0 ? pa : pb) + (rr >> 5) * nkb * (3 * PLANE_BYTES) + (rr & 31) * 16;
-    }
-    u32x4_t rh[PER], rm[PER], rl[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int ch = ((threadIdx.x + j * PROBE_THREADS) / PS) % CH;
-        const int64_t k8 = (int64_t)ch * 8;
-        const char *c = src[j] + (k8 >> 5) * (3 * PLANE_BYTES) + ((k8 & 31) >> 3) * 512;
-        const bool in = k8 < kpad;
-        rh[j] = in ? *reinterpret_cast<const u32x4_t *>(c) : u32x4_t{0, 0, 0, 0};
-        rm[j] = in ? *reinterpret_cast<const u32x4_t *>(c + PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
-        rl[j] = in ? *reinterpret_cast<const u32x4_t *>(c + 2 * PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
-    }
-    for (int64_t k0 = 0; k0 < sh.k; k0 += PK) {
-        // stage: chunk id -> (operand, chunk in pass, sample row); row fastest;
-        // hi + mid + lo of a float32 x is x itself (the two additions are exact)
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int id = threadIdx.x + j * PROBE_THREADS;
-            const int r = id % PS, ch = (id / PS) % CH, ab = id / (PS * CH);
-            float x[8];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                x[2 * w] = (__uint_as_float(rh[j][w] << 16) + __uint_as_float(rm[j][w] << 16)) +
-                           __uint_as_float(rl[j][w] << 16);
-                x[2 * w + 1] = (__uint_as_float(rh[j][w] & 0xffff0000u) + __uint_as_float(rm[j][w] & 0xffff0000u)) +
-                               __uint_as_float(rl[j][w] & 0xffff0000u);
-            }
-            float4 *d = reinterpret_cast<float4 *>(&xs[ab][r][ch * 8]);
-            d[0] = make_float4(x[0], x[1], x[2], x[3]);
-            d[1] = make_float4(x[4], x[5], x[6], x[7]);
-        }
-        __builtin_amdgcn_s_waitcnt(LGKM0);
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-        if (k0 + PK < sh.k) {
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int ch = ((threadIdx.x + j * PROBE_THREADS) / PS) % CH;
-                const int64_t k8 = k0 + PK + (int64_t)ch * 8;
-                const char *c = src[j] + (k8 >> 5) * (3 * PLANE_BYTES) + ((k8 & 31) >> 3) * 512;
-                const bool in = k8 < kpad;
-                rh[j] = in ? *reinterpret_cast<const u32x4_t *>(c) : u32x4_t{0, 0, 0, 0};
-                rm[j] = in ? *reinterpret_cast<const u32x4_t *>(c + PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
-                rl[j] = in ? *reinterpret_cast<const u32x4_t *>(c + 2 * PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
-            }
-        }
-        const float4 *ar = reinterpret_cast<const float4 *>(&xs[0][u][slice * (PK / NW)]);
-        const float4 *br = reinterpret_cast<const float4 *>(&xs[1][v][slice * (PK / NW)]);
-#pragma unroll 8
-        for (int j = 0; j < PK / NW / 4; ++j) {
-            const float4 a4 = ar[j], b4 = br[j];
-            acc = __builtin_fma((double)a4.x, (double)b4.x, acc);
-            acc = __builtin_fma((double)a4.y, (double)b4.y, acc);
-            acc = __builtin_fma((double)a4.z, (double)b4.z, acc);
-            acc = __builtin_fma((double)a4.w, (double)b4.w, acc);
-        }
-        // the next pass overwrites xs: every LDS read above has been consumed
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-    }
-    part[slice][q] = acc;
-    __syncthreads();
-    // wavefront 0, one sample per lane: compare, then sum the squares over
-    // the wavefront (a fixed butterfly: every lane ends with the same sums)
-    if (threadIdx.x < 64) {
-        const int64_t row = row0 + probe_pick(tile, u, rext, 0), col = col0 + probe_pick(tile, v, cext, 1);
-        double ref = part[0][q];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) ref += part[w][q];
-        const double c = (double)C[row * sh.ldc + col];
-        ProbeRecord &r = rec[tile];
-        r.ref[q] = ref;
-        double e2 = (c - ref) * (c - ref), r2 = ref * ref;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            e2 += __shfl_xor(e2, o, 64);
-            r2 += __shfl_xor(r2, o, 64);
-        }
-        if (q < PS) {
-            r.rows[q] = (int32_t)(row0 + probe_pick(tile, q, rext, 0));
-            r.cols[q] = (int32_t)(col0 + probe_pick(tile, q, cext, 1));
-        }
-        if (q == 0) {
-            r.err2 = e2;
-            r.ref2 = r2;
-            r.corrected = (r2 > 0.0) ? (e2 > tau2 * r2) : (e2 > 0.0);
-            r.pad[0] = r.pad[1] = r.pad[2] = 0;
-        }
-    }
+    probe_tile<PROBE_THREADS>(pa, pb, C, sh.m, sh.n, sh.k, sh.ldc, bm, bn, tile, (int)(tile / tiles_n),
+                              (int)(tile % tiles_n), nkb, tau2, rec + tile, L);
 }
 
 // Tile configurations (BM x BN, wavefront grid, K-step bytes, ring depth):

@@ -185,6 +185,8 @@ struct BatchQueue {
     const BatchUnit *units;
     uint32_t nunits;
     uint32_t *counter, *done;  // zero before the first launch; left at zero
+    int32_t auto_prec;         // 1: three products + per-tile float64 probe + correction; 0: six products
+    double tau2;               // AUTO: squared relative error bound of the probe
 };
 int batch_tile_supported(int tile);
 int batch_workgroups();

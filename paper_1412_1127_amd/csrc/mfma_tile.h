@@ -711,5 +711,187 @@ __device__ inline uint32_t hash32(uint32_t x)
     return x;
 }
 
+// ---------------------------------------------------------- float64 probe --
+
+constexpr int PS = PROBE_SIDE;       // sampled rows (and columns) per tile
+constexpr int PROBE_PK = 1024;       // K elements per pass
+constexpr int PROBE_PKS = PROBE_PK + 4;  // LDS row stride (floats): rows fall in different banks
+constexpr int PROBE_NW = 8;          // K slices per pass, summed separately and then in slice order
+
+// The k-th of PS consecutive positions in [0, extent), starting at a hashed
+// multiple of PS (salt 0: rows, 1: columns); clamped at a ragged edge.  PS
+// consecutive rows of a packed operand share each 128-byte line of a 16-byte
+// K chunk (rows are 16 bytes apart in a unit), so the probe reads whole
+// lines; rows spread over the tile would use 16 bytes of each.
+__device__ inline int probe_pick(int64_t tile, int k, int extent, int salt)
+{
+    const int blocks = (extent + PS - 1) / PS;
+    const int b = (int)(hash32((uint32_t)(tile * 2 + salt) * 2654435761u + 977u) % (uint32_t)blocks);
+    const int v = b * PS + k;
+    return v < extent ? v : extent - 1;
+}
+
+struct ProbeLds {
+    float xs[2][PS][PROBE_PKS];   // [A / B^T][sample row][k in pass], exact float32
+    double part[PROBE_NW][PS * PS];
+    int marked;
+};
+
+// The float64 error probe of one output tile (tile index `tile` = tm *
+// tiles_n + tn, bm x bn) of a cheap-pass result C (m x n, leading dimension
+// ldc), by a workgroup of THREADS threads (64 to 512, a multiple of 64).  It
+// takes PS consecutive rows and PS consecutive columns of the tile (hashed
+// block positions), computes the PS x PS dot products in float64 from the
+// exact operands (each float32 x float32 product is exact in float64),
+// compares them with C, and marks the tile for correction when the sampled
+// relative Frobenius error exceeds sqrt(tau2) (or the samples are all zero
+// but C is not).  C must be visible to the workgroup.  Returns the decision
+// in every thread; rec (nullable) receives the record.
+//
+// K runs in passes of PROBE_PK elements: the workgroup first rebuilds the PS
+// rows of A and PS rows of B^T for the pass as exact float32 in LDS (each
+// thread loads 16-byte chunks of the three planes; eight neighbouring lanes
+// read one 128-byte line), then sample q's products over the w-th of
+// PROBE_NW slices of the pass go to one float64 accumulator (wavefront
+// w % (THREADS / 64), lane q), which carries them over the passes; the
+// PROBE_NW slice sums of a sample are added in slice order at the end.  The
+// sums therefore do not depend on THREADS.  A pass stages and sums only the
+// 8-element chunks that hold elements below k (the rest of a pass would add
+// exact zero products, which change no sum but the sign of a zero one, and
+// no decision).  The raw plane words of the next
+// pass are loaded while this pass is staged and summed (double buffering in
+// registers); the barriers are raw s_barrier after an LDS-only wait, since a
+// full workgroup fence would also wait for those loads.
+template <int THREADS>
+__device__ __attribute__((always_inline)) inline bool probe_tile(const char *__restrict__ pa,
+                                                                 const char *__restrict__ pb,
+                                                                 const float *__restrict__ C, int64_t m, int64_t n,
+                                                                 int64_t k, int64_t ldc, int bm, int bn, int64_t tile,
+                                                                 int tm, int tn, int64_t nkb, double tau2,
+                                                                 ProbeRecord *__restrict__ rec, ProbeLds &L)
+{
+    constexpr int WAVES = THREADS / 64;
+    constexpr int SPW = PROBE_NW / WAVES;             // slices per wavefront
+    constexpr int CH = PROBE_PK / 8;                  // 16-byte chunks per row per pass
+    constexpr int PER = 2 * PS * CH / THREADS;        // 16-byte chunks per thread per pass
+    static_assert(PS * PS == 64 && PS == 8, "8 x 8 samples, one per lane");
+    static_assert(THREADS % 64 == 0 && PROBE_NW % WAVES == 0 && (2 * PS * CH) % THREADS == 0, "thread count");
+    constexpr int LGKM0 = 0xF | (7 << 4) | (3 << 14);  // s_waitcnt lgkmcnt(0)
+    const int64_t row0 = (int64_t)tm * bm, col0 = (int64_t)tn * bn;
+    const int rext = (int)min<int64_t>(bm, m - row0), cext = (int)min<int64_t>(bn, n - col0);
+    const int q = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int u = q / PS, v = q % PS;
+    const int64_t kpad = nkb * 32;                    // elements the packed operands hold per row
+    double acc[SPW];
+#pragma unroll
+    for (int z = 0; z < SPW; ++z) acc[z] = 0.0;
+    // chunk j of this thread: operand ab, sample row r, chunk ch of a pass
+    const char *src[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int id = threadIdx.x + j * THREADS;
+        const int r = id % PS, ab = id / (PS * CH);
+        const int64_t rr = ab == 0 ? row0 + probe_pick(tile, r, rext, 0) : col0 + probe_pick(tile, r, cext, 1);
+        src[j] = (ab == 0 ? pa : pb) + (rr >> 5) * nkb * (3 * PLANE_BYTES) + (rr & 31) * 16;
+    }
+    u32x4_t rh[PER], rm[PER], rl[PER];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int ch = ((threadIdx.x + j * THREADS) / PS) % CH;
+            const int64_t k8 = k0 + (int64_t)ch * 8;
+            const char *c = src[j] + (k8 >> 5) * (3 * PLANE_BYTES) + ((k8 & 31) >> 3) * 512;
+            const bool in = k8 < kpad;
+            rh[j] = in ? *reinterpret_cast<const u32x4_t *>(c) : u32x4_t{0, 0, 0, 0};
+            rm[j] = in ? *reinterpret_cast<const u32x4_t *>(c + PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
+            rl[j] = in ? *reinterpret_cast<const u32x4_t *>(c + 2 * PLANE_BYTES) : u32x4_t{0, 0, 0, 0};
+        }
+    };
+    load(0);
+    for (int64_t k0 = 0; k0 < k; k0 += PROBE_PK) {
+        const int kk = (int)min<int64_t>(PROBE_PK, k - k0);  // elements of this pass below k
+        const int nch = (kk + 7) / 8;                       // chunks staged and read
+        // stage: chunk id -> (operand, chunk in pass, sample row); row fastest;
+        // hi + mid + lo of a float32 x is x itself (the two additions are exact)
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int id = threadIdx.x + j * THREADS;
+            const int r = id % PS, ch = (id / PS) % CH, ab = id / (PS * CH);
+            if (ch >= nch) continue;
+            float x[8];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                x[2 * w] = (__uint_as_float(rh[j][w] << 16) + __uint_as_float(rm[j][w] << 16)) +
+                           __uint_as_float(rl[j][w] << 16);
+                x[2 * w + 1] = (__uint_as_float(rh[j][w] & 0xffff0000u) + __uint_as_float(rm[j][w] & 0xffff0000u)) +
+                               __uint_as_float(rl[j][w] & 0xffff0000u);
+            }
+            float4 *d = reinterpret_cast<float4 *>(&L.xs[ab][r][ch * 8]);
+            d[0] = make_float4(x[0], x[1], x[2], x[3]);
+            d[1] = make_float4(x[4], x[5], x[6], x[7]);
+        }
+        __builtin_amdgcn_s_waitcnt(LGKM0);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (k0 + PROBE_PK < k) load(k0 + PROBE_PK);
+#pragma unroll
+        for (int z = 0; z < SPW; ++z) {
+            const int slice = wave + z * WAVES;
+            const float4 *ar = reinterpret_cast<const float4 *>(&L.xs[0][u][slice * (PROBE_PK / PROBE_NW)]);
+            const float4 *br = reinterpret_cast<const float4 *>(&L.xs[1][v][slice * (PROBE_PK / PROBE_NW)]);
+            // float4 groups of this slice below kk (whole staged chunks)
+            const int ng = min(PROBE_PK / PROBE_NW / 4, max(0, (kk - slice * (PROBE_PK / PROBE_NW) + 3) / 4));
+#pragma unroll 8
+            for (int j = 0; j < ng; ++j) {
+                const float4 a4 = ar[j], b4 = br[j];
+                acc[z] = __builtin_fma((double)a4.x, (double)b4.x, acc[z]);
+                acc[z] = __builtin_fma((double)a4.y, (double)b4.y, acc[z]);
+                acc[z] = __builtin_fma((double)a4.z, (double)b4.z, acc[z]);
+                acc[z] = __builtin_fma((double)a4.w, (double)b4.w, acc[z]);
+            }
+        }
+        // the next pass overwrites xs: every LDS read above has been consumed
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int z = 0; z < SPW; ++z) L.part[wave + z * WAVES][q] = acc[z];
+    __syncthreads();
+    // wavefront 0, one sample per lane: compare, then sum the squares over
+    // the wavefront (a fixed butterfly: every lane ends with the same sums)
+    if (threadIdx.x < 64) {
+        const int64_t row = row0 + probe_pick(tile, u, rext, 0), col = col0 + probe_pick(tile, v, cext, 1);
+        double ref = L.part[0][q];
+#pragma unroll
+        for (int w = 1; w < PROBE_NW; ++w) ref += L.part[w][q];
+        const double c = (double)C[row * ldc + col];
+        double e2 = (c - ref) * (c - ref), r2 = ref * ref;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            e2 += __shfl_xor(e2, o, 64);
+            r2 += __shfl_xor(r2, o, 64);
+        }
+        const int marked = (r2 > 0.0) ? (e2 > tau2 * r2) : (e2 > 0.0);
+        if (rec) {
+            rec->ref[q] = ref;
+            if (q < PS) {
+                rec->rows[q] = (int32_t)(row0 + probe_pick(tile, q, rext, 0));
+                rec->cols[q] = (int32_t)(col0 + probe_pick(tile, q, cext, 1));
+            }
+            if (q == 0) {
+                rec->err2 = e2;
+                rec->ref2 = r2;
+                rec->corrected = marked;
+                rec->pad[0] = rec->pad[1] = rec->pad[2] = 0;
+            }
+        }
+        if (q == 0) L.marked = marked;
+    }
+    __syncthreads();
+    return L.marked != 0;
+}
+
 }  // namespace dev
 }  // namespace accx

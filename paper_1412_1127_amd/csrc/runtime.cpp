@@ -95,6 +95,7 @@ constexpr int kMaxSlots = 256;
 
 std::set<accx_batch_s *> &batches();  // open batches (defined with the batch code)
 void batch_release(accx_batch_s *b);
+void batch_destroy_all();  // release and delete every open batch
 
 struct State {
     std::recursive_mutex mu;
@@ -952,11 +953,7 @@ acc_status acc_shutdown(void)
         delete r;
     }
     st.regions.clear();
-    for (accx_batch_s *b : batches()) {
-        batch_release(b);
-        delete b;
-    }
-    batches().clear();
+    batch_destroy_all();
     for (auto *m : {&st.mm_ws, &st.red_ws, &st.red_plain_ws, &st.red_vars_ws}) {
         for (auto &kv : *m) ws_release(kv.second);
         m->clear();
@@ -1832,6 +1829,7 @@ const char *acc_status_string(acc_status s)
     case ACC_ERR_OUT_OF_MEMORY: return "ACC_ERR_OUT_OF_MEMORY";
     case ACC_ERR_DEVICE: return "ACC_ERR_DEVICE";
     case ACC_ERR_NO_DEVICE: return "ACC_ERR_NO_DEVICE";
+    default: break;
     }
     return "unknown acc_status";
 }
@@ -1957,6 +1955,15 @@ std::vector<accx::BatchUnit> batch_units(std::vector<accx::BatchMat> &mats, cons
     return units;
 }
 
+void batch_destroy_all()
+{
+    for (accx_batch_s *b : batches()) {
+        batch_release(b);
+        delete b;
+    }
+    batches().clear();
+}
+
 void batch_release(accx_batch_s *b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1987,7 +1994,9 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
     acc_status s = check_ready();
     if (s != ACC_OK) return s;
     if (nitems <= 0 || !items) return fail(ACC_ERR_INVALID_ARG, "empty batch");
-    if (flags & ~ACC_BATCH_AUTOTUNE) return fail(ACC_ERR_INVALID_ARG, "unknown batch flag");
+    if (flags & ~(ACC_BATCH_AUTOTUNE | ACC_BATCH_PREC_AUTO)) return fail(ACC_ERR_INVALID_ARG, "unknown batch flag");
+    const bool auto_prec = (flags & ACC_BATCH_PREC_AUTO) != 0;
+    const int products = auto_prec ? 3 : 6;
 
     std::vector<accx::BatchMat> mats;
     std::vector<accx::BatchRed> reds;
@@ -2014,13 +2023,13 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
             m.len = it.n;
             m.nkb = (it.n * 2 + 63) / 64;
             m.tile = batch_tile(it, kBatchDefaultThreshold);
-            m.products = 6;
+            m.products = products;
             mats.push_back(m);
             mat_item.push_back(i);
             pk_bytes.push_back(accx::packed_bytes(it.n, it.n, 2, 3));
             max_tiles += ((it.n + 63) / 64) * ((it.n + 63) / 64);
             info.flops += 2.0 * (double)it.n * (double)it.n * (double)it.n;
-            info.mfma_flops += 6.0 * 2.0 * (double)it.n * (double)it.n * (double)it.n;
+            info.mfma_flops += products * 2.0 * (double)it.n * (double)it.n * (double)it.n;
         } else if (it.kind == ACC_BATCH_REDUCE) {
             if (it.n < 0) return fail(ACC_ERR_INVALID_ARG, where + "n must be >= 0");
             if ((it.n > 0 && !it.a) || !it.c) return fail(ACC_ERR_INVALID_ARG, where + "NULL pointer");
@@ -2097,6 +2106,8 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
         b->queue.counter = z;
         b->queue.done = z + 1;
     }
+    b->queue.auto_prec = auto_prec ? 1 : 0;
+    b->queue.tau2 = probe_tau() * probe_tau();
     b->queue.mats = reinterpret_cast<const accx::BatchMat *>(base + o_mats);
     b->queue.reds = reinterpret_cast<const accx::BatchRed *>(base + o_reds);
     b->queue.units = reinterpret_cast<const accx::BatchUnit *>(base + o_units);

@@ -22,14 +22,17 @@ def ax():
 class Batch:
     """Seeded inputs on the device, the batch items, and host copies."""
 
-    def __init__(self, ax, lens, ns, seed, tile=0, offsets=None):
+    def __init__(self, ax, lens, ns, seed, tile=0, offsets=None, flags=0, gen=None):
         import torch
         self.ax = ax
         self.mats, self.reds = [], []
         items = []
         for k, n in enumerate(lens):
-            a = synth.uniform_pm1_f32((n, n), seed, 1000 + 2 * k)
-            b = synth.uniform_pm1_f32((n, n), seed, 1001 + 2 * k)
+            if gen is not None and gen(k) is not None:
+                a, b = gen(k)(n, seed, 1000 + 2 * k), gen(k)(n, seed, 1001 + 2 * k)
+            else:
+                a = synth.uniform_pm1_f32((n, n), seed, 1000 + 2 * k)
+                b = synth.uniform_pm1_f32((n, n), seed, 1001 + 2 * k)
             da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
             dc = torch.full((n, n), float("nan"), device="cuda")
             self.mats.append((a, b, da, db, dc, n))
@@ -43,8 +46,8 @@ class Batch:
             init = 0.25 * k
             self.reds.append((x, buf, res, n, init))
             items.append(ax.batch_reduce(buf.data_ptr() + 4 * off, n, res, init))
-        print("batch: %d matmuls, %d reductions" % (len(lens), len(ns)), flush=True)
-        self.handle = ax.accx_batch_create(items)
+        print("batch: %d matmuls, %d reductions, flags %#x" % (len(lens), len(ns), flags), flush=True)
+        self.handle = ax.accx_batch_create(items, flags)
 
     def outputs(self):
         import torch
@@ -91,6 +94,79 @@ def test_batch_matmul_bitwise_equals_standalone(ax):
             torch.cuda.synchronize()
             assert np.array_equal(c, solo.cpu().numpy()), (tile, n)
         bt.close()
+
+
+def _biased_split(n, seed, stream):
+    # x = h + m + l, each on its own bf16 grid and all positive: the three
+    # products the cheap pass drops add up instead of cancelling (2.3e-5
+    # relative error without the correction)
+    g = synth.rng(seed, stream)
+    h = 1.0 + g.integers(0, 16, (n, n)) * 2.0 ** -7
+    m = 2.0 ** -9 * (1.0 + g.integers(64, 128, (n, n)) * 2.0 ** -7)
+    l = 2.0 ** -18 * (1.0 + g.integers(16, 32, (n, n)) * 2.0 ** -5)
+    return (h + m + l).astype(np.float32)
+
+
+def _low_precision(n, seed, stream):
+    # 8-bit significands: one bf16 term per input, the cheap pass is exact
+    g = synth.rng(seed, stream)
+    return (g.integers(-128, 128, (n, n)) * 2.0 ** -7).astype(np.float32)
+
+
+def _auto_gen(k):
+    return [None, _biased_split, _low_precision][k % 3]
+
+
+def test_auto_batch_bitwise_equals_standalone_auto(ax):
+    import torch
+    lens = [96, 256, 700, 130, 512, 64]
+    for tile in (ax.ACC_TILE_128, ax.ACC_TILE_64):
+        bt = Batch(ax, lens, [1000], SEED + 5, tile=tile, flags=ax.ACC_BATCH_PREC_AUTO, gen=_auto_gen)
+        ax.accx_batch_launch(bt.handle)
+        cs, _ = bt.outputs()
+        for k, ((a, b, da, db, dc, n), c) in enumerate(zip(bt.mats, cs)):
+            solo = torch.empty_like(dc)
+            # the packed operands and the probe records, no split area: the
+            # standalone AUTO call runs unsplit, as the batch does
+            flags = ax.ACC_KERNEL_TILED | ax.ACC_PREC_AUTO | tile
+            off, _cnt = ax.accx_probe_layout(n, flags)
+            _o, cnt64 = ax.accx_probe_layout(n, ax.ACC_KERNEL_TILED | ax.ACC_PREC_AUTO | ax.ACC_TILE_64)
+            base = off + cnt64 * 608
+            w = torch.empty(base, dtype=torch.uint8, device="cuda")
+            ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, solo, n, flags, w, base)
+            torch.cuda.synchronize()
+            assert np.array_equal(c, solo.cpu().numpy()), (tile, n, k)
+            assert rel_fro(c, oracle.matmul_f32(a, b)) <= FP32_REL_FRO_TOL, (tile, n, k)
+        bt.close()
+
+
+def test_auto_batch_corrects_and_replays(ax):
+    # every third matmul has biased-split inputs (the cheap pass alone is
+    # off by about 2.3e-5): only the per-tile probe and correction bring it
+    # within the bound; graph replays equal the eager launch
+    import torch
+    g = synth.rng(SEED, 12)
+    lens = [int(v) for v in g.choice([64 * k for k in range(1, 12)], 18)]
+    ns = [int(v) for v in g.integers(1 << 10, 1 << 20, 6)]
+    bt = Batch(ax, lens, ns, SEED + 6, flags=ax.ACC_BATCH_PREC_AUTO | ax.ACC_BATCH_AUTOTUNE, gen=_auto_gen)
+    ax.accx_batch_launch_eager(bt.handle)
+    ref_c, ref_r = bt.outputs()
+    for k, ((a, b, *_r, n), c) in enumerate(zip(bt.mats, ref_c)):
+        assert rel_fro(c, oracle.matmul_f32(a, b)) <= FP32_REL_FRO_TOL, (k, n)
+    for (x, _b, _r, n, init), got in zip(bt.reds, ref_r):
+        ref = oracle.sum_f32(x, init)
+        assert abs(got - ref) <= 1e-5 * abs(ref), (n, got, ref)
+    for rep in range(2):
+        for m in bt.mats:
+            m[4].fill_(float("nan"))
+        (torch.randn(1 << 20, device="cuda") * 2).sum().item()
+        ax.accx_batch_launch(bt.handle)
+        cs, rs = bt.outputs()
+        assert all(np.array_equal(x, y) for x, y in zip(cs, ref_c)), rep
+        assert rs == ref_r, rep
+    info = ax.accx_batch_info(bt.handle)
+    assert info["mfma_flops"] == 3 * info["flops"]
+    bt.close()
 
 
 def test_graph_replays_equal_eager(ax):
