@@ -700,7 +700,9 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
         }
 }
 
-// 32-bit integer hash (timing operands, probe positions).
+// 32-bit integer hash (timing operands, probe positions): the published
+// xorshift-multiply "lowbias32" mixer (two multiply rounds, shifts 16, 15,
+// 16).
 __device__ inline uint32_t hash32(uint32_t x)
 {
     x ^= x >> 16;
