@@ -149,6 +149,65 @@ __device__ inline uint32_t pack_i8_items(const int32_t *__restrict__ X, int64_t 
     return mx;
 }
 
+// One digit (the low byte of each element) of int32 rows into the packed
+// layout, with coalesced loads: a wavefront takes 4 rows x 64 elements of one
+// unit (lane l: row l / 16, elements 4 (l % 16) .. +3 -- one 16-byte load;
+// 16 lanes read a row's 256 bytes), packs the low bytes of its four elements
+// into one word and stores it at its place in the unit (four lanes fill one
+// 16-byte chunk).  Work items are (32-row block, 4-row group, K unit), K
+// fastest, so that consecutive wavefronts walk along the same rows; each
+// wavefront keeps NI items' loads in flight.  w0 / wstep: this wavefront's
+// first item and the number of wavefronts.  Returns the lane's max |x|.
+__device__ inline uint32_t pack_i8_rows_one(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
+                                            char *__restrict__ out, int64_t nrb, int64_t nkb, int pstride, int64_t w0,
+                                            int64_t wstep)
+{
+    constexpr int NI = 4;
+    const int lane = threadIdx.x & 63;
+    const int lr = lane >> 4, lk = (lane & 15) * 4;
+    const int64_t items = nrb * 8 * nkb;
+    const bool vec = ((ld & 3) == 0) && ((((uintptr_t)X) & 15u) == 0);
+    uint32_t mx = 0;
+    for (int64_t i0 = w0; i0 < items; i0 += (int64_t)NI * wstep) {
+        i32x4 v[NI];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int64_t it = i0 + u * wstep;
+            v[u] = i32x4{0, 0, 0, 0};
+            if (it < items) {
+                const int64_t kb = it % nkb, rq = it / nkb;  // rq = 32-row block * 8 + row group
+                const int64_t row = rq * 4 + lr, k = kb * 64 + lk;
+                if (row < R) {
+                    if (vec && k + 4 <= K) {
+                        v[u] = *reinterpret_cast<const i32x4 *>(X + row * ld + k);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (k + e < K) v[u][e] = X[row * ld + k + e];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int64_t it = i0 + u * wstep;
+            if (it >= items) break;
+            const int64_t kb = it % nkb, rq = it / nkb;
+            const int64_t rb = rq >> 3;
+            const int r = (int)(rq & 7) * 4 + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t a = v[u][e] < 0 ? (uint32_t)0 - (uint32_t)v[u][e] : (uint32_t)v[u][e];
+                mx = a > mx ? a : mx;
+            }
+            char *o = out + (rb * nkb + kb) * ((int64_t)pstride * PLANE_BYTES) + (lk >> 4) * 512 + r * 16 +
+                      (lk & 15);
+            *reinterpret_cast<int *>(o) = low_bytes4(v[u][0], v[u][1], v[u][2], v[u][3]);
+        }
+    }
+    return mx;
+}
+
 // maxabs (optional): max |x| over the operand as block_max_record leaves it.
 template <bool TRANS>
 __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
@@ -342,6 +401,8 @@ __global__ __launch_bounds__(256) void pack_f32_pair(const float *__restrict__ A
 // The first `nplanes` int8 digit planes (of `pstride` per unit) of B^T for
 // column tile bx of X and part by % I8_SPLIT of the 64-element K unit
 // by / I8_SPLIT; returns the thread's max |x|.
+// ONE: nplanes is 1 (the multi-digit code is left out of the kernel).
+template <bool ONE>
 __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
                                         char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int pstride,
                                         int64_t bx, int64_t by, uint32_t (*t)[TP_COLS])
@@ -366,7 +427,7 @@ __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R
             mx = a > mx ? a : mx;
         }
         char *o = out + ((rb0 + u) * nkb + kb) * ((int64_t)pstride * PLANE_BYTES) + (part * CPT + c) * 512 + r * 16;
-        if (nplanes == 1) {  // one digit: the low bytes
+        if (ONE || nplanes == 1) {  // one digit: the low bytes
             *reinterpret_cast<i32x4 *>(o) = i32x4{low_bytes4(x[0], x[1], x[2], x[3]), low_bytes4(x[4], x[5], x[6], x[7]),
                                                   low_bytes4(x[8], x[9], x[10], x[11]),
                                                   low_bytes4(x[12], x[13], x[14], x[15])};
@@ -397,7 +458,7 @@ __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, 
 {
     __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
     const uint32_t mx =
-        pack_i8_cols(X, R, K, ld, out, nrb, nkb, nplanes, nplanes, blockIdx.x % gbx, blockIdx.x / gbx, t);
+        pack_i8_cols<false>(X, R, K, ld, out, nrb, nkb, nplanes, nplanes, blockIdx.x % gbx, blockIdx.x / gbx, t);
     if (maxabs) block_max_record(mx, maxabs);
 }
 
@@ -408,6 +469,9 @@ __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, 
 // decide (optional): the two max|x| words of a finished one-digit pass; the
 // launch is then the multi-digit pass: it runs only if more than one digit
 // is needed and writes that many planes (nplanes is ignored).
+// ONE: one digit (nplanes = 1, no decide): coalesced row packing for A and no
+// multi-digit code in the kernel (fewer registers, more wavefronts per CU).
+template <bool ONE>
 __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ A, int64_t M, int64_t lda,
                                                     char *__restrict__ pa, const int32_t *__restrict__ B, int64_t N,
                                                     int64_t ldb, char *__restrict__ pb, int64_t K, int nplanes,
@@ -423,12 +487,17 @@ __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ 
     const int64_t nkb = (K + 63) / 64;
     uint32_t mx = 0;
     if ((int)blockIdx.x < ga) {
-        mx = pack_i8_items<false>(A, M, K, lda, pa, (M + 31) / 32, nkb, np, pstride,
-                                  (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)ga * 256);
+        if constexpr (ONE)
+            mx = pack_i8_rows_one(A, M, K, lda, pa, (M + 31) / 32, nkb, pstride,
+                                  (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), (int64_t)ga * 4);
+        else
+            mx = pack_i8_items<false>(A, M, K, lda, pa, (M + 31) / 32, nkb, np, pstride,
+                                      (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)ga * 256);
     } else {
         // the staging buffer is reused: a barrier before each refill
         for (int64_t b = blockIdx.x - ga; b < gb; b += gridDim.x - ga) {
-            const uint32_t m = pack_i8_cols(B, N, K, ldb, pb, (N + 31) / 32, nkb, np, pstride, b % gbx, b / gbx, t);
+            const uint32_t m =
+                pack_i8_cols<ONE>(B, N, K, ldb, pb, (N + 31) / 32, nkb, np, pstride, b % gbx, b / gbx, t);
             mx = m > mx ? m : mx;
             __syncthreads();
         }
@@ -738,11 +807,18 @@ hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const i
         ga = std::min<int64_t>(ga, cap);
         gbl = std::min<int64_t>(gbl, cap);
     }
+    const bool one = !decide && planes == 1;
+    if (one && ua > 0) ga = std::min<int64_t>(cdiv(ua * 8, 4 * 4), (int64_t)device_cu_count() * 8);  // 4 items per wavefront
     if (ga + gbl == 0) return hipSuccess;
     tmark("pack_i8", s, true);
-    hipLaunchKernelGGL(pack_i8_pair, dim3((unsigned)(ga + gbl)), dim3(256), 0, s, a, m, lda, static_cast<char *>(pa),
-                       b, n, ldb, static_cast<char *>(pb), k, planes, decide ? 4 : planes, (int)ga,
-                       (int)std::max<int64_t>(gbx, 1), gb, maxabs, decide);
+    if (one)
+        hipLaunchKernelGGL(pack_i8_pair<true>, dim3((unsigned)(ga + gbl)), dim3(256), 0, s, a, m, lda,
+                           static_cast<char *>(pa), b, n, ldb, static_cast<char *>(pb), k, 1, 1, (int)ga,
+                           (int)std::max<int64_t>(gbx, 1), gb, maxabs, decide);
+    else
+        hipLaunchKernelGGL(pack_i8_pair<false>, dim3((unsigned)(ga + gbl)), dim3(256), 0, s, a, m, lda,
+                           static_cast<char *>(pa), b, n, ldb, static_cast<char *>(pb), k, planes, decide ? 4 : planes,
+                           (int)ga, (int)std::max<int64_t>(gbx, 1), gb, maxabs, decide);
     tmark("pack_i8", s, false);
     return hipGetLastError();
 }
