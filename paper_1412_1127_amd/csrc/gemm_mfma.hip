@@ -57,12 +57,15 @@ __device__ inline int low_bytes4(int32_t a, int32_t b, int32_t c, int32_t d)
 }
 
 // Record a workgroup's max |x| (256 threads, each holding its own max) in
-// *maxabs, which starts at zero.  Only maxima above 127 are recorded: the
-// digit count depends on max |x| only through thresholds from 127 up, so the
-// word ends as the operand's max |x| when that exceeds 127 and stays zero
-// otherwise.  One atomic per workgroup at most, and none on one-digit data
-// (a single contended address serialises every atomic on it).
-__device__ inline void block_max_record(uint32_t mx, uint32_t *maxabs)
+// the operand's word *maxabs (stamp << 32 | max, see recorded_max).  Only
+// maxima above 127 are recorded: the digit count depends on max |x| only
+// through thresholds from 127 up, so the word ends as this call's stamp and
+// the operand's max |x| when that exceeds 127, and is left as it was
+// otherwise.  A compare-and-swap loop replaces a word that carries another
+// stamp or a smaller maximum; none on one-digit data, and few once the
+// largest maxima are in (a single contended address serialises every atomic
+// on it).
+__device__ inline void block_max_record(uint32_t mx, uint64_t *maxabs, uint32_t stamp)
 {
     __shared__ uint32_t wmax[4];
 #pragma unroll
@@ -76,7 +79,14 @@ __device__ inline void block_max_record(uint32_t mx, uint32_t *maxabs)
         uint32_t m = wmax[0];
 #pragma unroll
         for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
-        if (m > 127u && m > __hip_atomic_load(maxabs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxabs, m);
+        if (m > 127u) {
+            uint64_t w = __hip_atomic_load(maxabs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t want = ((uint64_t)stamp << 32) | m;
+            while (recorded_max(w, stamp) < m &&
+                   !__hip_atomic_compare_exchange_strong(maxabs, &w, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)) {
+            }
+        }
     }
 }
 
@@ -208,15 +218,12 @@ __device__ inline uint32_t pack_i8_rows_one(const int32_t *__restrict__ X, int64
     return mx;
 }
 
-// maxabs (optional): max |x| over the operand as block_max_record leaves it.
 template <bool TRANS>
 __global__ __launch_bounds__(256) void pack_i8(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
-                                               char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
-                                               uint32_t *__restrict__ maxabs)
+                                               char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes)
 {
-    const uint32_t mx = pack_i8_items<TRANS>(X, R, K, ld, out, nrb, nkb, nplanes, nplanes,
-                                             (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
-    if (maxabs) block_max_record(mx, maxabs);
+    (void)pack_i8_items<TRANS>(X, R, K, ld, out, nrb, nkb, nplanes, nplanes, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                               (int64_t)gridDim.x * 256);
 }
 
 
@@ -451,21 +458,18 @@ __device__ inline uint32_t pack_i8_cols(const int32_t *__restrict__ X, int64_t R
 }
 
 // Grid: gbx column tiles of X per K tile, I8_SPLIT K tiles per K unit.
-// maxabs as for pack_i8.
 __global__ __launch_bounds__(256) void pack_i8_t(const int32_t *__restrict__ X, int64_t R, int64_t K, int64_t ld,
-                                                 char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes,
-                                                 uint32_t *__restrict__ maxabs, int gbx)
+                                                 char *__restrict__ out, int64_t nrb, int64_t nkb, int nplanes, int gbx)
 {
     __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
-    const uint32_t mx =
-        pack_i8_cols<false>(X, R, K, ld, out, nrb, nkb, nplanes, nplanes, blockIdx.x % gbx, blockIdx.x / gbx, t);
-    if (maxabs) block_max_record(mx, maxabs);
+    (void)pack_i8_cols<false>(X, R, K, ld, out, nrb, nkb, nplanes, nplanes, blockIdx.x % gbx, blockIdx.x / gbx, t);
 }
 
 // A and B^T of one product in one launch: workgroups [0, ga) pack the rows of
 // A (max |x| into maxabs[0]), the others the gb column tiles of B (gbx per K
 // tile, taken grid-stride; maxabs[1]).  Units hold `pstride` planes, of
-// which `nplanes` are written.  maxabs (optional) as for pack_i8.
+// which `nplanes` are written.  maxabs (optional): the two max|x| words of
+// this call (stamp `stamp`), as block_max_record leaves them.
 // decide (optional): the two max|x| words of a finished one-digit pass; the
 // launch is then the multi-digit pass: it runs only if more than one digit
 // is needed and writes that many planes (nplanes is ignored).
@@ -476,11 +480,12 @@ __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ 
                                                     char *__restrict__ pa, const int32_t *__restrict__ B, int64_t N,
                                                     int64_t ldb, char *__restrict__ pb, int64_t K, int nplanes,
                                                     int pstride, int ga, int gbx, int64_t gb,
-                                                    uint32_t *__restrict__ maxabs, const uint32_t *__restrict__ decide)
+                                                    uint64_t *__restrict__ maxabs, const uint64_t *__restrict__ decide,
+                                                    uint32_t stamp)
 {
     int np = nplanes;
     if (decide) {
-        np = limbs_needed(decide);
+        np = limbs_needed(decide, stamp);
         if (np == 1) return;  // uniform: the whole grid exits
     }
     __shared__ __attribute__((aligned(16))) uint32_t t[TP_ROWS][TP_COLS];
@@ -502,7 +507,7 @@ __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ 
             __syncthreads();
         }
     }
-    if (maxabs) block_max_record(mx, maxabs + ((int)blockIdx.x < ga ? 0 : 1));
+    if (maxabs) block_max_record(mx, maxabs + ((int)blockIdx.x < ga ? 0 : 1), stamp);
 }
 
 
@@ -518,7 +523,7 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
     // probe records are per tile of the probed pass, which may be larger
     if (g.probe && !g.probe[(tm >> g.probe_shm) * g.probe_tiles_n + (tn >> g.probe_shn)].corrected)
         return;                                                          // whole workgroup: uniform
-    if (g.decide && !limb_gate(g.decide, g.expect)) return;             // the whole grid: uniform
+    if (g.decide && !limb_gate(g.decide, g.gen, g.expect)) return;      // the whole grid: uniform
     if (g.ksplit > 1) {
         GemmArgs h = g;
         h.split = (int)(blockIdx.x / (unsigned)T);
@@ -549,7 +554,7 @@ __global__ __launch_bounds__(512) void gemm_i8_multi(GemmArgs g)
     constexpr uint64_t PLMAX = P >= 4 ? PL_L4 : P == 3 ? PL_L3 : PL_L2;
     constexpr int NPMAX = P >= 4 ? 10 : P == 3 ? 8 : 4;
     __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPMAX, PLMAX>()];
-    const int nd = g.decide ? limbs_needed(g.decide) : g.expect;
+    const int nd = g.decide ? limbs_needed(g.decide, g.gen) : g.expect;
     if (nd < 2) return;  // uniform: the whole grid exits
     const int T = g.tiles_m * g.tiles_n;
     for (int t = blockIdx.x; t < T; t += gridDim.x) {
@@ -763,7 +768,7 @@ hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, int64_t l
 }
 
 hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld, bool trans, int planes, void *out,
-                          uint32_t *maxabs, hipStream_t s)
+                          hipStream_t s)
 {
     const int64_t nrb = cdiv(rows, 32), nkb = cdiv(k, 64);
     if (nrb * nkb == 0) return hipSuccess;
@@ -771,10 +776,10 @@ hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld,
     tmark("pack_i8", s, true);
     if (trans)
         hipLaunchKernelGGL(pack_i8_t, dim3((unsigned)(cdiv(rows, TP_COLS) * I8_SPLIT * nkb)), dim3(256), 0, s, x, rows,
-                           k, ld, static_cast<char *>(out), nrb, nkb, planes, maxabs, (int)cdiv(rows, TP_COLS));
+                           k, ld, static_cast<char *>(out), nrb, nkb, planes, (int)cdiv(rows, TP_COLS));
     else
         hipLaunchKernelGGL(pack_i8<false>, dim3(grid), dim3(256), 0, s, x, rows, k, ld, static_cast<char *>(out), nrb,
-                           nkb, planes, maxabs);
+                           nkb, planes);
     tmark("pack_i8", s, false);
     return hipGetLastError();
 }
@@ -793,8 +798,8 @@ hipError_t launch_pack_bf16x3_pair(const float *a, int64_t m, int64_t lda, const
 }
 
 hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const int32_t *b, int64_t n, int64_t ldb,
-                               int64_t k, int planes, void *pa, void *pb, uint32_t *maxabs, hipStream_t s,
-                               const uint32_t *decide)
+                               int64_t k, int planes, void *pa, void *pb, uint64_t *maxabs, hipStream_t s,
+                               const uint64_t *decide, uint32_t stamp)
 {
     const int64_t nkb = cdiv(k, 64), ua = cdiv(m, 32) * nkb;
     int64_t ga = ua > 0 ? pack_grid(ua) : 0;
@@ -814,11 +819,11 @@ hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const i
     if (one)
         hipLaunchKernelGGL(pack_i8_pair<true>, dim3((unsigned)(ga + gbl)), dim3(256), 0, s, a, m, lda,
                            static_cast<char *>(pa), b, n, ldb, static_cast<char *>(pb), k, 1, 1, (int)ga,
-                           (int)std::max<int64_t>(gbx, 1), gb, maxabs, decide);
+                           (int)std::max<int64_t>(gbx, 1), gb, maxabs, decide, stamp);
     else
         hipLaunchKernelGGL(pack_i8_pair<false>, dim3((unsigned)(ga + gbl)), dim3(256), 0, s, a, m, lda,
                            static_cast<char *>(pa), b, n, ldb, static_cast<char *>(pb), k, planes, decide ? 4 : planes,
-                           (int)ga, (int)std::max<int64_t>(gbx, 1), gb, maxabs, decide);
+                           (int)ga, (int)std::max<int64_t>(gbx, 1), gb, maxabs, decide, stamp);
     tmark("pack_i8", s, false);
     return hipGetLastError();
 }
@@ -994,7 +999,7 @@ hipError_t launch_gemm_f32mm(const void *pa, const void *pb, float *c, const Gem
 }
 
 hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,
-                          hipStream_t s, const uint32_t *decide, const SplitK &sk)
+                          hipStream_t s, const uint64_t *decide, uint32_t stamp, const SplitK &sk)
 {
     if (sh.m <= 0 || sh.n <= 0) return hipSuccess;
     GemmArgs g{};
@@ -1008,6 +1013,7 @@ hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const Gemm
     g.nrb_a = cdiv(sh.m, 32);
     g.nrb_b = cdiv(sh.n, 32);
     g.decide = decide;
+    g.gen = stamp;
     g.expect = limbs;
     const int t = tile ? tile : default_tile(sh.m, sh.n);
     if (sk.parts > 1 && limbs == 1) {

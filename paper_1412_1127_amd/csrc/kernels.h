@@ -65,22 +65,24 @@ size_t packed_bytes(int64_t rows, int64_t k_elems, int elem_bytes, int planes);
 // (element (e, r) at x[e*ld + r]; packs the columns, i.e. B^T).
 hipError_t launch_pack_bf16x3(const float *x, int64_t rows, int64_t k, int64_t ld, bool trans, void *out,
                               hipStream_t s);
-// int32 -> `planes` balanced base-256 digit planes; maxabs (nullable) gets
-// atomicMax of |x| (must hold 0 or a smaller value beforehand).
+// int32 -> `planes` balanced base-256 digit planes.
 hipError_t launch_pack_i8(const int32_t *x, int64_t rows, int64_t k, int64_t ld, bool trans, int planes, void *out,
-                          uint32_t *maxabs, hipStream_t s);
+                          hipStream_t s);
 // Both operands of one product in one launch: A (m x k, rows) into pa and B
 // (k x n, packed as B^T) into pb, as the two calls above would; for int8,
-// maxabs (nullable) gets A's max in word 0 and B's in word 1.
+// maxabs (nullable, int8) gets A's max |x| in word 0 and B's in word 1, as
+// 64-bit words (stamp << 32 | max) that need no clearing between calls: each
+// call passes a fresh nonzero stamp, and a word with another stamp reads as
+// no maximum above 127 recorded.
 hipError_t launch_pack_bf16x3_pair(const float *a, int64_t m, int64_t lda, const float *b, int64_t n, int64_t ldb,
                                    int64_t k, void *pa, void *pb, hipStream_t s);
 // decide (optional, int8): the two max|x| words of a finished one-digit
-// pass; the launch then packs only if more than one digit is needed, and
-// writes as many digit planes as are needed into units of four planes
-// (`planes` is ignored).
+// pass with stamp `stamp`; the launch then packs only if more than one digit
+// is needed, and writes as many digit planes as are needed into units of
+// four planes (`planes` is ignored).
 hipError_t launch_pack_i8_pair(const int32_t *a, int64_t m, int64_t lda, const int32_t *b, int64_t n, int64_t ldb,
-                               int64_t k, int planes, void *pa, void *pb, uint32_t *maxabs, hipStream_t s,
-                               const uint32_t *decide = nullptr);
+                               int64_t k, int planes, void *pa, void *pb, uint64_t *maxabs, hipStream_t s,
+                               const uint64_t *decide = nullptr, uint32_t stamp = 0);
 // C (m x n, leading dimension ldc) = sum over the product set of A-plane x
 // B-plane, A and B packed with k elements per row.
 // products: 6 = FULL6, 5 = FIVE (FULL6 without mid*mid), 3 = CHEAP3, -3 = the
@@ -142,7 +144,8 @@ hipError_t launch_gemm_f32mm(const void *pa, const void *pb, float *c, const Gem
 // multi-digit kernel (limbs = 4 units) only if more are needed, with as many
 // digits as are needed.
 hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,
-                          hipStream_t s, const uint32_t *decide = nullptr, const SplitK &sk = SplitK());
+                          hipStream_t s, const uint64_t *decide = nullptr, uint32_t stamp = 0,
+                          const SplitK &sk = SplitK());
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
 
 // ---- measurement kernels (onbox.hip) ---------------------------------------

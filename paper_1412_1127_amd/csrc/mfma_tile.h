@@ -236,7 +236,8 @@ struct GemmArgs {
     const ProbeRecord *probe;  // non-null: skip tiles whose record says no correction
     int probe_shm, probe_shn;  // log2 of (probed tile) / (this tile), rows and columns
     int probe_tiles_n;         // probed tiles per row of C
-    const uint32_t *decide;    // non-null: run only if limb_gate(decide, expect)
+    const uint64_t *decide;    // non-null: run only if limb_gate(decide, gen, expect)
+    uint32_t gen;              // the call's stamp in the decide words
     int expect;
     // Split K: ksplit > 1 cuts the K range into ksplit parts (kb_count units
     // each, the last shorter); the workgroup of part `split` of tile `tile`
@@ -248,22 +249,35 @@ struct GemmArgs {
     uint32_t *tickets;    // one per tile: zero before the launch, left at zero
 };
 
+// The one-digit pass leaves, per operand, a 64-bit word (stamp << 32 |
+// max |x|) in which it records maxima above 127 only; the stamp is the
+// call's own (a number the host draws per call, never 0).  A word with
+// another stamp -- left by an earlier call, or whatever the workspace held
+// -- was not written by this call and reads as 0.  The words never need
+// clearing: a reader can only see this call's stamp with a maximum the call
+// recorded (or, if stale contents happen to carry the same stamp, with a
+// larger one, which can only ask for more digits than needed).
+__device__ inline uint32_t recorded_max(uint64_t w, uint32_t stamp)
+{
+    return (uint32_t)(w >> 32) == stamp ? (uint32_t)w : 0u;
+}
+
 // Digits the int8 path needs for two operands with the given max |x| words:
 // the fewest balanced base-256 digits that hold every value exactly (four
-// hold any int32 modulo 2^32).  A word may read zero for any max |x| up to
-// 127 (the pack records only larger maxima): the answer is one digit either
-// way.
-__device__ inline int limbs_needed(const uint32_t *maxabs2)
+// hold any int32 modulo 2^32).  A max |x| up to 127 may read as zero (only
+// larger maxima are recorded): the answer is one digit either way.
+__device__ inline int limbs_needed(const uint64_t *maxabs2, uint32_t stamp)
 {
-    const uint32_t m = maxabs2[0] > maxabs2[1] ? maxabs2[0] : maxabs2[1];
+    const uint32_t a = recorded_max(maxabs2[0], stamp), b = recorded_max(maxabs2[1], stamp);
+    const uint32_t m = a > b ? a : b;
     return m <= 127u ? 1 : m <= 32639u ? 2 : m <= 8355711u ? 3 : 4;
 }
 
 // The one-digit kernels (expect = 1) run when one digit is enough; the
-// four-digit kernels (expect = 4) serve every other case.
-__device__ inline bool limb_gate(const uint32_t *maxabs2, int expect)
+// multi-digit kernels (expect = 4) serve every other case.
+__device__ inline bool limb_gate(const uint64_t *maxabs2, uint32_t stamp, int expect)
 {
-    return (limbs_needed(maxabs2) == 1) == (expect == 1);
+    return (limbs_needed(maxabs2, stamp) == 1) == (expect == 1);
 }
 
 // Map the linear workgroup id to an output tile.  Workgroups are dealt to

@@ -24,6 +24,7 @@
 #include <mutex>
 #include <new>
 #include <set>
+#include <atomic>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -579,11 +580,22 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
     return check_launch(e, "gemm (bf16x3) launch");
 }
 
+// Stamp of one int32 call's max|x| words: a process-wide counter, never 0.
+uint32_t next_stamp()
+{
+    static std::atomic<uint32_t> counter{0};
+    uint32_t v;
+    do {
+        v = counter.fetch_add(1, std::memory_order_relaxed) + 1;
+    } while (v == 0);
+    return v;
+}
+
 acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const GemmShape &sh, uint32_t flags,
                          char *work, size_t work_bytes, hipStream_t s)
 {
     const accx::SplitK sk = split_for(ACC_INT32, sh, flags, work, work_bytes);
-    uint32_t *maxabs = reinterpret_cast<uint32_t *>(work);
+    uint64_t *maxabs = reinterpret_cast<uint64_t *>(work);
     char *pa = work + kMaxabsBytes;
     const int nl = flag_limbs(flags);
     hipError_t e;
@@ -594,24 +606,26 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const G
         // they call for: two, three or four), the one-digit GEMM only if
         // they do not (each kernel reads the decision and exits at once
         // otherwise; the multi-digit kernels on small persistent grids, so
-        // that their exit costs little).
+        // that their exit costs little).  The max|x| words carry this call's
+        // stamp and need no clearing launch (recorded_max).
         const size_t pa1 = accx::packed_bytes(sh.m, sh.k, 1, 1), pa4 = accx::packed_bytes(sh.m, sh.k, 1, 4);
         char *p4 = pa + packed_pair(sh, 1, 1);
-        e = accx::launch_zero_u32(maxabs, 2, s);
+        const uint32_t stamp = next_stamp();
+        e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 1, pa, pa + pa1, maxabs, s, nullptr,
+                                      stamp);
         if (e == hipSuccess)
-            e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 1, pa, pa + pa1, maxabs, s);
-        if (e == hipSuccess)
-            e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 4, p4, p4 + pa4, nullptr, s, maxabs);
+            e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 4, p4, p4 + pa4, nullptr, s, maxabs,
+                                          stamp);
         if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
-        e = accx::launch_gemm_i8(pa, pa + pa1, c, sh, 1, resolve_tile(ACC_INT32, sh, flags, 1), s, maxabs, sk);
-        if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pa4, c, sh, 4, 0, s, maxabs);
+        e = accx::launch_gemm_i8(pa, pa + pa1, c, sh, 1, resolve_tile(ACC_INT32, sh, flags, 1), s, maxabs, stamp, sk);
+        if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pa4, c, sh, 4, 0, s, maxabs, stamp);
         return check_launch(e, "gemm (int8) launch");
     }
     const size_t pan = accx::packed_bytes(sh.m, sh.k, 1, nl);
     e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, nl, pa, pa + pan, nullptr, s);
     if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
     return check_launch(
-        accx::launch_gemm_i8(pa, pa + pan, c, sh, nl, resolve_tile(ACC_INT32, sh, flags, nl), s, nullptr, sk),
+        accx::launch_gemm_i8(pa, pa + pan, c, sh, nl, resolve_tile(ACC_INT32, sh, flags, nl), s, nullptr, 0, sk),
         "gemm (int8) launch");
 }
 
@@ -1595,7 +1609,7 @@ acc_status accx_pack_dev(acc_dtype t, const void *dX, int64_t rows, int64_t k, i
             ? accx::launch_pack_bf16x3(static_cast<const float *>(dX), rows, k, transposed ? rows : k,
                                        transposed != 0, dOut, stream)
             : accx::launch_pack_i8(static_cast<const int32_t *>(dX), rows, k, transposed ? rows : k, transposed != 0,
-                                   planes, dOut, nullptr, stream);
+                                   planes, dOut, stream);
     return check_launch(e, "pack launch");
 }
 
@@ -1650,10 +1664,10 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
             he = accx::launch_pack_bf16x3(static_cast<float *>(x), sh.n, sh.k, sh.n, true,
                                           static_cast<char *>(pk2) + pka, stream);
     } else {
-        he = accx::launch_pack_i8(static_cast<int32_t *>(x), sh.m, sh.k, sh.k, false, limbs, pk2, nullptr, stream);
+        he = accx::launch_pack_i8(static_cast<int32_t *>(x), sh.m, sh.k, sh.k, false, limbs, pk2, stream);
         if (he == hipSuccess)
             he = accx::launch_pack_i8(static_cast<int32_t *>(x), sh.n, sh.k, sh.n, true, limbs,
-                                      static_cast<char *>(pk2) + pka, nullptr, stream);
+                                      static_cast<char *>(pk2) + pka, stream);
     }
     if (he != hipSuccess) goto hip_out;
     {
@@ -1674,7 +1688,7 @@ acc_status autotune_impl(int t, const GemmShape &sh, uint32_t flags, unsigned ma
                        ? accx::launch_gemm_bf16x3(pk2, static_cast<char *>(pk2) + pka, static_cast<float *>(c), csh,
                                                   tune_variant(t, flags, 0), false, tile, stream, nullptr, sk)
                        : accx::launch_gemm_i8(pk2, static_cast<char *>(pk2) + pka, static_cast<int32_t *>(c), csh,
-                                              limbs, tile, stream, nullptr, sk);
+                                              limbs, tile, stream, nullptr, 0, sk);
         };
         const double work = std::max(1.0, 2.0 * (double)sh.m * (double)sh.n * (double)sh.k);
         const int reps = (int)std::max<double>(2.0, std::min<double>(50.0, 2e11 / work));

@@ -148,6 +148,28 @@ def test_i32_multi_digit_many_tiles(ax, bound):
         assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED | ax.ACC_LIMBS(limbs)), ref)
 
 
+def test_i32_digit_decision_with_reused_and_garbage_workspace(ax):
+    # the max|x| words in the workspace are never cleared: a call must not
+    # read an earlier call's maxima, nor whatever a workspace held, as its own
+    import torch
+    n = 300
+    small = [synth.int_uniform_i32((n, n), -100, 100, SEED, 61 + k) for k in range(2)]
+    big = [synth.full_range_i32((n, n), SEED, 63 + k) for k in range(2)]
+    mid = [synth.int_uniform_i32((n, n), -30000, 30000, SEED, 65 + k) for k in range(2)]
+    nbytes = ax.accx_matmul_workspace_size(ax.ACC_INT32, n, ax.ACC_KERNEL_TILED)
+    w = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device="cuda")
+    g = synth.rng(SEED, 67)
+    for k, (a, b) in enumerate([small, big, small, mid, small, big]):
+        if k == 4:
+            w.copy_(torch.from_numpy(g.integers(0, 256, nbytes).astype(np.uint8)).cuda())
+        da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        dc = torch.full((n, n), -7, dtype=torch.int32, device="cuda")
+        print("int32 auto with a reused workspace, call %d" % k, flush=True)
+        ax.accx_matmul_dev(ax.ACC_INT32, da, db, dc, n, ax.ACC_KERNEL_TILED, w, nbytes)
+        torch.cuda.synchronize()
+        assert np.array_equal(dc.cpu().numpy(), oracle.matmul_i32(a, b)), k
+
+
 def test_i32_wraparound(ax):
     n = 48
     a = np.full((n, n), 2 ** 31 - 1, np.int32)
