@@ -511,11 +511,11 @@ __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ 
 }
 
 
+// One workgroup's tile (or split-K part of a tile) of gemm_packed.
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
           int LAM, bool F32MM>
-__global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
+__device__ __attribute__((always_inline)) inline void gemm_packed_body(const GemmArgs &g, char *lds)
 {
-    __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPROD, PL>()];
     int tm, tn;
     const int T = g.tiles_m * g.tiles_n;
     const int t = (int)(blockIdx.x % (unsigned)T);  // split K: part blockIdx.x / T of tile t
@@ -539,6 +539,14 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
     }
 }
 
+template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
+          int LAM, bool F32MM>
+__global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPROD, PL>()];
+    gemm_packed_body<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM>(g, lds);
+}
+
 // int32 with several int8 digits per operand (packed units of P planes), on
 // 128 x 128 tiles of 8 wavefronts (64 x 32 each, one int32 accumulator set
 // per shift group), two LDS stages.  A persistent grid takes the tiles
@@ -547,15 +555,18 @@ __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 // one-digit pass; the kernel exits when one digit is enough) or from the
 // caller (g.expect).  Digit pairs (k, m) below the count with k + m <= 3:
 // 4 products for two digits, 8 for three, 10 for four.
-template <int P>
-__global__ __launch_bounds__(512) void gemm_i8_multi(GemmArgs g)
+constexpr int I8M_BM = 128, I8M_BN = 128, I8M_KBK = 64, I8M_WGM = 2, I8M_WGN = 4, I8M_NS = 2;
+template <int P> constexpr int i8_multi_lds_bytes()
 {
-    constexpr int BM = 128, BN = 128, KBK = 64, WGM = 2, WGN = 4, NS = 2;
-    constexpr uint64_t PLMAX = P >= 4 ? PL_L4 : P == 3 ? PL_L3 : PL_L2;
-    constexpr int NPMAX = P >= 4 ? 10 : P == 3 ? 8 : 4;
-    __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPMAX, PLMAX>()];
-    const int nd = g.decide ? limbs_needed(g.decide, g.gen) : g.expect;
-    if (nd < 2) return;  // uniform: the whole grid exits
+    return gemm_lds_bytes<I8M_BM, I8M_BN, I8M_KBK, I8M_NS, P >= 4 ? 10 : P == 3 ? 8 : 4,
+                          P >= 4 ? PL_L4 : P == 3 ? PL_L3 : PL_L2>();
+}
+
+// The tiles of the multi-digit product with nd digits, grid-stride.
+template <int P>
+__device__ __attribute__((always_inline)) inline void gemm_i8_multi_body(const GemmArgs &g, int nd, char *lds)
+{
+    constexpr int BM = I8M_BM, BN = I8M_BN, KBK = I8M_KBK, WGM = I8M_WGM, WGN = I8M_WGN, NS = I8M_NS;
     const int T = g.tiles_m * g.tiles_n;
     for (int t = blockIdx.x; t < T; t += gridDim.x) {
         int tm, tn;
@@ -571,6 +582,35 @@ __global__ __launch_bounds__(512) void gemm_i8_multi(GemmArgs g)
         }
         __syncthreads();  // every wavefront is done with the LDS stages before the next tile's loads
     }
+}
+
+template <int P>
+__global__ __launch_bounds__(512) void gemm_i8_multi(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(1024))) char lds[i8_multi_lds_bytes<P>()];
+    const int nd = g.decide ? limbs_needed(g.decide, g.gen) : g.expect;
+    if (nd < 2) return;  // uniform: the whole grid exits
+    gemm_i8_multi_body<P>(g, nd, lds);
+}
+
+// The automatic int32 path on the one-digit 256 x 256 tile: one launch that
+// runs either that tile (g, one workgroup per tile or split-K part) or, when
+// the one-digit pass's maxima call for more digits, the multi-digit product
+// (gm: four-plane operands, 128 x 128 tiles taken grid-stride by the same
+// workgroups).  Saves the launch of the multi-digit kernel that would exit at
+// once on one-digit data.
+// grid1: the workgroups of the one-digit tile (tiles x split parts); the
+// grid may be larger, for the multi-digit product's sake.
+__global__ __launch_bounds__(512) void gemm_i8_auto256(GemmArgs g, GemmArgs gm, int grid1)
+{
+    constexpr int LDS1 = gemm_lds_bytes<256, 256, 64, 3, 1, PL_L1>();
+    constexpr int LDSM = i8_multi_lds_bytes<4>();
+    __shared__ __attribute__((aligned(1024))) char lds[LDS1 > LDSM ? LDS1 : LDSM];
+    const int nd = limbs_needed(g.decide, g.gen);
+    if (nd > 1)
+        gemm_i8_multi_body<4>(gm, nd, lds);
+    else if ((int)blockIdx.x < grid1)
+        gemm_packed_body<true, 1, 256, 256, 64, 2, 4, 3, 1, PL_L1, 1, 1, false>(g, lds);
 }
 
 // ------------------------------------------------------- float64 probe --
@@ -1032,6 +1072,54 @@ hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const Gemm
     }
     tmark("gemm_i8", s, false);
     return e;
+}
+
+hipError_t launch_gemm_i8_auto(const void *pa1, const void *pb1, const void *pa4, const void *pb4, int32_t *c,
+                               const GemmShape &sh, int tile, hipStream_t s, const uint64_t *maxabs, uint32_t stamp,
+                               const SplitK &sk)
+{
+    if (sh.m <= 0 || sh.n <= 0) return hipSuccess;
+    const int t = tile ? tile : default_tile(sh.m, sh.n);
+    if (t != GEMM_TILE_256) {  // the other one-digit tiles: two launches
+        hipError_t e = launch_gemm_i8(pa1, pb1, c, sh, 1, t, s, maxabs, stamp, sk);
+        if (e == hipSuccess) e = launch_gemm_i8(pa4, pb4, c, sh, 4, 0, s, maxabs, stamp);
+        return e;
+    }
+    GemmArgs g{};
+    g.A = static_cast<const char *>(pa1);
+    g.B = static_cast<const char *>(pb1);
+    g.C = c;
+    g.M = sh.m;
+    g.N = sh.n;
+    g.ldc = sh.ldc;
+    g.nkb = cdiv(sh.k, 64);
+    g.nrb_a = cdiv(sh.m, 32);
+    g.nrb_b = cdiv(sh.n, 32);
+    g.decide = maxabs;
+    g.gen = stamp;
+    g.expect = 1;
+    g.tiles_m = (int)cdiv(sh.m, 256);
+    g.tiles_n = (int)cdiv(sh.n, 256);
+    if (sk.parts > 1) set_split(g, sk, (256 + 4 * (int64_t)g.tiles_m * g.tiles_n + 255) / 256 * 256);
+    if (g.ksplit > 1) {
+        g.kb_count = (g.nkb + g.ksplit - 1) / g.ksplit;
+        if ((g.nkb + g.kb_count - 1) / g.kb_count != g.ksplit) return hipErrorInvalidValue;  // host policy bug
+        hipError_t e = launch_zero_u32(g.tickets, g.tiles_m * g.tiles_n, s);
+        if (e != hipSuccess) return e;
+    }
+    GemmArgs gm = g;
+    gm.A = static_cast<const char *>(pa4);
+    gm.B = static_cast<const char *>(pb4);
+    gm.expect = 4;
+    gm.ksplit = 1;
+    gm.tiles_m = (int)cdiv(sh.m, I8M_BM);
+    gm.tiles_n = (int)cdiv(sh.n, I8M_BN);
+    const int64_t grid1 = (int64_t)g.tiles_m * g.tiles_n * (g.ksplit > 1 ? g.ksplit : 1);
+    const int64_t gridm = std::min<int64_t>((int64_t)gm.tiles_m * gm.tiles_n, device_cu_count());
+    tmark("gemm_i8", s, true);
+    hipLaunchKernelGGL(gemm_i8_auto256, dim3((unsigned)std::max(grid1, gridm)), dim3(512), 0, s, g, gm, (int)grid1);
+    tmark("gemm_i8", s, false);
+    return hipGetLastError();
 }
 
 }  // namespace accx

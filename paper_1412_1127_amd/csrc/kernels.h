@@ -146,6 +146,13 @@ hipError_t launch_gemm_f32mm(const void *pa, const void *pb, float *c, const Gem
 hipError_t launch_gemm_i8(const void *pa, const void *pb, int32_t *c, const GemmShape &sh, int limbs, int tile,
                           hipStream_t s, const uint64_t *decide = nullptr, uint32_t stamp = 0,
                           const SplitK &sk = SplitK());
+// The automatic int32 GEMMs after the one-digit and multi-digit passes: the
+// one-digit product on `tile` (pa1, pb1) if one digit is enough, else the
+// multi-digit one (pa4, pb4: units of four planes); one launch when the
+// one-digit tile is 256 x 256, two otherwise.
+hipError_t launch_gemm_i8_auto(const void *pa1, const void *pb1, const void *pa4, const void *pb4, int32_t *c,
+                               const GemmShape &sh, int tile, hipStream_t s, const uint64_t *maxabs, uint32_t stamp,
+                               const SplitK &sk = SplitK());
 hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t s);
 
 // ---- measurement kernels (onbox.hip) ---------------------------------------

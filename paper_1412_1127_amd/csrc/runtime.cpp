@@ -617,8 +617,8 @@ acc_status run_tiled_i32(const int32_t *a, const int32_t *b, int32_t *c, const G
             e = accx::launch_pack_i8_pair(a, sh.m, sh.lda, b, sh.n, sh.ldb, sh.k, 4, p4, p4 + pa4, nullptr, s, maxabs,
                                           stamp);
         if (e != hipSuccess) return fail_hip(e, "pack (int8) launch");
-        e = accx::launch_gemm_i8(pa, pa + pa1, c, sh, 1, resolve_tile(ACC_INT32, sh, flags, 1), s, maxabs, stamp, sk);
-        if (e == hipSuccess) e = accx::launch_gemm_i8(p4, p4 + pa4, c, sh, 4, 0, s, maxabs, stamp);
+        e = accx::launch_gemm_i8_auto(pa, pa + pa1, p4, p4 + pa4, c, sh, resolve_tile(ACC_INT32, sh, flags, 1), s,
+                                      maxabs, stamp, sk);
         return check_launch(e, "gemm (int8) launch");
     }
     const size_t pan = accx::packed_bytes(sh.m, sh.k, 1, nl);

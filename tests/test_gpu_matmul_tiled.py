@@ -170,6 +170,22 @@ def test_i32_digit_decision_with_reused_and_garbage_workspace(ax):
         assert np.array_equal(dc.cpu().numpy(), oracle.matmul_i32(a, b)), k
 
 
+# On the 256 x 256 one-digit tile the automatic path is one launch that runs
+# the one-digit tile or, for larger data, the multi-digit product on the same
+# workgroups (more of them than one-digit tiles at these sizes, split K at
+# 1100); both branches, bit-exact.
+@pytest.mark.parametrize("n", [300, 1100])
+@pytest.mark.parametrize("kind", ["one", "two", "full"])
+def test_i32_auto_on_256_tile(ax, n, kind):
+    if kind == "full":
+        a, b = synth.full_range_i32((n, n), SEED, 71), synth.full_range_i32((n, n), SEED, 72)
+    else:
+        bound = 100 if kind == "one" else 30000
+        a = synth.int_uniform_i32((n, n), -bound, bound, SEED, 71)
+        b = synth.int_uniform_i32((n, n), -bound, bound, SEED, 72)
+    assert np.array_equal(_run(ax, a, b, ax.ACC_KERNEL_TILED | ax.ACC_TILE_256), oracle.matmul_i32(a, b))
+
+
 def test_i32_wraparound(ax):
     n = 48
     a = np.full((n, n), 2 ** 31 - 1, np.int32)
