@@ -63,6 +63,10 @@ def _args():
     p.add_argument("--streams", type=int, choices=[1, 2], default=1,
                    help="scale: 2 runs the int32 matmul and the reduction on a second stream, overlapped "
                         "with the float32 matmul")
+    p.add_argument("--region", choices=["fused", "separate"], default="fused",
+                   help="scale, one stream: 'fused' runs the float32 matmul and the reduction as one region "
+                        "(accx_matmul_reduce_dev: the sum rides in the three-product pass's launch when that "
+                        "pass runs on the 256 x 256 tile); 'separate' makes one call per operation")
     p.add_argument("--ingest-counters", metavar="DIR", default=None,
                    help="write the HBM traffic summary from rocprofv3 FETCH_SIZE/WRITE_SIZE runs in DIR and exit")
     p.add_argument("--no-onbox", action="store_true",
@@ -150,13 +154,14 @@ def ingest_counters(root: str, prec: str) -> int:
         head = "void accx::(anonymous namespace)::gemm_packed<"
         return k[len(head):k.index(">(")].split(", ") if k.startswith(head) and ">(" in k else []
 
+    # (last template argument: "true" for the pass that carries the
+    # co-scheduled reduction, recorded under its own workload key)
     g = [k for k in by if targs(k)[:4] == ["false", "3", "256", "256"] and targs(k)[8] == str(nprod)
          and by[k][0] and by[k][1]]
-    if len(g) != 1:
-        print("expected one float32 256 x 256 GEMM with %d products, found %d" % (nprod, len(g)), file=sys.stderr)
+    if not g or len({targs(k)[-1] for k in g}) != len(g):
+        print("expected one float32 256 x 256 GEMM with %d products per kind, found %d" % (nprod, len(g)),
+              file=sys.stderr)
         return 1
-    fv, wv = by[g[0]]
-    fm, wm = sum(fv) / len(fv), sum(wv) / len(wv)
     cur = _source_hash("gemm_mfma.hip", "mfma_tile.h")
     try:
         with open(TRAFFIC_FILE) as f:
@@ -164,9 +169,13 @@ def ingest_counters(root: str, prec: str) -> int:
     except (OSError, ValueError, AttributeError):
         old = {}
     out = {"gemm_bf16x3": {k: v for k, v in old.items() if v.get("source_hash") == cur}}  # drop stale entries
-    out["gemm_bf16x3"]["len4096_" + prec] = {
-        "fetch_bytes": fm * ff * 1024, "write_bytes": wm * wf * 1024, "fetch_kib_raw": fm, "write_kib_raw": wm,
-        "fetch_factor": ff, "write_factor": wf, "source_hash": cur, "kernel": g[0]}
+    for k in g:
+        fv, wv = by[k]
+        fm, wm = sum(fv) / len(fv), sum(wv) / len(wv)
+        key = "len4096_" + prec + ("_coreduce" if targs(k)[-1] == "true" else "")
+        out["gemm_bf16x3"][key] = {
+            "fetch_bytes": fm * ff * 1024, "write_bytes": wm * wf * 1024, "fetch_kib_raw": fm, "write_kib_raw": wm,
+            "fetch_factor": ff, "write_factor": wf, "source_hash": cur, "kernel": k}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
@@ -264,6 +273,9 @@ def run_scale(args) -> int:
     wf = torch.empty(ax.accx_matmul_workspace_size(ax.ACC_FLOAT32, n, f_flags), dtype=torch.uint8, device=dev)
     wi = torch.empty(ax.accx_matmul_workspace_size(ax.ACC_INT32, n, i_flags), dtype=torch.uint8, device=dev)
     wr = torch.zeros(ax.accx_reduce_workspace_size(ax.ACC_FLOAT32, nred, 0), dtype=torch.uint8, device=dev)
+    fused = args.region == "fused" and args.streams == 1
+    wfr = (torch.empty(ax.accx_matmul_reduce_workspace_size(n, f_flags, nred), dtype=torch.uint8, device=dev)
+           if fused else None)
 
     tuned = {}
     if not args.no_autotune and not args.tile:
@@ -279,6 +291,11 @@ def run_scale(args) -> int:
     fork, join = torch.cuda.Event(), torch.cuda.Event()
 
     def step():
+        if fused:
+            # one region: the float32 matmul nest and the reduction nest
+            ax.accx_matmul_reduce_dev(da, db, dc, n, f_flags, dx, nred, 0.0, dr, wfr, wfr.numel(), sh)
+            ax.accx_matmul_dev(ax.ACC_INT32, dai, dbi, dci, n, i_flags, wi, wi.numel(), sh)
+            return
         if side is not stream:
             fork.record(stream)
             side.wait_event(fork)
@@ -325,6 +342,16 @@ def run_scale(args) -> int:
         step()
     torch.cuda.synchronize()
     ktimes = ax.accx_timing_read(reset=True)
+    # with the fused region, the three-product pass and the reduction also
+    # run apart (separate calls, after the timed region), for their own
+    # rooflines
+    kalone = None
+    if fused:
+        for _ in range(nb):
+            ax.accx_matmul_dev(ax.ACC_FLOAT32, da, db, dc, n, f_flags, wf, wf.numel(), sh)
+            ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, dx, nred, 0.0, dr, 0, wr, wr.numel(), sh)
+        torch.cuda.synchronize()
+        kalone = ax.accx_timing_read(reset=True)
     ax.accx_timing_enable(False)
 
     if args.copy_calib:
@@ -345,14 +372,28 @@ def run_scale(args) -> int:
     # the int32 matmul launches a one-digit and a four-digit GEMM, one of which
     # exits at once: its cost per matmul is the sum over both
     gi_ms = ktimes["gemm_i8"][1] / nb if "gemm_i8" in ktimes else None
+    # the sum rode in the three-product pass if its partials were added by
+    # the small final launch (no reduce_fast launch)
+    co_red = "reduce_final" in ktimes and "reduce_fast" not in ktimes
     red_ms = kavg("reduce_fast")
     g_flops = nprod * 2.0 * n ** 3
     achieved = g_flops / (g_ms * 1e-3) / 1e12 if g_ms else None
-    workload = "len%d_%s" % (n, args.prec)
+    workload = "len%d_%s%s" % (n, args.prec, "_coreduce" if co_red else "")
     roofline = {"kernel": "gemm_bf16x3", "bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": (achieved / PEAK_BF16_TFLOPS) if achieved else None,
                 "traffic": _traffic("gemm_bf16x3", workload),
                 "flops_per_launch": g_flops, "avg_ms": g_ms}
+    if co_red and g_ms:
+        # the same launch also streamed the reduction's 4 * n_reduce bytes
+        roofline["co_scheduled_reduce_bytes"] = 4.0 * nred
+        roofline["co_scheduled_reduce_gbs"] = 4.0 * nred / (g_ms * 1e-3) / 1e9
+        roofline["co_scheduled_reduce_frac_hbm"] = roofline["co_scheduled_reduce_gbs"] / PEAK_HBM_GBS
+    if kalone:
+        ga, ra = kavg("gemm_bf16x3", kalone), kavg("reduce_fast", kalone)
+        roofline["apart"] = {"gemm_ms": ga, "gemm_frac": g_flops / (ga * 1e-3) / 1e12 / PEAK_BF16_TFLOPS if ga else None,
+                             "reduce_ms": ra,
+                             "reduce_frac_hbm": 4.0 * nred / (ra * 1e-3) / 1e9 / PEAK_HBM_GBS if ra else None,
+                             "saved_ms": (ga + ra - g_ms) if (ga and ra and g_ms) else None}
 
     components = {}
     f32_total = sum(v[1] for k, v in ktimes.items() if "bf16x3" in k or k == "probe_f64") / nb
@@ -368,6 +409,9 @@ def run_scale(args) -> int:
                                 if gi_ms else None}
     components["reduce"] = {"ms": red_ms, "gbs": 4.0 * nred / (red_ms * 1e-3) / 1e9 if red_ms else None,
                             "frac_hbm": (4.0 * nred / (red_ms * 1e-3) / 1e9 / PEAK_HBM_GBS) if red_ms else None}
+    if co_red:
+        components["reduce"]["co_scheduled_in"] = "gemm_bf16x3"
+        components["reduce"]["final_ms"] = kavg("reduce_final")
     components["kernels"] = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "min_ms": v[2], "max_ms": v[3]}
                              for k, v in ktimes.items()}
     components["breakdown_steps"] = nb
@@ -431,6 +475,7 @@ def run_scale(args) -> int:
                                "and int32 uniform [-16,16], plus reduction(+) over %d float32 uniform[0,1)"
                                % (n, nred),
                    "len": n, "n_reduce": nred, "precision": args.prec, "seed": seed, "streams": args.streams,
+                   "region": "fused" if fused else "separate", "reduce_co_scheduled": co_red,
                    "tiles": {k: {"tile": [t for t, v in ax.TILES.items() if v == tv][0], "tune_ms": ms}
                              for k, (tv, ms) in tuned.items()}},
         "latency_ms": {"p50": _pct(step_ms, 50), "p99": _pct(step_ms, 99),

@@ -358,6 +358,30 @@ ACCX_API acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, cons
                                     const void *init, void *dResult, uint32_t flags, void *dWork, size_t work_bytes,
                                     void *hip_stream);
 
+/* One compute region holding two independent nests: the float32 loop nest
+ * of Listing 1a (section 1.3) on dA, dB -> dC (len*len elements, as
+ * accx_matmul_dev) and a reduction(+) nest (section 2.3) over dX[0, n)
+ * into the device float *dResult = init + sum (init a HOST value).  The
+ * paper's kernels construct lets one region hold several such nests; here,
+ * when the matmul runs the three-product pass on the 256 x 256 tile
+ * (ACC_PREC_AUTO or ACC_PREC_CHEAP3 with that tile chosen or autotuned, no
+ * split K) and dX is 16-byte aligned, the sum is co-scheduled inside that
+ * pass's launch: each workgroup streams a slice of dX beside its matrix
+ * work, and one small launch adds the workgroups' partials in a fixed
+ * order.  Otherwise the two nests run one after the other.  dC is bitwise
+ * what accx_matmul_dev computes with the same flags; the sum is
+ * deterministic for given (len, n, flags) but adds in another order than
+ * accx_reduce_sum_dev.  Pointers 4-byte aligned, dX may be NULL when n = 0;
+ * dWork: at least accx_matmul_reduce_workspace_size bytes (any contents),
+ * or NULL for the library's per-stream workspace.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
+ACCX_API acc_status accx_matmul_reduce_dev(const float *dA, const float *dB, float *dC, int64_t len, uint32_t flags,
+                                           const float *dX, int64_t n, float init, float *dResult, void *dWork,
+                                           size_t work_bytes, void *hip_stream);
+/* Workspace bytes accx_matmul_reduce_dev needs for (len, flags, n).
+ * Errors: INVALID_ARG. */
+ACCX_API acc_status accx_matmul_reduce_workspace_size(int64_t len, uint32_t flags, int64_t n, size_t *bytes_out);
+
 /* accx_reduce_dev for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Same arguments, kernels and results (bitwise those of accx_reduce_dev with

@@ -168,6 +168,8 @@ _SIGS = {
                         _sz, _vp],
     "accx_reduce_dev_noalloc": [ctypes.c_int, _vp, _i64, ctypes.POINTER(acc_reduce_var), ctypes.c_int, _vp, _vp,
                                 _u32, _vp],
+    "accx_matmul_reduce_dev": [_vp, _vp, _vp, _i64, _u32, _vp, _i64, ctypes.c_float, _vp, _vp, _sz, _vp],
+    "accx_matmul_reduce_workspace_size": [_i64, _u32, _i64, ctypes.POINTER(_sz)],
     "accx_onbox_mfma": [ctypes.c_int, _i64, ctypes.POINTER(ctypes.c_double), _vp],
     "accx_onbox_read": [_vp, _i64, _vp],
     "accx_packed_size": [ctypes.c_int, _i64, _i64, ctypes.c_int, ctypes.POINTER(_sz)],
@@ -483,6 +485,21 @@ def accx_reduce_sum_dev(dtype: int, dX, n: int, init, dResult, flags: int = 0, w
     iv = _CTYPE[int(dtype)](float(init) if dtype in (ACC_FLOAT32, ACC_FLOAT64) else int(init))
     _check(_lib.accx_reduce_sum_dev(int(dtype), _addr(dX), int(n), ctypes.byref(iv), _addr(dResult), int(flags),
                                     _addr(work), int(work_bytes), _stream(stream)), "accx_reduce_sum_dev")
+
+
+def accx_matmul_reduce_workspace_size(len_: int, flags: int, n: int) -> int:
+    v = _sz(0)
+    _check(_lib.accx_matmul_reduce_workspace_size(int(len_), int(flags), int(n), ctypes.byref(v)),
+           "accx_matmul_reduce_workspace_size")
+    return int(v.value)
+
+
+def accx_matmul_reduce_dev(dA, dB, dC, len_: int, flags: int, dX, n: int, init: float, dResult, work=None,
+                           work_bytes: int = 0, stream=None) -> None:
+    """float32 matmul nest and reduction(+) nest in one region (the sum may ride in the matmul's launch)."""
+    _check(_lib.accx_matmul_reduce_dev(_addr(dA), _addr(dB), _addr(dC), int(len_), int(flags), _addr(dX), int(n),
+                                       float(init), _addr(dResult), _addr(work), int(work_bytes), _stream(stream)),
+           "accx_matmul_reduce_dev")
 
 
 def accx_packed_size(dtype: int, rows: int, k: int, planes: int) -> int:

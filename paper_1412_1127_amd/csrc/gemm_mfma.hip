@@ -513,7 +513,7 @@ __global__ __launch_bounds__(256) void pack_i8_pair(const int32_t *__restrict__ 
 
 // One workgroup's tile (or split-K part of a tile) of gemm_packed.
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          int LAM, bool F32MM>
+          int LAM, bool F32MM, bool RED = false>
 __device__ __attribute__((always_inline)) inline void gemm_packed_body(const GemmArgs &g, char *lds)
 {
     int tm, tn;
@@ -535,16 +535,17 @@ __device__ __attribute__((always_inline)) inline void gemm_packed_body(const Gem
         h.B = g.B + off;
         gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM>(h, tm, tn, lds);
     } else {
-        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM>(g, tm, tn, lds);
+        gemm_tile<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM, RED>(g, tm, tn, lds);
     }
 }
 
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          int LAM, bool F32MM>
+          int LAM, bool F32MM, bool RED = false>
 __global__ __launch_bounds__(WGM *WGN * 64) void gemm_packed(GemmArgs g)
 {
-    __shared__ __attribute__((aligned(1024))) char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPROD, PL>()];
-    gemm_packed_body<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM>(g, lds);
+    __shared__ __attribute__((aligned(1024)))
+    char lds[gemm_lds_bytes<BM, BN, KBK, NS, NPROD, PL>() + (RED ? red_lds_bytes<WGM * WGN * 64, NS>() : 0)];
+    gemm_packed_body<INT8, P, BM, BN, KBK, WGM, WGN, NS, NPROD, PL, NACC, LAM, F32MM, RED>(g, lds);
 }
 
 // int32 with several int8 digits per operand (packed units of P planes), on
@@ -924,7 +925,7 @@ int split_k_parts(int tile, int64_t m, int64_t n, int64_t nkb)
     const int64_t T = cdiv(m, bm) * cdiv(n, bn);
     const int64_t cus = device_cu_count();
     if (T <= 0 || 2 * T > cus) return 1;
-    int64_t parts = std::min<int64_t>(8, cus / T);
+    int64_t parts = std::min<int64_t>(dev::KSPLIT_MAX, cus / T);
     parts = std::min<int64_t>(parts, nkb / 8);  // at least eight 64-byte K units per part
     if (parts < 2) return 1;
     return (int)cdiv(nkb, cdiv(nkb, parts));  // every part non-empty
@@ -948,7 +949,7 @@ int probe_tiles(int tile, int64_t m, int64_t n)
 
 void set_split(GemmArgs &g, const SplitK &sk, int64_t tiles_bytes_offset)
 {
-    g.ksplit = sk.parts > 1 ? sk.parts : 1;
+    g.ksplit = sk.parts > 1 ? std::min(sk.parts, KSPLIT_MAX) : 1;  // the host plans at most KSPLIT_MAX
     if (g.ksplit > 1) {
         g.tickets = static_cast<uint32_t *>(sk.work);
         g.partials = static_cast<char *>(sk.work) + tiles_bytes_offset;
@@ -1011,6 +1012,39 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
     tmark(tname, s, false);
     return e;
 }
+
+hipError_t launch_gemm_bf16x3_red(const void *pa, const void *pb, float *c, const GemmShape &sh, const float *x,
+                                  int64_t n, uint32_t *part, hipStream_t s)
+{
+    if (sh.m <= 0 || sh.n <= 0) return hipErrorInvalidValue;  // no workgroup to carry the sum
+    if (((uintptr_t)x & 15u) != 0) return hipErrorInvalidValue;
+    GemmArgs g{};
+    g.A = static_cast<const char *>(pa);
+    g.B = static_cast<const char *>(pb);
+    g.C = c;
+    g.M = sh.m;
+    g.N = sh.n;
+    g.ldc = sh.ldc;
+    g.nkb = cdiv(sh.k * 2, 64);
+    g.nrb_a = cdiv(sh.m, 32);
+    g.nrb_b = cdiv(sh.n, 32);
+    g.tiles_m = (int)cdiv(sh.m, 256);
+    g.tiles_n = (int)cdiv(sh.n, 256);
+    g.ksplit = 1;
+    const int64_t grid = (int64_t)g.tiles_m * g.tiles_n;
+    g.red_x = x;
+    g.red_nvec = n / 4;
+    g.red_ntail = (int)(n % 4);
+    g.red_per = cdiv(g.red_nvec, grid);
+    g.red_part = part;
+    tmark("gemm_bf16x3", s, true);
+    hipLaunchKernelGGL((gemm_packed<false, 3, 256, 256, 32, 2, 4, 3, 3, PL_CHEAP3, 1, 2, false, true>), dim3((unsigned)grid),
+                       dim3(512), 0, s, g);
+    tmark("gemm_bf16x3", s, false);
+    return hipGetLastError();
+}
+
+int red_fused_parts(int64_t m, int64_t n) { return (int)(cdiv(m, 256) * cdiv(n, 256)); }
 
 hipError_t launch_gemm_f32mm(const void *pa, const void *pb, float *c, const GemmShape &sh, int tile, hipStream_t s,
                               const SplitK &sk)

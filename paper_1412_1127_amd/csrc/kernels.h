@@ -34,6 +34,9 @@ hipError_t launch_reduce_f32(const float *x, int64_t n, float init, float *resul
                              bool plain, hipStream_t s);
 hipError_t launch_reduce_i32(const int32_t *x, int64_t n, int32_t init, int32_t *result, void *work,
                              bool plain, hipStream_t s);
+// result = init + the g float partials' (bits) sum, in index order over a
+// fixed tree (the fast reduction's second launch).
+hipError_t launch_reduce_final_f32(const uint32_t *partials, int g, float init, float *result, hipStream_t s);
 
 // Reduction variables over one array (any operator, element type).
 enum { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2, RED_OR = 3, RED_MAX_VARS = 4 };
@@ -121,6 +124,13 @@ size_t split_k_bytes(int tile, int64_t m, int64_t n, int parts);
 hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const GemmShape &sh, int products,
                               bool accumulate, int tile, hipStream_t s, const ProbeRecord *probe = nullptr,
                               const SplitK &sk = SplitK(), int probe_tile = 0);
+// The three-product pass on the 256 x 256 tile (bitwise as
+// launch_gemm_bf16x3 with products 3 and that tile, unsplit) that also sums
+// the float32 array x[0, n) (16-byte aligned): one partial per workgroup in
+// part[0, red_fused_parts(m, n)), for launch_reduce_final_f32.
+hipError_t launch_gemm_bf16x3_red(const void *pa, const void *pb, float *c, const GemmShape &sh, const float *x,
+                                  int64_t n, uint32_t *part, hipStream_t s);
+int red_fused_parts(int64_t m, int64_t n);
 // Float64 probe of C per output tile of `tile`; tau: relative Frobenius
 // threshold above which a tile is marked for correction.
 hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, const GemmShape &sh, int tile, double tau,

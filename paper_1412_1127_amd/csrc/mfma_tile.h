@@ -223,6 +223,9 @@ constexpr int planes_used(uint64_t L, int nprod)
     return m + 1;
 }
 
+// Most parts a split-K launch cuts the K range into.
+constexpr int KSPLIT_MAX = 8;
+
 struct GemmArgs {
     const char *A;  // packed A, P planes
     const char *B;  // packed B^T, P planes
@@ -247,6 +250,14 @@ struct GemmArgs {
     int64_t kb_count;     // 64-byte K units this workgroup runs (<= nkb)
     void *partials;       // ksplit x tiles x BM x BN 4-byte words
     uint32_t *tickets;    // one per tile: zero before the launch, left at zero
+    // Co-scheduled reduction (the fused launch only, unsplit): besides its
+    // tile, workgroup b adds the 16-byte vectors [b * red_per, (b + 1) *
+    // red_per) of red_x (at most red_nvec) and the red_ntail (< 4) floats
+    // after them if b is 0, and leaves its sum's bits in red_part[b].
+    const float *red_x;
+    int64_t red_nvec, red_per;
+    int red_ntail;
+    uint32_t *red_part;
 };
 
 // The one-digit pass leaves, per operand, a 64-bit word (stamp << 32 |
@@ -326,6 +337,10 @@ constexpr int gemm_lds_bytes()
 {
     return NS * (BM / 32 + BN / 32) * planes_used(PL, NPROD) * 32 * KBK;
 }
+// The co-scheduled reduction's 16-byte vectors per thread per K-step, and
+// the LDS its ring adds to a tile of THREADS threads and NS stages.
+constexpr int RED_RV = 2;
+template <int THREADS, int NS> constexpr int red_lds_bytes() { return NS * THREADS * RED_RV * 16; }
 
 //
 // LAM selects the main loop: 0 plain (wait, barrier, read, compute), 1 full
@@ -341,8 +356,14 @@ constexpr int gemm_lds_bytes()
 // of global-load lead (needs NS >= 3).
 // F32MM: float32 operands (one plane of 4-byte elements) on the float32
 // matrix cores (MmaF32) instead of bf16 planes; plain loop only.
+// RED: the tile also runs the co-scheduled reduction of GemmArgs (red_*):
+// each K-step issues RV 16-byte non-temporal loads per thread of its slice
+// beside the step's operand loads and adds them after the next step's wait,
+// so the HBM-bound sum runs in the shadow of the matrix work (first-product
+// look-ahead loop, three stages); what the K loop leaves of the slice is
+// added after it.
 template <bool INT8, int P, int BM, int BN, int KBK, int WGM, int WGN, int NS, int NPROD, uint64_t PL, int NACC,
-          int LAM = 0, bool F32MM = false>
+          int LAM = 0, bool F32MM = false, bool RED = false>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &g, int tm, int tn, char *lds)
 {
     using M = typename Pick<F32MM, MmaF32, Mma<INT8>>::type;
@@ -368,6 +389,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
     static_assert(LAM != 2 || (SUB == 1 && NPROD > 1), "first-product look-ahead: one matrix step per stage");
     static_assert(NS * STAGE <= 160 * 1024, "LDS");
     static_assert(NPL <= P, "product list names a plane the operand lacks");
+    static_assert(!RED || (LAM == 2 && NS == 3 && !INT8), "co-scheduled reduction: first-product look-ahead, 3 stages");
 
     // wavefront index in a scalar register: everything derived from it
     // (copy descriptors, fragment offsets) stays out of vector registers
@@ -394,6 +416,23 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
         dst_off[c] = (isA ? 0 : MB * LUNIT) + u * LUNIT + p * (32 * KBK) + piece * 1024;
     }
 
+    // Co-scheduled reduction (RED): K-step s also carries RV 16-byte vectors
+    // per thread of this workgroup's slice of red_x -- vector rv0 + s * RTH *
+    // RV + u * RTH + thread, u < RV -- as direct-to-LDS loads issued with the
+    // step's operand loads into a ring of NS areas after the operand stages,
+    // so they arrive with the stage and are waited for by the same counts.
+    // A vector past the slice loads a valid dummy address (the packed A) and
+    // is not added.
+    constexpr int RTH = WAVES * 64, RV = RED ? RED_RV : 0, RSTAGE = RTH * RV * 16;
+    constexpr int LPWR = LPW + RV;  // loads per wave per K-step
+    static_assert(!RED || NS * (STAGE + RSTAGE) <= 160 * 1024, "LDS");
+    static_assert(!RED || LPWR * (NS - 2) < 64, "vmcnt range");
+    int64_t rv0 = 0, rv1 = 0;
+    if constexpr (RED) {
+        rv0 = (int64_t)blockIdx.x * g.red_per;
+        rv1 = rv0 + g.red_per < g.red_nvec ? rv0 + g.red_per : g.red_nvec;
+    }
+    auto red_vec = [&](int step, int u) { return rv0 + (int64_t)step * (RTH * RV) + u * RTH + (int)threadIdx.x; };
     auto issue = [&](int step) {
         const int64_t kb = step / HALVES;
         const int h = step % HALVES;
@@ -401,6 +440,15 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
 #pragma unroll
         for (int c = 0; c < LPW; ++c)
             dma16(src_base[c] + kb * ustride + h * (KBK * 32) + lane * 16, sbase + dst_off[c]);
+        if constexpr (RED) {
+            char *rbase = lds + NS * STAGE + (step % NS) * RSTAGE;
+#pragma unroll
+            for (int u = 0; u < RV; ++u) {
+                const int64_t v = red_vec(step, u);
+                const void *src = v < rv1 ? static_cast<const void *>(g.red_x + 4 * v) : static_cast<const void *>(g.A);
+                dma16(src, rbase + (u * RTH + wave * 64) * 16);
+            }
+        }
     };
 
     Acc acc[NACC][WBM][WBN];
@@ -437,10 +485,25 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
             for (int j = 0; j < WBN; ++j)
                 F.b[j] = *reinterpret_cast<const Frag *>(sB + (wn * WBN + j) * LUNIT + PB0 * 32 * KBK + off);
         };
+        typedef float f4r __attribute__((ext_vector_type(4)));
+        f4r racc[RV > 0 ? RV : 1];
+        if constexpr (RED) {
+#pragma unroll
+            for (int u = 0; u < RV; ++u) racc[u] = (f4r)0;
+        }
+        // this thread's vectors of step s, in LDS since the wait for stage s
+        // (each lane reads what its own loads wrote: no barrier involved)
+        auto red_add = [&](int step) {
+            const char *rbase = lds + NS * STAGE + (step % NS) * RSTAGE;
+#pragma unroll
+            for (int u = 0; u < RV; ++u)
+                if (red_vec(step, u) < rv1)
+                    racc[u] += *reinterpret_cast<const f4r *>(rbase + (u * RTH + (int)threadIdx.x) * 16);
+        };
         auto pla_step = [&](int step, const P0 &cur, P0 &next) {
             if (step + 1 < nsteps) {
                 if (step + NS - 2 <= nsteps - 1)
-                    __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 3)>());
+                    __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPWR * (NS - 3)>());
                 else
                     __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
                 asm volatile("" ::: "memory");
@@ -448,6 +511,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
                 asm volatile("" ::: "memory");
                 if (step + NS - 1 < nsteps) issue(step + NS - 1);
             }
+            if constexpr (RED) red_add(step);  // stage `step` arrived before the previous wait
             // the other planes of this stage (intact until the next
             // iteration's refill), B before A and in the order the products
             // need them, so that each product waits only for its own reads
@@ -501,7 +565,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
         };
         if (nsteps > 0) {
             if (NS - 2 <= nsteps - 1)
-                __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPW * (NS - 2)>());
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm<LPWR * (NS - 2)>());
             else
                 __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
             asm volatile("" ::: "memory");
@@ -515,6 +579,28 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
                 pla_step(step + 1, F1, F0);
             }
             if (step < nsteps) pla_step(step, F0, F1);
+        }
+        if constexpr (RED) {
+            // what the K loop left of the slice, the tail floats, then this
+            // workgroup's sum in a fixed order (lanes, wavefronts)
+            const f4r *rx = reinterpret_cast<const f4r *>(g.red_x);
+            for (int64_t idx = rv0 + (int64_t)nsteps * (RTH * RV) + threadIdx.x; idx < rv1; idx += RTH)
+                racc[0] += __builtin_nontemporal_load(rx + idx);
+            float rs = 0.0f;
+#pragma unroll
+            for (int u = 0; u < RV; ++u) rs += (racc[u].x + racc[u].y) + (racc[u].z + racc[u].w);
+            if (blockIdx.x == 0 && (int)threadIdx.x < g.red_ntail) rs += g.red_x[g.red_nvec * 4 + threadIdx.x];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) rs += __shfl_xor(rs, o, 64);
+            __shared__ float red_w[WAVES];
+            if (lane == 0) red_w[wave] = rs;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                float t = 0.0f;
+#pragma unroll
+                for (int w = 0; w < WAVES; ++w) t += red_w[w];
+                g.red_part[blockIdx.x] = __float_as_uint(t);
+            }
         }
     } else if constexpr (LAM == 1) {
         struct FragSet {
@@ -632,48 +718,75 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const GemmArgs &
 
     // Split K: store this part's sums (register-major: word r*64 + lane of
     // block (wave, i, j)), and let the last part to finish add all parts in
-    // part order; the other parts are done.
+    // part order; the other parts are done.  The last part reads every
+    // part's words back, its own included (the same bits it stored), QG
+    // parts of a block per round of loads (the rounds, not the bytes, set
+    // the time of this step: one memory round trip each); QG (4, 2 or 1) is
+    // as large as the registers allow without lowering the tile's occupancy.
     if (NACC == 1 && g.ksplit > 1) {
         __shared__ int last_part;
         constexpr int BLOCKS = WAVES * WBM * WBN;
-        uint32_t *mine = static_cast<uint32_t *>(g.partials) +
-                         ((int64_t)g.split * (g.tiles_m * g.tiles_n) + g.tile) * (int64_t)(BLOCKS * 1024);
+        constexpr int QG = WBM * WBN >= 8 ? 4 : WBM * WBN >= 4 ? 2 : 1;
+        const int64_t tiles = (int64_t)g.tiles_m * g.tiles_n;
+        uint32_t *mine = static_cast<uint32_t *>(g.partials) + ((int64_t)g.split * tiles + g.tile) * (BLOCKS * 1024);
 #pragma unroll
         for (int i = 0; i < WBM; ++i)
 #pragma unroll
             for (int j = 0; j < WBN; ++j) {
                 uint32_t *blk = mine + ((wave * WBM + i) * WBN + j) * 1024;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) blk[r * 64 + lane] = word_of(acc[0][i][j][r]);
+                for (int r = 0; r < 16; ++r)
+                    __hip_atomic_store(blk + r * 64 + lane, word_of(acc[0][i][j][r]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
-        __threadfence();
+        // Device-scope stores go through to the level all XCDs share, and
+        // count as done only once they are there: waiting for them (before
+        // the barrier, so for every wavefront) orders them before the
+        // ticket, with no fence.  A device-scope fence would also write back
+        // this XCD's whole L2 (every other tile's dirty lines) and, on the
+        // reading side, invalidate it: measured, those two fences cost more
+        // than the parts' matrix work on a 512 x 4096 x 4096 product.  The
+        // last part reads the partials with device-scope loads, which go to
+        // that shared level too.
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+        asm volatile("" ::: "memory");
         __syncthreads();
         if (threadIdx.x == 0) last_part = atomicAdd(g.tickets + g.tile, 1u) == (uint32_t)(g.ksplit - 1);
         __syncthreads();
         if (!last_part) return;
-        __threadfence();
 #pragma unroll
         for (int i = 0; i < WBM; ++i)
 #pragma unroll
             for (int j = 0; j < WBN; ++j) {
+                const uint32_t *blk0 = static_cast<const uint32_t *>(g.partials) +
+                                       (int64_t)g.tile * (BLOCKS * 1024) + ((wave * WBM + i) * WBN + j) * 1024 + lane;
                 // float: ((0 + part 0) + part 1) + ...; int: the same modulo 2^32
                 float fs[16];
                 uint32_t us[16];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) fs[r] = 0.0f, us[r] = 0u;
-                for (int q = 0; q < g.ksplit; ++q) {
-                    const uint32_t *blk = static_cast<const uint32_t *>(g.partials) +
-                                          ((int64_t)q * (g.tiles_m * g.tiles_n) + g.tile) * (int64_t)(BLOCKS * 1024) +
-                                          ((wave * WBM + i) * WBN + j) * 1024;
+                for (int q0 = 0; q0 < g.ksplit; q0 += QG) {
+                    uint32_t w[QG][16];
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const uint32_t w = q == g.split ? word_of(acc[0][i][j][r])
-                                                        : __hip_atomic_load(blk + r * 64 + lane, __ATOMIC_RELAXED,
-                                                                            __HIP_MEMORY_SCOPE_AGENT);
-                        if (INT8)
-                            us[r] += w;
-                        else
-                            fs[r] += __builtin_bit_cast(float, w);
+                    for (int d = 0; d < QG; ++d) {
+                        // a part past the last re-reads the last one, unused
+                        const int q = q0 + d < g.ksplit ? q0 + d : g.ksplit - 1;
+                        const uint32_t *blk = blk0 + (int64_t)q * tiles * (BLOCKS * 1024);
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            w[d][r] = __hip_atomic_load(blk + r * 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+#pragma unroll
+                    for (int d = 0; d < QG; ++d) {
+                        if (q0 + d >= g.ksplit) break;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            if (INT8)
+                                us[r] += w[d][r];
+                            else
+                                fs[r] += __builtin_bit_cast(float, w[d][r]);
+                        }
                     }
                 }
 #pragma unroll

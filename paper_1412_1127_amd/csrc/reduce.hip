@@ -549,6 +549,14 @@ hipError_t launch_reduce_f32(const float *x, int64_t n, float init, float *resul
     return launch_reduce<float>(x, n, init, result, work, plain, s);
 }
 
+hipError_t launch_reduce_final_f32(const uint32_t *partials, int g, float init, float *result, hipStream_t s)
+{
+    tmark("reduce_final", s, true);
+    hipLaunchKernelGGL(reduce_fast_final<float>, dim3(1), dim3(RT), 0, s, partials, (unsigned)g, init, result);
+    tmark("reduce_final", s, false);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_i32(const int32_t *x, int64_t n, int32_t init, int32_t *result, void *work, bool plain,
                              hipStream_t s)
 {

@@ -540,8 +540,25 @@ accx::SplitK split_for(int t, const GemmShape &sh, uint32_t flags, char *work, s
     return sk;
 }
 
+// A reduction co-scheduled with the three-product pass (see
+// accx_matmul_reduce_dev): x[0, n), one partial per workgroup in part.
+struct CoReduce {
+    const float *x;
+    int64_t n;
+    uint32_t *part;
+};
+
+// The three-product pass of a float32 product, on `tile`, carrying `red`
+// if given (the caller has checked that the fused launch applies).
+hipError_t cheap_pass(const char *pa, const char *pbt, float *c, const GemmShape &sh, int tile, const accx::SplitK &sk,
+                      const CoReduce *red, hipStream_t s)
+{
+    if (red) return accx::launch_gemm_bf16x3_red(pa, pbt, c, sh, red->x, red->n, red->part, s);
+    return accx::launch_gemm_bf16x3(pa, pbt, c, sh, 3, false, tile, s, nullptr, sk);
+}
+
 acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmShape &sh, uint32_t flags, char *work,
-                         size_t work_bytes, hipStream_t s)
+                         size_t work_bytes, hipStream_t s, const CoReduce *red = nullptr)
 {
     const accx::SplitK sk = split_for(ACC_FLOAT32, sh, flags, work, work_bytes);
     if (is_f32mm(flags)) {
@@ -566,7 +583,7 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
         int tile = resolve_tile(ACC_FLOAT32, sh, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
         if (!tile) tile = accx::default_tile(sh.m, sh.n);
         auto *rec = reinterpret_cast<accx::ProbeRecord *>(work + probe_offset(sh));
-        e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, 3, false, tile, s, nullptr, sk);
+        e = cheap_pass(pa, pbt, c, sh, tile, sk, red, s);
         if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, sh, tile, probe_tau(), rec, s);
         // the correction runs on 64 x 64 tiles, so a marked tile costs its
         // share of the work, not a whole pass of the big tile
@@ -575,8 +592,10 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
         return check_launch(e, "gemm (bf16x3, probed) launch");
     }
     const int products = (prec == ACC_PREC_CHEAP3) ? 3 : (prec == ACC_PREC_FIVE) ? 5 : 6;
-    e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, products, false, resolve_tile(ACC_FLOAT32, sh, flags, 0), s, nullptr,
-                                 sk);
+    if (red) e = cheap_pass(pa, pbt, c, sh, 0, sk, red, s);
+    else
+        e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, products, false, resolve_tile(ACC_FLOAT32, sh, flags, 0), s,
+                                     nullptr, sk);
     return check_launch(e, "gemm (bf16x3) launch");
 }
 
@@ -1505,6 +1524,84 @@ acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, const acc_red
 {
     std::lock_guard<std::recursive_mutex> lk(S().mu);
     return dev_reduce(t, dX, n, vars, nvars, init, dResult, flags, dWork, work_bytes, hip_stream);
+}
+
+namespace {
+// A float32 matmul nest and an independent reduction(+) nest in one region:
+// whether the sum rides in the three-product pass's launch (the pass runs
+// unsplit on the 256 x 256 tile and x is 16-byte aligned), and where the
+// workspace holds the matmul's part and the reduction's partials.
+struct MatRedPlan {
+    bool fused = false;
+    size_t mm = 0, red_off = 0, total = 0;
+    int parts = 0;
+};
+
+MatRedPlan matred_plan(const GemmShape &sh, uint32_t flags, int64_t n, const void *dX)
+{
+    MatRedPlan p;
+    p.mm = matmul_ws_bytes(ACC_FLOAT32, sh, flags);
+    p.red_off = align256(p.mm);
+    p.parts = accx::red_fused_parts(sh.m, sh.n);
+    p.total = p.red_off + std::max(sizeof(uint32_t) * (size_t)p.parts, accx::reduce_fast_workspace_bytes(n));
+    const uint32_t prec = flags & ACC_PREC_MASK;
+    if (is_plain(flags) || (prec != ACC_PREC_AUTO && prec != ACC_PREC_CHEAP3)) return p;
+    if (!dX || ((uintptr_t)dX & 15u)) return p;
+    int tile = resolve_tile(ACC_FLOAT32, sh, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
+    if (!tile) tile = accx::default_tile(sh.m, sh.n);
+    if (tile != accx::GEMM_TILE_256 || split_plan(ACC_FLOAT32, sh, flags).parts > 1) return p;
+    p.fused = true;
+    return p;
+}
+}  // namespace
+
+acc_status accx_matmul_reduce_workspace_size(int64_t len, uint32_t flags, int64_t n, size_t *bytes_out)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    if (!bytes_out) return fail(ACC_ERR_INVALID_ARG, "bytes_out is NULL");
+    acc_status s = validate_matmul(ACC_FLOAT32, len, flags);
+    if (s != ACC_OK) return s;
+    if (n < 0) return fail(ACC_ERR_INVALID_ARG, "n must be >= 0");
+    *bytes_out = matred_plan(accx::square_shape(len), flags, n, nullptr).total;
+    return ACC_OK;
+}
+
+acc_status accx_matmul_reduce_dev(const float *dA, const float *dB, float *dC, int64_t len, uint32_t flags,
+                                  const float *dX, int64_t n, float init, float *dResult, void *dWork,
+                                  size_t work_bytes, void *hip_stream)
+{
+    std::lock_guard<std::recursive_mutex> lk(S().mu);
+    State &st = S();
+    acc_status s = check_ready();
+    if (s != ACC_OK) return s;
+    if ((s = validate_matmul(ACC_FLOAT32, len, flags)) != ACC_OK) return s;
+    if (flags & ACC_ASYNC) return fail(ACC_ERR_INVALID_ARG, "ACC_ASYNC applies to region calls only");
+    if (n < 0) return fail(ACC_ERR_INVALID_ARG, "n must be >= 0");
+    if (!dA || !dB || !dC || !dResult || (n > 0 && !dX)) return fail(ACC_ERR_INVALID_ARG, "NULL device pointer");
+    if (((uintptr_t)dA | (uintptr_t)dB | (uintptr_t)dC | (uintptr_t)dX | (uintptr_t)dResult) & 3u)
+        return fail(ACC_ERR_INVALID_ARG, "device pointers must be 4-byte aligned");
+    if ((s = launch_fault()) != ACC_OK) return s;
+    const GemmShape sh = accx::square_shape(len);
+    const MatRedPlan p = matred_plan(sh, flags, n, n > 0 ? dX : nullptr);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (dWork) {
+        if (work_bytes < p.total) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
+    } else {
+        Workspace &w = st.mm_ws[stream];
+        if ((s = ws_reserve(w, p.total, false, stream)) != ACC_OK) return s;
+        dWork = w.ptr;
+        work_bytes = w.bytes;
+    }
+    char *work = static_cast<char *>(dWork);
+    if (!p.fused) {
+        if ((s = run_matmul(ACC_FLOAT32, dA, dB, dC, sh, flags, work, p.mm, stream)) != ACC_OK) return s;
+        return check_launch(accx::launch_reduce_f32(dX, n, init, dResult, work + p.red_off, false, stream),
+                            "reduction launch");
+    }
+    auto *part = reinterpret_cast<uint32_t *>(work + p.red_off);
+    const CoReduce red{dX, n, part};
+    if ((s = run_tiled_f32(dA, dB, dC, sh, flags, work, p.mm, stream, &red)) != ACC_OK) return s;
+    return check_launch(accx::launch_reduce_final_f32(part, p.parts, init, dResult, stream), "reduction launch");
 }
 
 acc_status accx_onbox_mfma(int kind, int64_t rounds, double *ops_out, void *hip_stream)

@@ -287,6 +287,41 @@ def test_split_k_long_inner_dimension(ax, tile):
     assert rel_fro(c3, oracle.gemm(a, b)) <= FP32_REL_FRO_TOL
 
 
+@pytest.mark.parametrize("tile,m,n,k", [("256", 1792, 1792, 4096), ("256x128", 1536, 768, 4096),
+                                         ("128", 640, 2176, 4096)])
+def test_split_k_part_counts_off_the_load_group(ax, tile, m, n, k):
+    # On a 256-CU GPU these shapes split K into 5, 7 and 3 parts: the last
+    # part reads the parts back in groups of 4, 4 and 2, so the last group is
+    # partly past the last part (those loads must not be added).  Checked on
+    # sampled rows against the oracle, and for the same bits on every run.
+    import torch
+
+    import paper_1412_1127_amd as pk
+    g = synth.rng(SEED, 87)
+    rows = np.unique(np.concatenate([[0, m - 1], g.integers(0, m, 24)]))
+    for dt in ("f32", "i32"):
+        a, b = _inputs(m, n, k, "f32" if dt == "f32" else "i32small", 88)
+        dtype = ax.ACC_FLOAT32 if dt == "f32" else ax.ACC_INT32
+        fl = _flags(ax, "full6" if dt == "f32" else "tiled") | pk.TILES[tile]
+        base = ax.accx_gemm_workspace_size(dtype, m, n, k, _flags(ax, "full6" if dt == "f32" else "tiled")
+                                           | pk.TILES["64"])
+        full = ax.accx_gemm_workspace_size(dtype, m, n, k, fl)
+        assert full > base                                                     # this shape splits
+        if torch.cuda.get_device_properties(0).multi_processor_count == 256:
+            bm, bn = {"256": (256, 256), "256x128": (256, 128), "128": (128, 128)}[tile]
+            tiles = -(-m // bm) * -(-n // bn)
+            parts = (full - base - (256 + 4 * tiles + 255) // 256 * 256) // (tiles * bm * bn * 4)
+            assert parts == {"256": 5, "256x128": 7, "128": 3}[tile], parts
+        print("split K %s %s m=%d n=%d k=%d" % (tile, dt, m, n, k), flush=True)
+        c1 = _gemm(ax, a, b, fl, pads=(0, 0, 0))
+        ref = oracle.gemm(np.ascontiguousarray(a[rows]), b)
+        if dt == "f32":
+            assert rel_fro(c1[rows], ref) <= FP32_REL_FRO_TOL
+        else:
+            assert np.array_equal(c1[rows], ref)
+        assert np.array_equal(_gemm(ax, a, b, fl, pads=(0, 0, 0)), c1)
+
+
 def test_split_k_with_a_small_caller_workspace_runs_unsplit(ax):
     # a workspace that holds the operands but not the split area: no split
     import torch
