@@ -189,7 +189,7 @@ __device__ inline uint32_t pack_i8_rows_one(const int32_t *__restrict__ X, int64
                 const int64_t row = rq * 4 + lr, k = kb * 64 + lk;
                 if (row < R) {
                     if (vec && k + 4 <= K) {
-                        v[u] = *reinterpret_cast<const i32x4 *>(X + row * ld + k);
+                        v[u] = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(X + row * ld + k));
                     } else {
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
@@ -255,7 +255,7 @@ __device__ inline void stage_rows(const uint32_t *__restrict__ X, int64_t R, int
         uint32_t w[4] = {0u, 0u, 0u, 0u};
         if (k < K) {
             if (vec && col + 4 <= R) {
-                const u32x4_t v = *reinterpret_cast<const u32x4_t *>(X + k * ld + col);
+                const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(X + k * ld + col));
                 w[0] = v.x, w[1] = v.y, w[2] = v.z, w[3] = v.w;
             } else {
 #pragma unroll

@@ -82,7 +82,8 @@ __device__ __attribute__((always_inline)) inline void pack_bf16x3_range(const fl
             for (int t = 0; t < 8; ++t) v[t] = (row < R && k0 + t < K) ? X[(k0 + t) * ld + row] : 0.0f;
         } else if (row < R && k0 + 8 <= K && ((ld & 3) == 0) && (((uintptr_t)X & 15u) == 0)) {
             const f32x4 *p = reinterpret_cast<const f32x4 *>(X + row * ld + k0);
-            const f32x4 a = p[0], b = p[1];
+            // read once: non-temporal, so that the stream keeps out of the caches
+            const f32x4 a = __builtin_nontemporal_load(p), b = __builtin_nontemporal_load(p + 1);
             v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
         } else {
 #pragma unroll
@@ -857,14 +858,18 @@ constexpr int PROBE_PKS = PROBE_PK + 4;  // LDS row stride (floats): rows fall i
 constexpr int PROBE_NW = 8;          // K slices per pass, summed separately and then in slice order
 
 // The k-th of PS consecutive positions in [0, extent), starting at a hashed
-// multiple of PS (salt 0: rows, 1: columns); clamped at a ragged edge.  PS
-// consecutive rows of a packed operand share each 128-byte line of a 16-byte
-// K chunk (rows are 16 bytes apart in a unit), so the probe reads whole
-// lines; rows spread over the tile would use 16 bytes of each.
-__device__ inline int probe_pick(int64_t tile, int k, int extent, int salt)
+// multiple of PS; clamped at a ragged edge.  `key` is the tile's row index
+// for rows (salt 0) and its column index for columns (salt 1), so the tiles
+// of one tile row sample the same rows of A, and those of one tile column
+// the same columns of B: each operand row is fetched once from memory and
+// re-read from cache by the other tiles.  PS consecutive rows of a packed
+// operand share each 128-byte line of a 16-byte K chunk (rows are 16 bytes
+// apart in a unit), so the probe reads whole lines; rows spread over the
+// tile would use 16 bytes of each.
+__device__ inline int probe_pick(int64_t key, int k, int extent, int salt)
 {
     const int blocks = (extent + PS - 1) / PS;
-    const int b = (int)(hash32((uint32_t)(tile * 2 + salt) * 2654435761u + 977u) % (uint32_t)blocks);
+    const int b = (int)(hash32((uint32_t)(key * 2 + salt) * 2654435761u + 977u) % (uint32_t)blocks);
     const int v = b * PS + k;
     return v < extent ? v : extent - 1;
 }
@@ -929,7 +934,7 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
     for (int j = 0; j < PER; ++j) {
         const int id = threadIdx.x + j * THREADS;
         const int r = id % PS, ab = id / (PS * CH);
-        const int64_t rr = ab == 0 ? row0 + probe_pick(tile, r, rext, 0) : col0 + probe_pick(tile, r, cext, 1);
+        const int64_t rr = ab == 0 ? row0 + probe_pick(tm, r, rext, 0) : col0 + probe_pick(tn, r, cext, 1);
         src[j] = (ab == 0 ? pa : pb) + (rr >> 5) * nkb * (3 * PLANE_BYTES) + (rr & 31) * 16;
     }
     u32x4_t rh[PER], rm[PER], rl[PER];
@@ -1000,7 +1005,7 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
     // wavefront 0, one sample per lane: compare, then sum the squares over
     // the wavefront (a fixed butterfly: every lane ends with the same sums)
     if (threadIdx.x < 64) {
-        const int64_t row = row0 + probe_pick(tile, u, rext, 0), col = col0 + probe_pick(tile, v, cext, 1);
+        const int64_t row = row0 + probe_pick(tm, u, rext, 0), col = col0 + probe_pick(tn, v, cext, 1);
         double ref = L.part[0][q];
 #pragma unroll
         for (int w = 1; w < PROBE_NW; ++w) ref += L.part[w][q];
@@ -1015,8 +1020,8 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
         if (rec) {
             rec->ref[q] = ref;
             if (q < PS) {
-                rec->rows[q] = (int32_t)(row0 + probe_pick(tile, q, rext, 0));
-                rec->cols[q] = (int32_t)(col0 + probe_pick(tile, q, cext, 1));
+                rec->rows[q] = (int32_t)(row0 + probe_pick(tm, q, rext, 0));
+                rec->cols[q] = (int32_t)(col0 + probe_pick(tn, q, cext, 1));
             }
             if (q == 0) {
                 rec->err2 = e2;
