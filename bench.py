@@ -372,9 +372,10 @@ def run_scale(args) -> int:
     # the int32 matmul launches a one-digit and a four-digit GEMM, one of which
     # exits at once: its cost per matmul is the sum over both
     gi_ms = ktimes["gemm_i8"][1] / nb if "gemm_i8" in ktimes else None
-    # the sum rode in the three-product pass if its partials were added by
-    # the small final launch (no reduce_fast launch)
-    co_red = "reduce_final" in ktimes and "reduce_fast" not in ktimes
+    # the sum rode in the three-product pass if no reduction kernel of its
+    # own ran (its last step runs in the probe's launch, or with CHEAP3 in a
+    # one-workgroup launch of its own)
+    co_red = fused and "reduce_fast" not in ktimes
     red_ms = kavg("reduce_fast")
     g_flops = nprod * 2.0 * n ** 3
     achieved = g_flops / (g_ms * 1e-3) / 1e12 if g_ms else None
@@ -411,7 +412,7 @@ def run_scale(args) -> int:
                             "frac_hbm": (4.0 * nred / (red_ms * 1e-3) / 1e9 / PEAK_HBM_GBS) if red_ms else None}
     if co_red:
         components["reduce"]["co_scheduled_in"] = "gemm_bf16x3"
-        components["reduce"]["final_ms"] = kavg("reduce_final")
+        components["reduce"]["final_ms"] = kavg("reduce_final")  # None: added in the probe's launch
     components["kernels"] = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "min_ms": v[2], "max_ms": v[3]}
                              for k, v in ktimes.items()}
     components["breakdown_steps"] = nb

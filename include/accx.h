@@ -367,8 +367,9 @@ ACCX_API acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, cons
  * (ACC_PREC_AUTO or ACC_PREC_CHEAP3 with that tile chosen or autotuned, no
  * split K) and dX is 16-byte aligned, the sum is co-scheduled inside that
  * pass's launch: each workgroup streams a slice of dX beside its matrix
- * work, and one small launch adds the workgroups' partials in a fixed
- * order.  Otherwise the two nests run one after the other.  dC is bitwise
+ * work, and the workgroups' partials are added in a fixed order by the
+ * next launch (the float64 probe's with AUTO, a one-workgroup launch with
+ * CHEAP3).  Otherwise the two nests run one after the other.  dC is bitwise
  * what accx_matmul_dev computes with the same flags; the sum is
  * deterministic for given (len, n, flags) but adds in another order than
  * accx_reduce_sum_dev.  Pointers 4-byte aligned, dX may be NULL when n = 0;

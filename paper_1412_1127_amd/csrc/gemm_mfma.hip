@@ -621,15 +621,34 @@ __global__ __launch_bounds__(512) void gemm_i8_auto256(GemmArgs g, GemmArgs gm, 
 // with 512 threads, records written for the correction launch.
 constexpr int PROBE_THREADS = 512;
 
+// fin (optional): a co-scheduled reduction's per-workgroup partials, which
+// workgroup 0 adds (index order, fixed tree) into *fin.result = fin.init +
+// sum once its tile is probed -- the reduction's last step rides in this
+// launch instead of a launch of its own.
 __global__ __launch_bounds__(PROBE_THREADS) void probe_f64(const char *__restrict__ pa, const char *__restrict__ pb,
                                                            const float *__restrict__ C, GemmShape sh, int bm, int bn,
                                                            int tiles_n, int64_t nkb, double tau2,
-                                                           ProbeRecord *__restrict__ rec)
+                                                           ProbeRecord *__restrict__ rec, RedFinal fin)
 {
     __shared__ __attribute__((aligned(16))) ProbeLds L;
     const int64_t tile = blockIdx.x;
     probe_tile<PROBE_THREADS>(pa, pb, C, sh.m, sh.n, sh.k, sh.ldc, bm, bn, tile, (int)(tile / tiles_n),
                               (int)(tile % tiles_n), nkb, tau2, rec + tile, L);
+    if (fin.result && blockIdx.x == 0) {
+        __shared__ float w8[PROBE_THREADS / 64];
+        float t = 0.0f;
+        for (int k = threadIdx.x; k < fin.parts; k += PROBE_THREADS) t += __uint_as_float(fin.part[k]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if ((threadIdx.x & 63) == 0) w8[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int w = 0; w < PROBE_THREADS / 64; ++w) sum += w8[w];
+            *fin.result = fin.init + sum;
+        }
+    }
 }
 
 // Tile configurations (BM x BN, wavefront grid, K-step bytes, ring depth):
@@ -905,7 +924,7 @@ void tile_dims(int tile, int64_t m, int64_t n, int &bm, int &bn)
 }
 
 hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, const GemmShape &sh, int tile, double tau,
-                            ProbeRecord *rec, hipStream_t s)
+                            ProbeRecord *rec, hipStream_t s, const RedFinal &fin)
 {
     int bm, bn;
     tile_dims(tile, sh.m, sh.n, bm, bn);
@@ -913,7 +932,7 @@ hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, cons
     if (tiles_m * tiles_n == 0) return hipSuccess;
     tmark("probe_f64", s, true);
     hipLaunchKernelGGL(probe_f64, dim3((unsigned)(tiles_m * tiles_n)), dim3(PROBE_THREADS), 0, s, static_cast<const char *>(pa),
-                       static_cast<const char *>(pb), c, sh, bm, bn, tiles_n, cdiv(sh.k * 2, 64), tau * tau, rec);
+                       static_cast<const char *>(pb), c, sh, bm, bn, tiles_n, cdiv(sh.k * 2, 64), tau * tau, rec, fin);
     tmark("probe_f64", s, false);
     return hipGetLastError();
 }

@@ -131,10 +131,19 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
 hipError_t launch_gemm_bf16x3_red(const void *pa, const void *pb, float *c, const GemmShape &sh, const float *x,
                                   int64_t n, uint32_t *part, hipStream_t s);
 int red_fused_parts(int64_t m, int64_t n);
+// The last step of a co-scheduled reduction: *result = init + the `parts`
+// float partials (bits) in part[], added in a fixed order.  result NULL: none.
+struct RedFinal {
+    const uint32_t *part = nullptr;
+    int parts = 0;
+    float init = 0.0f;
+    float *result = nullptr;
+};
 // Float64 probe of C per output tile of `tile`; tau: relative Frobenius
-// threshold above which a tile is marked for correction.
+// threshold above which a tile is marked for correction.  fin: a
+// reduction's last step, run by the launch's first workgroup.
 hipError_t launch_probe_f64(const void *pa, const void *pb, const float *c, const GemmShape &sh, int tile, double tau,
-                            ProbeRecord *rec, hipStream_t s);
+                            ProbeRecord *rec, hipStream_t s, const RedFinal &fin = RedFinal());
 // Output tiles of `tile` (0 = the heuristic's choice) over an m x n result.
 int probe_tiles(int tile, int64_t m, int64_t n);
 // The configuration the size heuristic picks for an m x n result.

@@ -541,11 +541,16 @@ accx::SplitK split_for(int t, const GemmShape &sh, uint32_t flags, char *work, s
 }
 
 // A reduction co-scheduled with the three-product pass (see
-// accx_matmul_reduce_dev): x[0, n), one partial per workgroup in part.
+// accx_matmul_reduce_dev): x[0, n), one partial per workgroup of the pass in
+// part[0, parts), and *result = init + sum at the end (in the probe's launch
+// with AUTO, else in a launch of its own after the pass).
 struct CoReduce {
     const float *x;
     int64_t n;
     uint32_t *part;
+    int parts;
+    float init;
+    float *result;
 };
 
 // The three-product pass of a float32 product, on `tile`, carrying `red`
@@ -584,7 +589,9 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
         if (!tile) tile = accx::default_tile(sh.m, sh.n);
         auto *rec = reinterpret_cast<accx::ProbeRecord *>(work + probe_offset(sh));
         e = cheap_pass(pa, pbt, c, sh, tile, sk, red, s);
-        if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, sh, tile, probe_tau(), rec, s);
+        accx::RedFinal fin;
+        if (red) fin = accx::RedFinal{red->part, red->parts, red->init, red->result};
+        if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, sh, tile, probe_tau(), rec, s, fin);
         // the correction runs on 64 x 64 tiles, so a marked tile costs its
         // share of the work, not a whole pass of the big tile
         if (e == hipSuccess)
@@ -592,8 +599,10 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
         return check_launch(e, "gemm (bf16x3, probed) launch");
     }
     const int products = (prec == ACC_PREC_CHEAP3) ? 3 : (prec == ACC_PREC_FIVE) ? 5 : 6;
-    if (red) e = cheap_pass(pa, pbt, c, sh, 0, sk, red, s);
-    else
+    if (red) {
+        e = cheap_pass(pa, pbt, c, sh, 0, sk, red, s);
+        if (e == hipSuccess) e = accx::launch_reduce_final_f32(red->part, red->parts, red->init, red->result, s);
+    } else
         e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, products, false, resolve_tile(ACC_FLOAT32, sh, flags, 0), s,
                                      nullptr, sk);
     return check_launch(e, "gemm (bf16x3) launch");
@@ -1599,9 +1608,8 @@ acc_status accx_matmul_reduce_dev(const float *dA, const float *dB, float *dC, i
                             "reduction launch");
     }
     auto *part = reinterpret_cast<uint32_t *>(work + p.red_off);
-    const CoReduce red{dX, n, part};
-    if ((s = run_tiled_f32(dA, dB, dC, sh, flags, work, p.mm, stream, &red)) != ACC_OK) return s;
-    return check_launch(accx::launch_reduce_final_f32(part, p.parts, init, dResult, stream), "reduction launch");
+    const CoReduce red{dX, n, part, p.parts, init, dResult};
+    return run_tiled_f32(dA, dB, dC, sh, flags, work, p.mm, stream, &red);
 }
 
 acc_status accx_onbox_mfma(int kind, int64_t rounds, double *ops_out, void *hip_stream)
