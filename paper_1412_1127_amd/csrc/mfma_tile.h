@@ -858,14 +858,13 @@ constexpr int PROBE_PKS = PROBE_PK + 4;  // LDS row stride (floats): rows fall i
 constexpr int PROBE_NW = 8;          // K slices per pass, summed separately and then in slice order
 
 // The k-th of PS consecutive positions in [0, extent), starting at a hashed
-// multiple of PS; clamped at a ragged edge.  `key` is the tile's row index
-// for rows (salt 0) and its column index for columns (salt 1), so the tiles
-// of one tile row sample the same rows of A, and those of one tile column
-// the same columns of B: each operand row is fetched once from memory and
-// re-read from cache by the other tiles.  PS consecutive rows of a packed
-// operand share each 128-byte line of a 16-byte K chunk (rows are 16 bytes
-// apart in a unit), so the probe reads whole lines; rows spread over the
-// tile would use 16 bytes of each.
+// multiple of PS (salt 0: rows, 1: columns), drawn per tile; clamped at a
+// ragged edge.  (Drawn per tile, not per tile row or column: with shared
+// picks every tile of a row would rest on the same sampled rows, so that one
+// unrepresentative sample would pass or mark the whole row together.)  PS
+// consecutive rows of a packed operand share each 128-byte line of a 16-byte
+// K chunk (rows are 16 bytes apart in a unit), so the probe reads whole
+// lines; rows spread over the tile would use 16 bytes of each.
 __device__ inline int probe_pick(int64_t key, int k, int extent, int salt)
 {
     const int blocks = (extent + PS - 1) / PS;
@@ -934,7 +933,7 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
     for (int j = 0; j < PER; ++j) {
         const int id = threadIdx.x + j * THREADS;
         const int r = id % PS, ab = id / (PS * CH);
-        const int64_t rr = ab == 0 ? row0 + probe_pick(tm, r, rext, 0) : col0 + probe_pick(tn, r, cext, 1);
+        const int64_t rr = ab == 0 ? row0 + probe_pick(tile, r, rext, 0) : col0 + probe_pick(tile, r, cext, 1);
         src[j] = (ab == 0 ? pa : pb) + (rr >> 5) * nkb * (3 * PLANE_BYTES) + (rr & 31) * 16;
     }
     u32x4_t rh[PER], rm[PER], rl[PER];
@@ -1005,7 +1004,7 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
     // wavefront 0, one sample per lane: compare, then sum the squares over
     // the wavefront (a fixed butterfly: every lane ends with the same sums)
     if (threadIdx.x < 64) {
-        const int64_t row = row0 + probe_pick(tm, u, rext, 0), col = col0 + probe_pick(tn, v, cext, 1);
+        const int64_t row = row0 + probe_pick(tile, u, rext, 0), col = col0 + probe_pick(tile, v, cext, 1);
         double ref = L.part[0][q];
 #pragma unroll
         for (int w = 1; w < PROBE_NW; ++w) ref += L.part[w][q];
@@ -1020,8 +1019,8 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
         if (rec) {
             rec->ref[q] = ref;
             if (q < PS) {
-                rec->rows[q] = (int32_t)(row0 + probe_pick(tm, q, rext, 0));
-                rec->cols[q] = (int32_t)(col0 + probe_pick(tn, q, cext, 1));
+                rec->rows[q] = (int32_t)(row0 + probe_pick(tile, q, rext, 0));
+                rec->cols[q] = (int32_t)(col0 + probe_pick(tile, q, cext, 1));
             }
             if (q == 0) {
                 rec->err2 = e2;

@@ -593,7 +593,9 @@ acc_status run_tiled_f32(const float *a, const float *b, float *c, const GemmSha
         if (red) fin = accx::RedFinal{red->part, red->parts, red->init, red->result};
         if (e == hipSuccess) e = accx::launch_probe_f64(pa, pbt, c, sh, tile, probe_tau(), rec, s, fin);
         // the correction runs on 64 x 64 tiles, so a marked tile costs its
-        // share of the work, not a whole pass of the big tile
+        // share of the work, not a whole pass of the big tile (128 x 128
+        // correction tiles measured slower on the row-scaled LEN=8192
+        // inputs: 0.89 against 0.77 ms)
         if (e == hipSuccess)
             e = accx::launch_gemm_bf16x3(pa, pbt, c, sh, -3, true, accx::GEMM_TILE_64, s, rec, accx::SplitK(), tile);
         return check_launch(e, "gemm (bf16x3, probed) launch");
