@@ -90,6 +90,17 @@ def test_sequential_when_the_pass_cannot_carry_the_sum(ax, len_, prec, offset):
     assert abs(got - ref) <= SUM_REL_TOL * abs(ref)
 
 
+def test_co_scheduled_on_a_ragged_matrix(ax):
+    # LEN=4000: still one 256 x 256 tile per CU (16 x 16 tiles, the last row
+    # and column of tiles ragged), so the sum rides in the pass; an odd n
+    # leaves a tail of three floats
+    n = (1 << 23) + 3
+    c, c0, got, ref, names = _run(ax, 4000, _flags(ax, "auto"), n)
+    assert "reduce_fast" not in names
+    assert np.array_equal(c, c0)
+    assert abs(got - ref) <= SUM_REL_TOL * abs(ref)
+
+
 def test_caller_workspace_and_repeatable(ax):
     n = (1 << 24) + 7
     fl = _flags(ax, "auto")
