@@ -365,7 +365,9 @@ ACCX_API acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, cons
  * paper's kernels construct lets one region hold several such nests; here,
  * when the matmul runs the three-product pass on the 256 x 256 tile
  * (ACC_PREC_AUTO or ACC_PREC_CHEAP3 with that tile chosen or autotuned, no
- * split K) and dX is 16-byte aligned, the sum is co-scheduled inside that
+ * split K), dX is 16-byte aligned and n is at most what the pass's K loop
+ * carries (2^28 floats at len = 4096: 2 x 16-byte loads per thread per
+ * K-step of 16 elements), the sum is co-scheduled inside that
  * pass's launch: each workgroup streams a slice of dX beside its matrix
  * work, and the workgroups' partials are added in a fixed order by the
  * next launch (the float64 probe's with AUTO, a one-workgroup launch with

@@ -1065,6 +1065,14 @@ hipError_t launch_gemm_bf16x3_red(const void *pa, const void *pb, float *c, cons
 
 int red_fused_parts(int64_t m, int64_t n) { return (int)(cdiv(m, 256) * cdiv(n, 256)); }
 
+int64_t red_fused_capacity(int64_t m, int64_t n, int64_t k)
+{
+    // K-steps of the 256 x 256 three-product pass (16 elements each) x 512
+    // threads x RED_RV vectors of 4 floats, per workgroup
+    const int64_t nsteps = cdiv(k * 2, 64) * 2;
+    return (int64_t)red_fused_parts(m, n) * nsteps * 512 * RED_RV * 4;
+}
+
 hipError_t launch_gemm_f32mm(const void *pa, const void *pb, float *c, const GemmShape &sh, int tile, hipStream_t s,
                               const SplitK &sk)
 {

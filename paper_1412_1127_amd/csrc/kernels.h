@@ -131,6 +131,9 @@ hipError_t launch_gemm_bf16x3(const void *pa, const void *pb, float *c, const Ge
 hipError_t launch_gemm_bf16x3_red(const void *pa, const void *pb, float *c, const GemmShape &sh, const float *x,
                                   int64_t n, uint32_t *part, hipStream_t s);
 int red_fused_parts(int64_t m, int64_t n);
+// Floats the pass's K loop carries (beyond them, each workgroup adds the rest
+// of its slice after the loop, with one load in flight per thread).
+int64_t red_fused_capacity(int64_t m, int64_t n, int64_t k);
 // The last step of a co-scheduled reduction: *result = init + the `parts`
 // float partials (bits) in part[], added in a fixed order.  result NULL: none.
 struct RedFinal {

@@ -1558,6 +1558,9 @@ MatRedPlan matred_plan(const GemmShape &sh, uint32_t flags, int64_t n, const voi
     const uint32_t prec = flags & ACC_PREC_MASK;
     if (is_plain(flags) || (prec != ACC_PREC_AUTO && prec != ACC_PREC_CHEAP3)) return p;
     if (!dX || ((uintptr_t)dX & 15u)) return p;
+    // a sum larger than the pass's loads can carry runs on its own at full
+    // HBM rate instead of in the pass's tail
+    if (n > accx::red_fused_capacity(sh.m, sh.n, sh.k)) return p;
     int tile = resolve_tile(ACC_FLOAT32, sh, (flags & ~ACC_PREC_MASK) | ACC_PREC_CHEAP3, 0);
     if (!tile) tile = accx::default_tile(sh.m, sh.n);
     if (tile != accx::GEMM_TILE_256 || split_plan(ACC_FLOAT32, sh, flags).parts > 1) return p;

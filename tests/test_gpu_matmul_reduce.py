@@ -101,6 +101,28 @@ def test_co_scheduled_on_a_ragged_matrix(ax):
     assert abs(got - ref) <= SUM_REL_TOL * abs(ref)
 
 
+def test_sum_beyond_the_pass_capacity_runs_apart(ax):
+    # the LEN=4096 pass carries at most 2^28 floats (two 16-byte loads per
+    # thread per K-step); one vector more and the sum runs on its own
+    import torch
+    x = torch.ones((1 << 28) + 4, device="cuda")
+    a = torch.zeros((4096, 4096), device="cuda")
+    c = torch.empty_like(a)
+    res = torch.empty(1, device="cuda")
+    for n, fused in (((1 << 28), True), ((1 << 28) + 4, False)):
+        ax.accx_timing_enable(True)
+        ax.accx_timing_read(reset=True)
+        ax.accx_matmul_reduce_dev(a, a, c, 4096, _flags(ax, "auto"), x, n, 0.0, res)
+        torch.cuda.synchronize()
+        names = set(ax.accx_timing_read(reset=True))
+        ax.accx_timing_enable(False)
+        assert ("reduce_fast" not in names) == fused, (n, names)
+        # ones: every partial sum is exact up to the float32 spacing of the
+        # total (32 at 2^28), so the result is n to that spacing
+        assert abs(res.item() - n) <= 32.0, (n, res.item())
+        assert not c.any().item()
+
+
 def test_caller_workspace_and_repeatable(ax):
     n = (1 << 24) + 7
     fl = _flags(ax, "auto")
