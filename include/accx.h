@@ -311,8 +311,9 @@ ACCX_API acc_status accx_matmul_workspace_size(acc_dtype t, int64_t len, uint32_
 
 /* The loop nest on device pointers dA, dB, dC (len*len elements each, 4-byte
  * aligned, dC not overlapping dA or dB), enqueued on `hip_stream` (NULL = the
- * null stream).  dWork: device workspace of at least the size above, or NULL
- * to use a library-owned workspace of that stream (grown on demand).
+ * null stream).  dWork: device workspace of at least the size above,
+ * 256-byte aligned (as hipMalloc and torch allocations are), or NULL to use
+ * a library-owned workspace of that stream (grown on demand).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
 ACCX_API acc_status accx_matmul_dev(acc_dtype t, const void *dA, const void *dB, void *dC, int64_t len,
                            uint32_t flags, void *dWork, size_t work_bytes, void *hip_stream);
@@ -375,8 +376,8 @@ ACCX_API acc_status accx_reduce_dev(acc_dtype t, const void *dX, int64_t n, cons
  * what accx_matmul_dev computes with the same flags; the sum is
  * deterministic for given (len, n, flags) but adds in another order than
  * accx_reduce_sum_dev.  Pointers 4-byte aligned, dX may be NULL when n = 0;
- * dWork: at least accx_matmul_reduce_workspace_size bytes (any contents),
- * or NULL for the library's per-stream workspace.
+ * dWork: at least accx_matmul_reduce_workspace_size bytes (any contents,
+ * 256-byte aligned), or NULL for the library's per-stream workspace.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE, NO_DEVICE. */
 ACCX_API acc_status accx_matmul_reduce_dev(const float *dA, const float *dB, float *dC, int64_t len, uint32_t flags,
                                            const float *dX, int64_t n, float init, float *dResult, void *dWork,

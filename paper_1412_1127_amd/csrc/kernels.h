@@ -114,7 +114,9 @@ struct SplitK {
     void *work = nullptr;
 };
 // The split the library uses for (tile, m, n) with nkb 64-byte K units per
-// row: more parts while the output tiles leave at least half the CUs idle.
+// row, when the output tiles leave at least half the CUs idle: as many parts
+// as fill the CUs' workgroup slots (two per CU for the 128 x 128 tile, one
+// for the others), at most KSPLIT_MAX.
 int split_k_parts(int tile, int64_t m, int64_t n, int64_t nkb);
 size_t split_k_bytes(int tile, int64_t m, int64_t n, int parts);
 

@@ -853,9 +853,9 @@ __device__ inline uint32_t hash32(uint32_t x)
 // ---------------------------------------------------------- float64 probe --
 
 constexpr int PS = PROBE_SIDE;       // sampled rows (and columns) per tile
-constexpr int PROBE_PK = 1024;       // K elements per pass
+constexpr int PROBE_PK = 1024;       // K elements per pass, at most
 constexpr int PROBE_PKS = PROBE_PK + 4;  // LDS row stride (floats): rows fall in different banks
-constexpr int PROBE_NW = 8;          // K slices per pass, summed separately and then in slice order
+constexpr int PROBE_NW = 8;          // wavefronts of a probing workgroup, at most (one partial sum each)
 
 // The k-th of PS consecutive positions in [0, extent), starting at a hashed
 // multiple of PS (salt 0: rows, 1: columns), drawn per tile; clamped at a
@@ -890,18 +890,24 @@ struct ProbeLds {
 // but C is not).  C must be visible to the workgroup.  Returns the decision
 // in every thread; rec (nullable) receives the record.
 //
-// K runs in passes of PROBE_PK elements: the workgroup first rebuilds the PS
-// rows of A and PS rows of B^T for the pass as exact float32 in LDS (each
-// thread loads 16-byte chunks of the three planes; eight neighbouring lanes
-// read one 128-byte line), then sample q's products over the w-th of
-// PROBE_NW slices of the pass go to one float64 accumulator (wavefront
-// w % (THREADS / 64), lane q), which carries them over the passes; the
-// PROBE_NW slice sums of a sample are added in slice order at the end.  The
-// sums therefore do not depend on THREADS.  A pass stages and sums only the
-// 8-element chunks that hold elements below k (the rest of a pass would add
-// exact zero products, which change no sum but the sign of a zero one, and
-// no decision).  The raw plane words of the next
-// pass are loaded while this pass is staged and summed (double buffering in
+// K runs in passes of PK = 2 THREADS elements: the workgroup first rebuilds
+// the PS rows of A and PS rows of B^T for the pass as exact float32 in LDS
+// (each thread loads four 16-byte chunks of the three planes; eight
+// neighbouring lanes read one 128-byte line).  Then each thread takes 4
+// consecutive K elements of the pass and half of the samples (sample rows
+// 0-3 in lanes 0-31 of a wavefront, 4-7 in lanes 32-63; every sample
+// column): it converts its 4 + 8 row segments to float64 once and adds the
+// 32 x 4 products, in K order, to 32 float64 accumulators that it carries
+// over the passes (register blocking: a product costs a quarter conversion
+// and no LDS read of its own).  At the end a butterfly over each
+// half-wavefront leaves lane l with its wavefront's sum for sample l (at
+// each of five steps a lane keeps half of its sums and adds its partner's
+// matching half), and the wavefront sums are added in wavefront order.  The
+// order of the additions is fixed for a given THREADS.  A pass stages and
+// sums only the 8-element chunks that hold elements below k (the rest of a
+// pass would add exact zero products, which change no sum but the sign of a
+// zero one, and no decision).  The raw plane words of the next pass are
+// loaded while this pass is staged and summed (double buffering in
 // registers); the barriers are raw s_barrier after an LDS-only wait, since a
 // full workgroup fence would also wait for those loads.
 template <int THREADS>
@@ -913,20 +919,22 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
                                                                  ProbeRecord *__restrict__ rec, ProbeLds &L)
 {
     constexpr int WAVES = THREADS / 64;
-    constexpr int SPW = PROBE_NW / WAVES;             // slices per wavefront
-    constexpr int CH = PROBE_PK / 8;                  // 16-byte chunks per row per pass
+    constexpr int PK = 2 * THREADS;                   // K elements per pass (at most PROBE_PK)
+    constexpr int CH = PK / 8;                        // 16-byte chunks per row per pass
     constexpr int PER = 2 * PS * CH / THREADS;        // 16-byte chunks per thread per pass
+    constexpr int HS = PS * PS / 2;                   // samples per thread (half of them)
     static_assert(PS * PS == 64 && PS == 8, "8 x 8 samples, one per lane");
-    static_assert(THREADS % 64 == 0 && PROBE_NW % WAVES == 0 && (2 * PS * CH) % THREADS == 0, "thread count");
+    static_assert(THREADS % 64 == 0 && WAVES <= PROBE_NW && PK <= PROBE_PK && PER == 4, "thread count");
     constexpr int LGKM0 = 0xF | (7 << 4) | (3 << 14);  // s_waitcnt lgkmcnt(0)
     const int64_t row0 = (int64_t)tm * bm, col0 = (int64_t)tn * bn;
     const int rext = (int)min<int64_t>(bm, m - row0), cext = (int)min<int64_t>(bn, n - col0);
     const int q = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int u = q / PS, v = q % PS;
+    const int uh = q >> 5;                            // sample rows 4 uh .. 4 uh + 3
+    const int kg = (wave * 32 + (q & 31)) * 4;        // this thread's K elements kg .. kg + 3 of a pass
     const int64_t kpad = nkb * 32;                    // elements the packed operands hold per row
-    double acc[SPW];
+    double acc[HS];                                   // acc[8 i + v]: sample (4 uh + i, v) = 32 uh + 8 i + v
 #pragma unroll
-    for (int z = 0; z < SPW; ++z) acc[z] = 0.0;
+    for (int z = 0; z < HS; ++z) acc[z] = 0.0;
     // chunk j of this thread: operand ab, sample row r, chunk ch of a pass
     const char *src[PER];
 #pragma unroll
@@ -950,8 +958,8 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
         }
     };
     load(0);
-    for (int64_t k0 = 0; k0 < k; k0 += PROBE_PK) {
-        const int kk = (int)min<int64_t>(PROBE_PK, k - k0);  // elements of this pass below k
+    for (int64_t k0 = 0; k0 < k; k0 += PK) {
+        const int kk = (int)min<int64_t>(PK, k - k0);  // elements of this pass below k
         const int nch = (kk + 7) / 8;                       // chunks staged and read
         // stage: chunk id -> (operand, chunk in pass, sample row); row fastest;
         // hi + mid + lo of a float32 x is x itself (the two additions are exact)
@@ -976,21 +984,27 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
         asm volatile("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        if (k0 + PROBE_PK < k) load(k0 + PROBE_PK);
+        if (k0 + PK < k) load(k0 + PK);
+        // this thread's 4 K elements, when their chunk was staged (staged
+        // chunks hold zeros past k)
+        if (kg < nch * 8) {
+            // the A segments in float64 once (16 values), then one B
+            // segment at a time: each accumulator adds its 4 products in
+            // K order
+            double xa[4][4];
 #pragma unroll
-        for (int z = 0; z < SPW; ++z) {
-            const int slice = wave + z * WAVES;
-            const float4 *ar = reinterpret_cast<const float4 *>(&L.xs[0][u][slice * (PROBE_PK / PROBE_NW)]);
-            const float4 *br = reinterpret_cast<const float4 *>(&L.xs[1][v][slice * (PROBE_PK / PROBE_NW)]);
-            // float4 groups of this slice below kk (whole staged chunks)
-            const int ng = min(PROBE_PK / PROBE_NW / 4, max(0, (kk - slice * (PROBE_PK / PROBE_NW) + 3) / 4));
-#pragma unroll 8
-            for (int j = 0; j < ng; ++j) {
-                const float4 a4 = ar[j], b4 = br[j];
-                acc[z] = __builtin_fma((double)a4.x, (double)b4.x, acc[z]);
-                acc[z] = __builtin_fma((double)a4.y, (double)b4.y, acc[z]);
-                acc[z] = __builtin_fma((double)a4.z, (double)b4.z, acc[z]);
-                acc[z] = __builtin_fma((double)a4.w, (double)b4.w, acc[z]);
+            for (int i = 0; i < 4; ++i) {
+                const float4 t4 = *reinterpret_cast<const float4 *>(&L.xs[0][4 * uh + i][kg]);
+                xa[i][0] = t4.x, xa[i][1] = t4.y, xa[i][2] = t4.z, xa[i][3] = t4.w;
+            }
+#pragma unroll
+            for (int j = 0; j < PS; ++j) {
+                const float4 t4 = *reinterpret_cast<const float4 *>(&L.xs[1][j][kg]);
+                const double xb[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[PS * i + j] = __builtin_fma(xa[i][e], xb[e], acc[PS * i + j]);
             }
         }
         // the next pass overwrites xs: every LDS read above has been consumed
@@ -998,16 +1012,30 @@ __device__ __attribute__((always_inline)) inline bool probe_tile(const char *__r
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
     }
+    // butterfly over the half-wavefront: at mask o a lane keeps the half of
+    // its c live sums that its lane bit o selects and adds its partner's
+    // copy of that half; lane l ends with acc[0] = the wavefront's sum for
+    // sample l
 #pragma unroll
-    for (int z = 0; z < SPW; ++z) L.part[wave + z * WAVES][q] = acc[z];
+    for (int o = 16, c = HS; o > 0; o >>= 1, c >>= 1) {
+        const bool hi = (q & o) != 0;
+#pragma unroll
+        for (int z = 0; z < c / 2; ++z) {
+            const double keep = hi ? acc[z + c / 2] : acc[z];
+            const double send = hi ? acc[z] : acc[z + c / 2];
+            acc[z] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    L.part[wave][q] = acc[0];
     __syncthreads();
     // wavefront 0, one sample per lane: compare, then sum the squares over
     // the wavefront (a fixed butterfly: every lane ends with the same sums)
     if (threadIdx.x < 64) {
+        const int u = q / PS, v = q % PS;
         const int64_t row = row0 + probe_pick(tile, u, rext, 0), col = col0 + probe_pick(tile, v, cext, 1);
         double ref = L.part[0][q];
 #pragma unroll
-        for (int w = 1; w < PROBE_NW; ++w) ref += L.part[w][q];
+        for (int w = 1; w < WAVES; ++w) ref += L.part[w][q];
         const double c = (double)C[row * ldc + col];
         double e2 = (c - ref) * (c - ref), r2 = ref * ref;
 #pragma unroll

@@ -328,6 +328,16 @@ acc_status check_launch(hipError_t e, const char *what)
     return ACC_OK;
 }
 
+// A caller's workspace holds packed operands read by 16-byte direct-to-LDS
+// loads, float64 probe records and atomic counters at offsets that are
+// multiples of 256 from its start: the start must be 256-byte aligned (as
+// hipMalloc and torch allocations are).
+acc_status check_work_align(const void *dWork)
+{
+    if ((uintptr_t)dWork & 255u) return fail(ACC_ERR_INVALID_ARG, "dWork must be 256-byte aligned");
+    return ACC_OK;
+}
+
 // ---- matmul dispatch ------------------------------------------------------
 
 using accx::GemmShape;
@@ -1437,6 +1447,7 @@ acc_status dev_gemm(int t, const GemmShape &sh, const void *dA, const void *dB, 
     const size_t need = matmul_ws_bytes(t, sh, flags);
     if (need) {
         if (dWork) {
+            if ((s = check_work_align(dWork)) != ACC_OK) return s;
             // below `need` but holding the operands: runs without split K
             if (work_bytes < matmul_ws_base(t, sh, flags)) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
         } else {
@@ -1511,6 +1522,7 @@ acc_status dev_reduce(int t, const void *dX, int64_t n, const acc_reduce_var *va
     const bool plain = (flags & ACC_REDUCE_PLAIN) != 0;
     const size_t need = vars_ws_bytes(t, n, vars, nvars, flags);
     if (dWork) {
+        if ((s = check_work_align(dWork)) != ACC_OK) return s;
         if (work_bytes < need) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
     } else {
         Workspace &w = !legacy ? st.red_vars_ws[stream] : plain ? st.red_plain_ws[stream] : st.red_ws[stream];
@@ -1599,6 +1611,7 @@ acc_status accx_matmul_reduce_dev(const float *dA, const float *dB, float *dC, i
     const MatRedPlan p = matred_plan(sh, flags, n, n > 0 ? dX : nullptr);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     if (dWork) {
+        if ((s = check_work_align(dWork)) != ACC_OK) return s;
         if (work_bytes < p.total) return fail(ACC_ERR_INVALID_ARG, "workspace too small");
     } else {
         Workspace &w = st.mm_ws[stream];

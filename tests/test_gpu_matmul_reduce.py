@@ -163,3 +163,27 @@ def test_argument_errors(ax):
     w = torch.empty(wb, dtype=torch.uint8, device="cuda")
     with pytest.raises(ax.AccxError):
         ax.accx_matmul_reduce_dev(a, a, a, 64, fl, a, 16, 0.0, r, w, wb - 1)
+
+
+def test_caller_workspace_must_be_256_byte_aligned(ax):
+    # the entry points that take a caller's workspace reject one whose start
+    # is not 256-byte aligned, before anything is launched
+    import torch
+    a = torch.zeros((256, 256), device="cuda")
+    c = torch.empty_like(a)
+    r = torch.empty(1, device="cuda")
+    fl = _flags(ax, "auto")
+    wb = ax.accx_matmul_reduce_workspace_size(256, fl, 1024)
+    w = torch.empty(wb + 256, dtype=torch.uint8, device="cuda")
+    assert w.data_ptr() % 256 == 0
+    off = w.data_ptr() + 16
+    with pytest.raises(ax.AccxError, match="256-byte"):
+        ax.accx_matmul_reduce_dev(a, a, c, 256, fl, a, 1024, 0.0, r, off, wb)
+    with pytest.raises(ax.AccxError, match="256-byte"):
+        ax.accx_matmul_dev(ax.ACC_FLOAT32, a, a, c, 256, fl, off, wb)
+    with pytest.raises(ax.AccxError, match="256-byte"):
+        ax.accx_reduce_sum_dev(ax.ACC_FLOAT32, a, 1024, 0.0, r, 0, off, wb)
+    # the aligned start of the same buffer works
+    ax.accx_matmul_reduce_dev(a, a, c, 256, fl, a, 1024, 0.0, r, w, wb)
+    torch.cuda.synchronize()
+    assert r.item() == 0.0 and not c.any().item()
