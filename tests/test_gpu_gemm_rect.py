@@ -2,7 +2,7 @@
 (C (m x n) = A (m x k) B (k x n), the nest of section 1.3 with its trip
 counts and row strides as parameters) with the CPU oracle, through the C ABI:
 every kernel, ragged shapes, padded rows, empty shapes, the region form, and
-the 512 x 4096 x 4096 row-block shape on sampled rows."""
+the whole 512 x 4096 x 4096 row block."""
 import numpy as np
 import pytest
 
@@ -244,29 +244,33 @@ def test_probe_records_on_rectangular_shape(ax):
         assert np.allclose(np.array(list(r.ref)), want, rtol=1e-12, atol=1e-12)
 
 
-def test_row_block_shape_sampled_rows(ax):
-    # one 512-row block of an 8192 x 4096 by 4096 x 4096 product: checked on
-    # sampled rows (the oracle computes those rows exactly)
+def test_row_block_whole_block(ax):
+    # one 512-row block of an 8192 x 4096 by 4096 x 4096 product (one GPU's
+    # share of the LEN=4096 product over eight), against the oracle on the
+    # whole block: float32 per 128 x 128 tile (no tile hides in a pooled
+    # norm) and over the block, int32 bit-exact
     import torch
     m, n, k = 512, 4096, 4096
-    g = synth.rng(SEED, 71)
-    rows = np.unique(np.concatenate([[0, m - 1], g.integers(0, m, 30)]))
     a, b = _inputs(m, n, k, "f32", 72)
-    ref = oracle.gemm(np.ascontiguousarray(a[rows]), b)
+    ref = oracle.gemm(a, b)
     da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
     for kernel in ("full6", "auto"):
         dc = torch.empty((m, n), dtype=torch.float32, device="cuda")
         print("row block m=%d n=%d k=%d %s" % (m, n, k, kernel), flush=True)
         ax.accx_gemm_dev(ax.ACC_FLOAT32, m, n, k, da, k, db, n, dc, n, _flags(ax, kernel))
         torch.cuda.synchronize()
-        assert rel_fro(dc.cpu().numpy()[rows], ref) <= FP32_REL_FRO_TOL
+        c = dc.cpu().numpy()
+        assert rel_fro(c, ref) <= FP32_REL_FRO_TOL
+        worst = max(rel_fro(c[i:i + 128, j:j + 128], ref[i:i + 128, j:j + 128])
+                    for i in range(0, m, 128) for j in range(0, n, 128))
+        assert worst <= FP32_REL_FRO_TOL, (kernel, worst)
     ai, bi = _inputs(m, n, k, "i32small", 74)
-    refi = oracle.gemm(np.ascontiguousarray(ai[rows]), bi)
+    refi = oracle.gemm(ai, bi)
     dai, dbi = torch.from_numpy(ai).cuda(), torch.from_numpy(bi).cuda()
     dci = torch.empty((m, n), dtype=torch.int32, device="cuda")
     ax.accx_gemm_dev(ax.ACC_INT32, m, n, k, dai, k, dbi, n, dci, n, _flags(ax, "tiled"))
     torch.cuda.synchronize()
-    assert np.array_equal(dci.cpu().numpy()[rows], refi)
+    assert np.array_equal(dci.cpu().numpy(), refi)
 
 
 @pytest.mark.parametrize("tile", [None, "256", "256w4", "128", "64"])
