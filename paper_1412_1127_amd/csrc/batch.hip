@@ -21,8 +21,9 @@
 // memset node.
 //
 // Precision: six products (FULL6), or AUTO: the three-product pass of the
-// tile, then the same workgroup probes that tile in float64 (probe_tile,
-// the standalone probe's samples and summation order) and, if the tile is
+// tile, then the same workgroup probes that tile in float64 (probe_tile:
+// the standalone probe's samples, summed in the order of this kernel's
+// 256-thread workgroups) and, if the tile is
 // marked, adds the three correction products over its 64 x 64 sub-tiles --
 // the standalone AUTO path's steps for that tile, done in place, so no other
 // workgroup and no other launch is involved.
@@ -114,13 +115,19 @@ __device__ __attribute__((always_inline)) inline void reduce_chunk(const BatchRe
     }
     s = block_sum_f(s, red4);
     if (threadIdx.x == 0) {
+        // The partial goes out as a device-scope store (through to the
+        // level the XCDs share) and counts as done before the ticket; the
+        // last chunk reads the partials with device-scope loads.  No fence:
+        // a device-scope fence writes back and invalidates this XCD's whole
+        // L2 under the matmul tiles that share it, once per chunk.
         __hip_atomic_store(r.partials + chunk, __float_as_uint(s), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm<0>());
+        asm volatile("" ::: "memory");
         *is_last = (atomicAdd(r.ticket, 1u) == (uint32_t)r.nchunks - 1);
     }
     __syncthreads();
     if (!*is_last) return;
-    __threadfence();
     float t = 0.0f;
     for (int k = threadIdx.x; k < r.nchunks; k += BT)
         t += __uint_as_float(__hip_atomic_load(r.partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -202,9 +209,12 @@ __global__ __launch_bounds__(BT, WG_PER_CU) void batch_persistent(BatchQueue q)
             matmul_unit<AUTO>(q.mats[w.item], w.sub, lds, q.tau2);
         __syncthreads();  // LDS and shared scalars are reused by the next unit
     }
-    // The last workgroup out resets the queue for the next launch.
+    // The last workgroup out resets the queue for the next launch.  Only
+    // device-scope atomics take part: each workgroup's last pull from the
+    // counter precedes its exit count in its own program order.  No fence,
+    // which would write back and invalidate this XCD's L2 under the
+    // workgroups still running.
     if (threadIdx.x == 0) {
-        __threadfence();
         if (atomicAdd(q.done, 1u) == gridDim.x - 1) {
             __hip_atomic_store(q.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(q.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
