@@ -2,8 +2,9 @@
 // section 1.3) and reduction(+) clauses (section 2.3; SRAD paragraph of
 // section 4.2) run as one graph of two kernels:
 //
-//  1. batch_pack: the bf16x3 split of every matmul operand, one grid row per
-//     operand (descriptor table of pack jobs);
+//  1. batch_pack: the bf16x3 split of every matmul operand, each operand on
+//     a number of workgroups in proportion to its size (descriptor table of
+//     pack jobs, and the job of each workgroup);
 //  2. batch_persistent: a persistent kernel (a fixed number of workgroups per
 //     CU) that pulls work units from one queue through an atomic counter:
 //     either one output tile of one matmul (the same LDS-tiled matrix-core
@@ -52,10 +53,13 @@ constexpr int LDS_MAX = cmax(cmax(gemm_lds_bytes<128, 128, 32, 3, 6, PL_FULL6>()
                              (int)sizeof(ProbeLds));
 static_assert(LDS_MAX * WG_PER_CU <= 160 * 1024, "persistent kernel LDS");
 
-__global__ __launch_bounds__(BT) void batch_pack(const BatchPackJob *__restrict__ jobs)
+// One workgroup of the pack launch: a share of one operand's chunks (the
+// operand's workgroups split its chunks grid-stride among themselves).
+__global__ __launch_bounds__(BT) void batch_pack(const BatchPackJob *__restrict__ jobs,
+                                                 const uint32_t *__restrict__ job_of)
 {
-    const BatchPackJob j = jobs[blockIdx.y];
-    const int64_t id0 = (int64_t)blockIdx.x * BT + threadIdx.x, step = (int64_t)gridDim.x * BT;
+    const BatchPackJob j = jobs[job_of[blockIdx.x]];
+    const int64_t id0 = (int64_t)(blockIdx.x - j.wg0) * BT + threadIdx.x, step = (int64_t)j.nwg * BT;
     if (j.trans)
         pack_bf16x3_range<true>(j.x, j.rows, j.k, j.ld, j.out, j.nrb, j.nkb, id0, step);
     else
@@ -228,11 +232,17 @@ int batch_tile_supported(int tile) { return tile == GEMM_TILE_128 || tile == GEM
 
 int batch_workgroups() { return device_cu_count() * WG_PER_CU; }
 
-hipError_t launch_batch_pack(const BatchPackJob *jobs, int njobs, hipStream_t s)
+int batch_pack_workgroups(int64_t nrb, int64_t nkb)
 {
-    if (njobs <= 0) return hipSuccess;
+    const int64_t chunks = nrb * nkb * 128;  // pack_bf16x3_range's work items
+    return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (chunks + 2 * BT - 1) / (2 * BT)));
+}
+
+hipError_t launch_batch_pack(const BatchPackJob *jobs, const uint32_t *job_of, int64_t nwg, hipStream_t s)
+{
+    if (nwg <= 0) return hipSuccess;
     tmark("batch_pack", s, true);
-    hipLaunchKernelGGL(batch_pack, dim3(64, (unsigned)njobs), dim3(BT), 0, s, jobs);
+    hipLaunchKernelGGL(batch_pack, dim3((unsigned)nwg), dim3(BT), 0, s, jobs, job_of);
     tmark("batch_pack", s, false);
     return hipGetLastError();
 }

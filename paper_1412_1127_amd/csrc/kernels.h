@@ -193,8 +193,12 @@ struct BatchPackJob {   // one bf16x3 operand to pack
     const float *x;
     char *out;
     int64_t rows, k, ld, nrb, nkb;
-    int32_t trans, pad;
+    int32_t trans, nwg;    // nwg: the pack launch's workgroups on this operand
+    uint32_t wg0, pad;     // the first of them
 };
+// Workgroups of the pack launch for an operand of nrb 32-row blocks and nkb
+// K units: about two 8-element chunks per thread, at least one.
+int batch_pack_workgroups(int64_t nrb, int64_t nkb);
 struct BatchMat {       // one matmul: packed operands, output, tiling
     const char *pa, *pb;
     float *c;
@@ -224,7 +228,8 @@ struct BatchQueue {
 };
 int batch_tile_supported(int tile);
 int batch_workgroups();
-hipError_t launch_batch_pack(const BatchPackJob *jobs, int njobs, hipStream_t s);
+// job_of[w]: the job of pack workgroup w (nwg workgroups in all).
+hipError_t launch_batch_pack(const BatchPackJob *jobs, const uint32_t *job_of, int64_t nwg, hipStream_t s);
 hipError_t launch_batch_persistent(const BatchQueue &q, hipStream_t s);
 
 int device_cu_count();  // compute units of the current device (cached)

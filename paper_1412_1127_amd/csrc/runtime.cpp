@@ -2028,6 +2028,8 @@ struct accx_batch_s {
     accx::BatchQueue queue{};
     accx::BatchPackJob *jobs = nullptr;  // device
     int njobs = 0;
+    uint32_t *job_of = nullptr;          // device: the job of each pack workgroup
+    int64_t pack_wgs = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     accx_batch_info_t info{};
@@ -2113,7 +2115,7 @@ void batch_release(accx_batch_s *b)
 
 hipError_t batch_enqueue(accx_batch_s *b, hipStream_t s)
 {
-    hipError_t e = accx::launch_batch_pack(b->jobs, b->njobs, s);
+    hipError_t e = accx::launch_batch_pack(b->jobs, b->job_of, b->pack_wgs, s);
     if (e == hipSuccess) e = accx::launch_batch_persistent(b->queue, s);
     return e;
 }
@@ -2203,6 +2205,12 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
     off = al(off + sizeof(accx::BatchUnit) * std::max<size_t>(1, max_units));
     const size_t o_jobs = off;
     off = al(off + sizeof(accx::BatchPackJob) * std::max<size_t>(1, 2 * mats.size()));
+    // pack workgroups: A and B^T of matmul k get batch_pack_workgroups each
+    int64_t pack_wgs = 0;
+    for (size_t k = 0; k < mats.size(); ++k)
+        pack_wgs += 2 * (int64_t)accx::batch_pack_workgroups((mats[k].len + 31) / 32, mats[k].nkb);
+    const size_t o_jobof = off;
+    off = al(off + sizeof(uint32_t) * (size_t)std::max<int64_t>(1, pack_wgs));
     const size_t o_zero = off;  // counters, tickets, partials: zero-filled
     size_t zbytes = 256;
     for (size_t k = 0; k < reds.size(); ++k) zbytes += 4 + 4 * (size_t)reds[k].nchunks;
@@ -2219,6 +2227,8 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
     b->dev_bytes = off;
     char *base = static_cast<char *>(b->dev);
     std::vector<accx::BatchPackJob> jobs;
+    std::vector<uint32_t> job_of;
+    job_of.reserve((size_t)pack_wgs);
     {
         size_t p = o_pack;
         for (size_t k = 0; k < mats.size(); ++k) {
@@ -2228,10 +2238,12 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
             mats[k].pa = pa;
             mats[k].pb = pb;
             const int64_t nrb = (it.n + 31) / 32;
-            jobs.push_back(
-                accx::BatchPackJob{static_cast<const float *>(it.a), pa, it.n, it.n, it.n, nrb, mats[k].nkb, 0, 0});
-            jobs.push_back(
-                accx::BatchPackJob{static_cast<const float *>(it.b), pb, it.n, it.n, it.n, nrb, mats[k].nkb, 1, 0});
+            const int nwg = accx::batch_pack_workgroups(nrb, mats[k].nkb);
+            for (int t = 0; t < 2; ++t) {
+                jobs.push_back(accx::BatchPackJob{static_cast<const float *>(t ? it.b : it.a), t ? pb : pa, it.n,
+                                                  it.n, it.n, nrb, mats[k].nkb, t, nwg, (uint32_t)job_of.size(), 0});
+                job_of.insert(job_of.end(), (size_t)nwg, (uint32_t)(jobs.size() - 1));
+            }
         }
         uint32_t *z = reinterpret_cast<uint32_t *>(base + o_zero);
         size_t w = 64;  // counter at word 0, done at word 1
@@ -2251,6 +2263,13 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
     b->queue.nunits = (uint32_t)units.size();
     b->jobs = reinterpret_cast<accx::BatchPackJob *>(base + o_jobs);
     b->njobs = (int)jobs.size();
+    b->job_of = reinterpret_cast<uint32_t *>(base + o_jobof);
+    b->pack_wgs = (int64_t)job_of.size();
+    if (b->pack_wgs != pack_wgs || pack_wgs >= ((int64_t)1 << 31)) {  // the layout's count, and one launch's grid
+        dev_free(b->dev, b->dev_bytes);
+        delete b;
+        return fail(ACC_ERR_INVALID_ARG, "batch too large");
+    }
 
     hipError_t e = hipSuccess;
     hipStream_t cs = nullptr;
@@ -2261,6 +2280,8 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
         e = hipMemcpy(base + o_units, units.data(), sizeof(accx::BatchUnit) * units.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !jobs.empty())
         e = hipMemcpy(base + o_jobs, jobs.data(), sizeof(accx::BatchPackJob) * jobs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !job_of.empty())
+        e = hipMemcpy(base + o_jobof, job_of.data(), sizeof(uint32_t) * job_of.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(base + o_zero, 0, zbytes);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     int64_t threshold = kBatchDefaultThreshold;
@@ -2272,7 +2293,7 @@ acc_status accx_batch_create(const accx_batch_item *items, int nitems, uint32_t 
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (e == hipSuccess) e = hipEventCreate(&e0);
         if (e == hipSuccess) e = hipEventCreate(&e1);
-        if (e == hipSuccess) e = accx::launch_batch_pack(b->jobs, b->njobs, cs);
+        if (e == hipSuccess) e = accx::launch_batch_pack(b->jobs, b->job_of, b->pack_wgs, cs);
         double best = 1e300;
         const int64_t cand[] = {0, 192, 320, 448, 576, 768, 65537};
         for (int64_t th : cand) {
