@@ -898,8 +898,9 @@ struct ProbeLds {
 // 0-3 in lanes 0-31 of a wavefront, 4-7 in lanes 32-63; every sample
 // column): it converts its 4 + 8 row segments to float64 once and adds the
 // 32 x 4 products, in K order, to 32 float64 accumulators that it carries
-// over the passes (register blocking: a product costs a quarter conversion
-// and no LDS read of its own).  At the end a butterfly over each
+// over the passes (register blocking: a product costs three eighths of a
+// conversion and 1.5 bytes of LDS reads, against two and 8 for one
+// accumulator per sample).  At the end a butterfly over each
 // half-wavefront leaves lane l with its wavefront's sum for sample l (at
 // each of five steps a lane keeps half of its sums and adds its partner's
 // matching half), and the wavefront sums are added in wavefront order.  The
