@@ -235,7 +235,7 @@ int batch_workgroups() { return device_cu_count() * WG_PER_CU; }
 int batch_pack_workgroups(int64_t nrb, int64_t nkb)
 {
     const int64_t chunks = nrb * nkb * 128;  // pack_bf16x3_range's work items
-    return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (chunks + 2 * BT - 1) / (2 * BT)));
+    return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (chunks + BT - 1) / BT));
 }
 
 hipError_t launch_batch_pack(const BatchPackJob *jobs, const uint32_t *job_of, int64_t nwg, hipStream_t s)

@@ -197,7 +197,7 @@ struct BatchPackJob {   // one bf16x3 operand to pack
     uint32_t wg0, pad;     // the first of them
 };
 // Workgroups of the pack launch for an operand of nrb 32-row blocks and nkb
-// K units: about two 8-element chunks per thread, at least one.
+// K units: about one 8-element chunk per thread (at most 4096 workgroups).
 int batch_pack_workgroups(int64_t nrb, int64_t nkb);
 struct BatchMat {       // one matmul: packed operands, output, tiling
     const char *pa, *pb;
