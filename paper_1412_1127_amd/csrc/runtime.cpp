@@ -2037,7 +2037,7 @@ struct accx_batch_s {
 
 namespace {
 
-constexpr int64_t kReduceChunk = 1 << 18;  // elements per reduction work unit
+constexpr int64_t kReduceChunk = 1 << 17;  // elements per reduction work unit
 
 std::set<accx_batch_s *> &batches()
 {

@@ -61,8 +61,10 @@ class Batch:
 def test_small_batch_parity(ax):
     g = synth.rng(SEED, 1)
     lens = [64, 100, 128, 257, 300, 511, 512, 640, 1000, 1, 33] + list(g.choice([64 * k for k in range(1, 9)], 9))
-    ns = [0, 1, 5, 1000, (1 << 16) + 3, 1 << 18, (1 << 18) + 1, 3 * (1 << 18) + 7]
-    bt = Batch(ax, lens, ns, SEED, offsets=[0, 1, 2, 3, 1, 0, 2, 3])
+    # around the reduction's work-unit size (2^17 elements): one element
+    # short, exact, one over, several units with a ragged last one
+    ns = [0, 1, 5, 1000, (1 << 16) + 3, (1 << 17) - 1, 1 << 18, (1 << 18) + 1, 3 * (1 << 18) + 7]
+    bt = Batch(ax, lens, ns, SEED, offsets=[0, 1, 2, 3, 1, 2, 0, 2, 3])
     ax.accx_batch_launch(bt.handle)
     cs, rs = bt.outputs()
     info = ax.accx_batch_info(bt.handle)
